@@ -1,0 +1,272 @@
+/*
+ * oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, single-threaded CPU oracle of the real-time chaotic video
+ * cipher of Jiang, Yuan, Li and Lu, "Real-time chaotic video encryption
+ * based on multithreaded parallel confusion and diffusion" (arXiv 2302.07411).
+ * It exists to check the GPU library bit for bit.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it; the GPU
+ * library neither links nor calls it, and the two share no source.
+ *
+ * Every function follows the paper step by step, in its order and notation:
+ *   - Sec. 3, Eq. (5): the piecewise linear chaotic map (PLCM);
+ *   - Sec. 3, PLCM byte extraction (two PLCMs, 6 mantissa bytes of every
+ *     iterate, the two byte sets XORed);
+ *   - Sec. 2, Eq. (1) and Algorithm 2: confusion (discretised Chirikov map);
+ *   - Sec. 2, Eq. (2): inverse confusion;
+ *   - Sec. 2, Eq. (3) and Algorithm 2: diffusion with the seed taken from
+ *     the next subframe;
+ *   - Sec. 2, Eq. (4): inverse diffusion;
+ *   - Sec. 2, Algorithms 1 and 2: r rounds of confusion then diffusion per
+ *     frame, PRBG state carried across frames.
+ * Where the paper is silent the oracle takes these readings (the same ones
+ * the library documents in include/chaosvid.h):
+ *   colour frames are interleaved HWC bytes; confusion moves whole pixels,
+ *   diffusion chains over the band's bytes in memory order;
+ *   band i covers rows [floor(i*H/n), floor((i+1)*H/n));
+ *   non-square frames use alpha=(a+o) mod H, beta=(o+g(alpha)) mod W with
+ *   g(alpha)=floor(s_c*sin((2*pi*alpha)/H)) evaluated in binary64;
+ *   the diffusion seed is the last byte of the next band after confusion and
+ *   before diffusion; "+" and "-" are mod 256;
+ *   the 6 bytes are bytes 0..5 (least significant first) of the binary64
+ *   bit pattern; the keystream of band i for one frame is the first r*S_i
+ *   bytes of ceil(r*S_i/6) steps, round j consuming bytes [j*S_i,(j+1)*S_i).
+ *
+ * Build: gcc -std=c11 -O2 -ffp-contract=off -fno-fast-math (SSE2 binary64,
+ * no FMA contraction), so every floating-point operation below is a single
+ * correctly rounded IEEE-754 operation.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ---------------------------------------------------------------- PLCM --- */
+
+/* Sec. 3, Eq. (5): F(x,p) = x/p on [0,p); (x-p)/(1/2-p) on [p,1/2];
+ * F(1-x,p) on (1/2,1]. */
+double oracle_plcm(double x, double p)
+{
+    if (x < p)
+        return x / p;
+    if (x <= 0.5)
+        return (x - p) / (0.5 - p);
+    return oracle_plcm(1.0 - x, p);
+}
+
+static uint64_t bits_of(double x)
+{
+    uint64_t u;
+    memcpy(&u, &x, sizeof u);
+    return u;
+}
+
+/* Sec. 3, PLCM byte generator: iterate both PLCMs once per step (x_1, x_2,
+ * ... -- the initial value itself is not emitted), take 6 bytes of each
+ * iterate's mantissa field, XOR the byte of map 1 with the byte of map 2.
+ * Writes exactly nbytes; the unused bytes of the last step are dropped.
+ * *x1 and *x2 are advanced by ceil(nbytes/6) steps. */
+void oracle_plcm_bytes(double *x1, double p1, double *x2, double p2,
+                       uint64_t nbytes, uint8_t *out)
+{
+    uint64_t made = 0;
+    while (made < nbytes) {
+        *x1 = oracle_plcm(*x1, p1);
+        *x2 = oracle_plcm(*x2, p2);
+        uint64_t u = bits_of(*x1), v = bits_of(*x2);
+        for (int k = 0; k < 6 && made < nbytes; k++)
+            out[made++] = (uint8_t)(((u >> (8 * k)) & 0xFF) ^ ((v >> (8 * k)) & 0xFF));
+    }
+}
+
+/* ------------------------------------------------------------ geometry --- */
+
+/* Algorithm 2 (startRow/endRow), generalised so that every row is covered
+ * when n does not divide H. */
+uint32_t oracle_band_lo(uint32_t H, uint32_t n, uint32_t i)
+{
+    return (uint32_t)(((uint64_t)i * H) / n);
+}
+
+static int64_t mod_nonneg(int64_t x, int64_t m)
+{
+    int64_t r = x % m;
+    return r < 0 ? r + m : r;
+}
+
+/* Eq. (1): the shift s_c*sin(2*pi*alpha/w) of row alpha, floored to an
+ * integer, in binary64 with the product and quotient taken left to right. */
+void oracle_gtable(uint32_t H, uint32_t s_c, int64_t *g)
+{
+    for (uint32_t alpha = 0; alpha < H; alpha++) {
+        double angle = ((2.0 * M_PI) * (double)alpha) / (double)H;
+        g[alpha] = (int64_t)floor((double)s_c * sin(angle));
+    }
+}
+
+/* ----------------------------------------------------------- confusion --- */
+
+/* Eq. (1) as Algorithm 2 applies it: every source pixel (a,o) is written to
+ * (alpha,beta) = ((a+o) mod H, (o+g[alpha]) mod W); the C bytes of a pixel
+ * move together. */
+void oracle_confuse(const uint8_t *in, uint8_t *out, uint32_t H, uint32_t W,
+                    uint32_t C, const int64_t *g)
+{
+    for (uint32_t a = 0; a < H; a++)
+        for (uint32_t o = 0; o < W; o++) {
+            int64_t alpha = mod_nonneg((int64_t)a + o, H);
+            int64_t beta = mod_nonneg((int64_t)o + g[alpha], W);
+            memcpy(out + ((uint64_t)alpha * W + beta) * C,
+                   in + ((uint64_t)a * W + o) * C, C);
+        }
+}
+
+/* Eq. (2): pixel (alpha,beta) goes back to o=(beta-g[alpha]) mod W and
+ * a=(alpha-o) mod H (for H=W this is a=(alpha-beta+g[alpha]) mod w). */
+void oracle_unconfuse(const uint8_t *in, uint8_t *out, uint32_t H, uint32_t W,
+                      uint32_t C, const int64_t *g)
+{
+    for (uint32_t alpha = 0; alpha < H; alpha++)
+        for (uint32_t beta = 0; beta < W; beta++) {
+            int64_t o = mod_nonneg((int64_t)beta - g[alpha], W);
+            int64_t a = mod_nonneg((int64_t)alpha - o, H);
+            memcpy(out + ((uint64_t)a * W + o) * C,
+                   in + ((uint64_t)alpha * W + beta) * C, C);
+        }
+}
+
+/* ----------------------------------------------------------- diffusion --- */
+
+/* Keystream layout of one frame used by the oracle: the r*S_i bytes of band
+ * i are stored from byte r*lo_i*W*C on (bands in order). */
+
+/* Eq. (3) for every band of the frame, round j: the first byte of band i is
+ * chained to s_d, the last byte of band (i+1) mod n of the confused frame
+ * (before diffusion); every other byte to the previous cipher byte. */
+void oracle_diffuse(const uint8_t *Y, uint8_t *Z, uint32_t H, uint32_t W,
+                    uint32_t C, uint32_t n, uint32_t r, uint32_t j,
+                    const uint8_t *ks)
+{
+    uint64_t row = (uint64_t)W * C;
+    for (uint32_t i = 0; i < n; i++) {
+        uint64_t lo = oracle_band_lo(H, n, i) * row;
+        uint64_t hi = oracle_band_lo(H, n, i + 1) * row;
+        uint64_t S = hi - lo;
+        uint64_t next_hi = oracle_band_lo(H, n, (i + 1) % n + 1) * row;
+        const uint8_t *b = ks + (uint64_t)r * lo + (uint64_t)j * S;
+        uint8_t prev = Y[next_hi - 1]; /* s_d */
+        for (uint64_t k = 0; k < S; k++) {
+            uint8_t sum = (uint8_t)(Y[lo + k] + b[k]);
+            Z[lo + k] = (uint8_t)(b[k] ^ sum ^ prev);
+            prev = Z[lo + k];
+        }
+    }
+}
+
+/* Eq. (4): P = (b xor C xor C_prev) - b.  The seed of band i is recovered
+ * first: it is the pre-diffusion last byte of band i'=(i+1) mod n, i.e.
+ * Eq. (4) applied to that band's last byte (its predecessor lies in the same
+ * band because every band holds at least 2 bytes). */
+void oracle_undiffuse(const uint8_t *Z, uint8_t *Y, uint32_t H, uint32_t W,
+                      uint32_t C, uint32_t n, uint32_t r, uint32_t j,
+                      const uint8_t *ks)
+{
+    uint64_t row = (uint64_t)W * C;
+    for (uint32_t i = 0; i < n; i++) {
+        uint64_t lo = oracle_band_lo(H, n, i) * row;
+        uint64_t hi = oracle_band_lo(H, n, i + 1) * row;
+        uint64_t S = hi - lo;
+        uint32_t ip = (i + 1) % n;
+        uint64_t lo_p = oracle_band_lo(H, n, ip) * row;
+        uint64_t hi_p = oracle_band_lo(H, n, ip + 1) * row;
+        uint64_t S_p = hi_p - lo_p;
+        uint8_t bp = ks[(uint64_t)r * lo_p + (uint64_t)j * S_p + S_p - 1];
+        uint8_t s_d = (uint8_t)((bp ^ Z[hi_p - 1] ^ Z[hi_p - 2]) - bp);
+        const uint8_t *b = ks + (uint64_t)r * lo + (uint64_t)j * S;
+        for (uint64_t k = 0; k < S; k++) {
+            uint8_t prev = k ? Z[lo + k - 1] : s_d;
+            Y[lo + k] = (uint8_t)((b[k] ^ Z[lo + k] ^ prev) - b[k]);
+        }
+    }
+}
+
+/* ------------------------------------------------------ whole frames --- */
+
+/* Algorithm 2, first two steps of the frame loop: the keystream of every
+ * band for T frames (r*F bytes per frame in the layout above).  x1, x2 hold
+ * the n chain states and are advanced. */
+void oracle_plcm_keystream(uint32_t H, uint32_t W, uint32_t C, uint32_t n,
+                           uint32_t r, double *x1, const double *p1,
+                           double *x2, const double *p2, uint64_t T,
+                           uint8_t *ks)
+{
+    uint64_t row = (uint64_t)W * C, F = (uint64_t)H * row;
+    for (uint64_t t = 0; t < T; t++)
+        for (uint32_t i = 0; i < n; i++) {
+            uint64_t lo = oracle_band_lo(H, n, i) * row;
+            uint64_t S = oracle_band_lo(H, n, i + 1) * row - lo;
+            oracle_plcm_bytes(&x1[i], p1[i], &x2[i], p2[i], (uint64_t)r * S,
+                              ks + t * (uint64_t)r * F + (uint64_t)r * lo);
+        }
+}
+
+/* Algorithms 1 and 2: for every frame, generate the keystream, then r times
+ * confuse the whole frame (Eq. 1) and diffuse every band (Eq. 3).  The
+ * confusion seed s_c[t] is the same for all rounds of frame t. */
+int oracle_encrypt(uint32_t H, uint32_t W, uint32_t C, uint32_t n, uint32_t r,
+                   double *x1, const double *p1, double *x2, const double *p2,
+                   const uint8_t *in, uint8_t *out, const uint32_t *s_c,
+                   uint64_t T)
+{
+    uint64_t F = (uint64_t)H * W * C;
+    uint8_t *ks = malloc((uint64_t)r * F), *A = malloc(F), *Y = malloc(F);
+    int64_t *g = malloc(sizeof(int64_t) * H);
+    if (!ks || !A || !Y || !g) {
+        free(ks); free(A); free(Y); free(g);
+        return -1;
+    }
+    for (uint64_t t = 0; t < T; t++) {
+        oracle_plcm_keystream(H, W, C, n, r, x1, p1, x2, p2, 1, ks);
+        oracle_gtable(H, s_c[t], g);
+        memcpy(A, in + t * F, F);
+        for (uint32_t j = 0; j < r; j++) {
+            oracle_confuse(A, Y, H, W, C, g);
+            oracle_diffuse(Y, A, H, W, C, n, r, j, ks);
+        }
+        memcpy(out + t * F, A, F);
+    }
+    free(ks); free(A); free(Y); free(g);
+    return 0;
+}
+
+/* Decryption: the same keystream, then the rounds in reverse order, each
+ * undoing diffusion (Eq. 4) and then confusion (Eq. 2). */
+int oracle_decrypt(uint32_t H, uint32_t W, uint32_t C, uint32_t n, uint32_t r,
+                   double *x1, const double *p1, double *x2, const double *p2,
+                   const uint8_t *in, uint8_t *out, const uint32_t *s_c,
+                   uint64_t T)
+{
+    uint64_t F = (uint64_t)H * W * C;
+    uint8_t *ks = malloc((uint64_t)r * F), *A = malloc(F), *Y = malloc(F);
+    int64_t *g = malloc(sizeof(int64_t) * H);
+    if (!ks || !A || !Y || !g) {
+        free(ks); free(A); free(Y); free(g);
+        return -1;
+    }
+    for (uint64_t t = 0; t < T; t++) {
+        oracle_plcm_keystream(H, W, C, n, r, x1, p1, x2, p2, 1, ks);
+        oracle_gtable(H, s_c[t], g);
+        memcpy(A, in + t * F, F);
+        for (uint32_t jj = r; jj-- > 0;) {
+            oracle_undiffuse(A, Y, H, W, C, n, r, jj, ks);
+            oracle_unconfuse(Y, A, H, W, C, g);
+        }
+        memcpy(out + t * F, A, F);
+    }
+    free(ks); free(A); free(Y); free(g);
+    return 0;
+}
