@@ -1,0 +1,203 @@
+"""Thin ctypes binding of libchaosvid (include/chaosvid.h).
+
+Argument marshalling only: every step of the cipher runs in the library's
+HIP kernels.  PyTorch provides device memory (uint8 CUDA tensors) and the
+current HIP stream.  Loading fails loudly when the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libchaosvid.so")
+
+CV_OK, CV_E_INVAL, CV_E_NOMEM, CV_E_HIP, CV_E_AGAIN, CV_E_STATE = range(6)
+CV_MAP_PLCM = 0
+CV_PATH_PLAIN = 0
+
+# every symbol include/chaosvid.h declares
+EXPORTS = (
+    "cv_spec_version", "cv_last_error", "cv_keysetup", "cv_key_free", "cv_key_get_state",
+    "cv_key_set_state", "cv_key_set_path", "cv_encrypt_frames", "cv_decrypt_frames",
+    "cv_keystream_frames", "cv_apply_rounds", "cv_key_get_launch", "cv_key_set_launch",
+)
+
+
+class CvGeom(ct.Structure):
+    _fields_ = [("height", ct.c_uint32), ("width", ct.c_uint32), ("channels", ct.c_uint32),
+                ("n_sub", ct.c_uint32), ("rounds", ct.c_uint32)]
+
+
+class CvLaunch(ct.Structure):
+    _fields_ = [("batch_frames", ct.c_uint32), ("threads", ct.c_uint32),
+                ("tile_rows_enc", ct.c_uint32), ("tile_rows_dec", ct.c_uint32)]
+
+
+class CvError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libchaosvid status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load() -> ct.CDLL:
+    """Load the in-tree libchaosvid.so (built by `python -m
+    paper_2302_07411_amd.build` or __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2302_07411_amd.build")
+    L = ct.CDLL(LIB_PATH)
+    vp, sz, u8p = ct.c_void_p, ct.c_size_t, ct.c_void_p
+    L.cv_spec_version.restype = ct.c_int
+    L.cv_spec_version.argtypes = []
+    L.cv_last_error.restype = ct.c_char_p
+    L.cv_last_error.argtypes = []
+    L.cv_keysetup.restype = ct.c_int
+    L.cv_keysetup.argtypes = [ct.POINTER(CvGeom), ct.c_int, ct.POINTER(ct.c_double), sz, ct.c_int,
+                              ct.POINTER(vp)]
+    L.cv_key_free.restype = None
+    L.cv_key_free.argtypes = [vp]
+    L.cv_key_get_state.restype = ct.c_int
+    L.cv_key_get_state.argtypes = [vp, ct.POINTER(ct.c_double), sz, ct.POINTER(ct.c_uint64)]
+    L.cv_key_set_state.restype = ct.c_int
+    L.cv_key_set_state.argtypes = [vp, ct.POINTER(ct.c_double), sz, ct.c_uint64]
+    L.cv_key_set_path.restype = ct.c_int
+    L.cv_key_set_path.argtypes = [vp, ct.c_int]
+    for name in ("cv_encrypt_frames", "cv_decrypt_frames"):
+        f = getattr(L, name)
+        f.restype = ct.c_int
+        f.argtypes = [vp, u8p, u8p, ct.POINTER(ct.c_uint32), sz, vp]
+    L.cv_key_get_launch.restype = ct.c_int
+    L.cv_key_get_launch.argtypes = [vp, ct.POINTER(CvLaunch)]
+    L.cv_key_set_launch.restype = ct.c_int
+    L.cv_key_set_launch.argtypes = [vp, ct.POINTER(CvLaunch)]
+    L.cv_keystream_frames.restype = ct.c_int
+    L.cv_keystream_frames.argtypes = [vp, u8p, sz, vp]
+    L.cv_apply_rounds.restype = ct.c_int
+    L.cv_apply_rounds.argtypes = [vp, ct.c_int, u8p, u8p, u8p, ct.POINTER(ct.c_uint32), sz, vp]
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != CV_OK:
+        raise CvError(status, load().cv_last_error().decode())
+
+
+def _ptr(t) -> int:
+    """Device address of a contiguous uint8 CUDA tensor."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.uint8 or not t.is_cuda:
+        raise TypeError("expected a torch.uint8 tensor on a HIP device")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _seeds(s_c, n: int):
+    arr = np.ascontiguousarray(np.asarray(s_c, dtype=np.uint32).reshape(-1))
+    if arr.size != n:
+        raise ValueError(f"need {n} confusion seeds, got {arr.size}")
+    return arr, arr.ctypes.data_as(ct.POINTER(ct.c_uint32))
+
+
+class Key:
+    """One stream's key: per-band PLCM generators on the device
+    (cv_keysetup).  `pm` is an (n, 4) array of (x0_1, p_1, x0_2, p_2)."""
+
+    def __init__(self, H, W, C, n, r, pm, device: int = 0):
+        L = load()
+        self.geom = (H, W, C, n, r)
+        self.frame_bytes = H * W * C
+        pm = np.ascontiguousarray(np.asarray(pm, np.float64).reshape(-1))
+        g = CvGeom(H, W, C, n, r)
+        h = ct.c_void_p()
+        _check(L.cv_keysetup(ct.byref(g), CV_MAP_PLCM, pm.ctypes.data_as(ct.POINTER(ct.c_double)),
+                             pm.size, device, ct.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().cv_key_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _nframes(self, t) -> int:
+        if t.numel() % self.frame_bytes:
+            raise ValueError("tensor size is not a whole number of frames")
+        return t.numel() // self.frame_bytes
+
+    def encrypt(self, src, dst, s_c, stream=None):
+        n = self._nframes(src)
+        if dst.numel() != src.numel():
+            raise ValueError("dst size differs from src")
+        arr, p = _seeds(s_c, n)
+        _check(load().cv_encrypt_frames(self._h, _ptr(src), _ptr(dst), p, n, _stream(stream)))
+
+    def decrypt(self, src, dst, s_c, stream=None):
+        n = self._nframes(src)
+        if dst.numel() != src.numel():
+            raise ValueError("dst size differs from src")
+        arr, p = _seeds(s_c, n)
+        _check(load().cv_decrypt_frames(self._h, _ptr(src), _ptr(dst), p, n, _stream(stream)))
+
+    def keystream(self, dst, n_frames: int, stream=None):
+        r = self.geom[4]
+        if dst.numel() != n_frames * r * self.frame_bytes:
+            raise ValueError("keystream buffer must hold n_frames*r*H*W*C bytes")
+        _check(load().cv_keystream_frames(self._h, _ptr(dst), n_frames, _stream(stream)))
+
+    def apply_rounds(self, decrypt: bool, src, dst, ks, s_c, stream=None):
+        n = self._nframes(src)
+        r = self.geom[4]
+        if ks.numel() != n * r * self.frame_bytes or dst.numel() != src.numel():
+            raise ValueError("buffer sizes do not match")
+        arr, p = _seeds(s_c, n)
+        _check(load().cv_apply_rounds(self._h, int(bool(decrypt)), _ptr(src), _ptr(dst), _ptr(ks),
+                                      p, n, _stream(stream)))
+
+    def get_state(self):
+        n = self.geom[3]
+        x = np.zeros(2 * n, np.float64)
+        fi = ct.c_uint64()
+        _check(load().cv_key_get_state(self._h, x.ctypes.data_as(ct.POINTER(ct.c_double)), x.size,
+                                       ct.byref(fi)))
+        return x.reshape(n, 2), fi.value
+
+    def set_state(self, x, frame_index: int):
+        x = np.ascontiguousarray(np.asarray(x, np.float64).reshape(-1))
+        _check(load().cv_key_set_state(self._h, x.ctypes.data_as(ct.POINTER(ct.c_double)), x.size,
+                                       frame_index))
+
+    def set_path(self, path: int):
+        _check(load().cv_key_set_path(self._h, path))
+
+    def get_launch(self) -> dict:
+        l = CvLaunch()
+        _check(load().cv_key_get_launch(self._h, ct.byref(l)))
+        return {f: getattr(l, f) for f, _ in CvLaunch._fields_}
+
+    def set_launch(self, **kw):
+        cur = self.get_launch()
+        cur.update(kw)
+        l = CvLaunch(**cur)
+        _check(load().cv_key_set_launch(self._h, ct.byref(l)))

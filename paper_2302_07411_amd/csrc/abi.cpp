@@ -1,0 +1,424 @@
+// Host runtime and C ABI of libchaosvid (declarations and contract in
+// include/chaosvid.h).
+//
+// A key owns the device-resident generator state of one stream and the
+// workspace its calls reuse: keystream for a batch of frames, one scratch
+// frame buffer per batch frame (the rounds ping-pong between it and the
+// output), and the per-frame row-shift tables.  Work is cut into batches of
+// at most `batch_frames` frames; per batch: shift tables H2D, one PRBG launch
+// for the whole batch, then r round launches over the whole batch.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "chaosvid.h"
+#include "cv_internal.h"
+
+using cv::Geom;
+
+struct cv_key {
+  Geom g{};
+  cv_map map = CV_MAP_PLCM;
+  int device = 0;
+  int path = CV_PATH_PLAIN;
+  uint64_t F = 0;              // bytes per frame
+  uint64_t frame_index = 0;    // frames processed so far
+  std::vector<double> pm;      // the n key records as given
+  double* d_state = nullptr;   // 2n: x of map 1, map 2 per band
+  cv::PlcmChain* d_chains = nullptr;
+  // workspace, grown on demand
+  uint32_t batch_frames = 0;
+  uint8_t* d_ks = nullptr;
+  uint8_t* d_scratch = nullptr;
+  uint32_t* d_gm = nullptr;
+  uint32_t* h_gm = nullptr;    // pinned staging of the shift tables
+  size_t ws_frames = 0;
+  hipEvent_t gm_done = nullptr;
+  bool gm_pending = false;
+  // launch shape
+  uint32_t threads = 1024;
+  uint32_t tile_enc = 0, tile_dec = 0;
+  uint32_t max_band_rows = 0;
+  size_t lds_max = 0;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+cv_status fail(cv_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+cv_status hip_fail(hipError_t e, const char* what) {
+  return fail(CV_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define CV_HIP(call)                                     \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);    \
+  } while (0)
+
+// Switch to the key's device for the lifetime of a call.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+// Sec. 2, Eq. (1): g(alpha) = floor(s_c * sin((2*pi*alpha)/H)), binary64,
+// left to right, reduced mod W for the kernels (beta = (o + g) mod W).
+void shift_table(uint32_t H, uint32_t W, uint32_t s_c, uint32_t* gm) {
+#pragma clang loop vectorize(disable)
+  for (uint32_t alpha = 0; alpha < H; alpha++) {
+    const double angle = ((2.0 * M_PI) * (double)alpha) / (double)H;
+    const int64_t g = (int64_t)floor((double)s_c * sin(angle));
+    int64_t m = g % (int64_t)W;
+    if (m < 0) m += W;
+    gm[alpha] = (uint32_t)m;
+  }
+}
+
+size_t lds_limit(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 64 * 1024;
+  return prop.sharedMemPerBlock;
+}
+
+bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + nb && y < x + na;
+}
+
+void free_workspace(cv_key* k) {
+  if (k->d_ks) (void)hipFree(k->d_ks);
+  if (k->d_scratch) (void)hipFree(k->d_scratch);
+  if (k->d_gm) (void)hipFree(k->d_gm);
+  if (k->h_gm) (void)hipHostFree(k->h_gm);
+  k->d_ks = k->d_scratch = nullptr;
+  k->d_gm = nullptr;
+  k->h_gm = nullptr;
+  k->ws_frames = 0;
+}
+
+cv_status ensure_workspace(cv_key* k, size_t frames) {
+  if (frames <= k->ws_frames) return CV_OK;
+  if (k->gm_pending) {
+    CV_HIP(hipEventSynchronize(k->gm_done));
+    k->gm_pending = false;
+  }
+  CV_HIP(hipDeviceSynchronize());  // older buffers may still be in use
+  free_workspace(k);
+  const Geom& g = k->g;
+  if (hipMalloc(&k->d_ks, frames * (uint64_t)g.r * k->F) != hipSuccess ||
+      hipMalloc(&k->d_scratch, frames * k->F) != hipSuccess ||
+      hipMalloc(&k->d_gm, frames * (uint64_t)g.H * sizeof(uint32_t)) != hipSuccess ||
+      hipHostMalloc(&k->h_gm, frames * (uint64_t)g.H * sizeof(uint32_t)) != hipSuccess) {
+    (void)hipGetLastError();
+    free_workspace(k);
+    return fail(CV_E_NOMEM, "workspace allocation failed");
+  }
+  k->ws_frames = frames;
+  return CV_OK;
+}
+
+// Stage the shift tables of `T` frames and copy them to the device.
+cv_status upload_shift_tables(cv_key* k, const uint32_t* s_c, size_t T, hipStream_t st) {
+  if (k->gm_pending) {  // the staging buffer is still being read by an earlier copy
+    CV_HIP(hipEventSynchronize(k->gm_done));
+    k->gm_pending = false;
+  }
+  const Geom& g = k->g;
+  for (size_t t = 0; t < T; t++) shift_table(g.H, g.W, s_c[t], k->h_gm + t * g.H);
+  CV_HIP(hipMemcpyAsync(k->d_gm, k->h_gm, T * g.H * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+  CV_HIP(hipEventRecord(k->gm_done, st));
+  k->gm_pending = true;
+  return CV_OK;
+}
+
+cv::RoundArgs round_args(const cv_key* k, const uint8_t* ks, uint32_t T) {
+  cv::RoundArgs a{};
+  a.ks = ks;
+  a.gm = k->d_gm;
+  a.frame_bytes = k->F;
+  a.ks_stride = (uint64_t)k->g.r * k->F;
+  a.g = k->g;
+  a.n_frames = T;
+  return a;
+}
+
+// r rounds over T frames (keystream already in `ks`).  Round outputs
+// alternate between `out` and the scratch buffer so that the last round
+// lands in `out` and no round reads the buffer it writes.
+cv_status run_rounds(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out, const uint8_t* ks,
+                     uint32_t T, hipStream_t st) {
+  const uint32_t r = k->g.r;
+  cv::RoundArgs a = round_args(k, ks, T);
+  const uint8_t* cur = in;
+  for (uint32_t s = 0; s < r; s++) {
+    uint8_t* target = ((r - 1 - s) % 2 == 0) ? out : k->d_scratch;
+    a.src = cur;
+    a.dst = target;
+    if (!decrypt) {
+      a.j = s;
+      a.tile_rows = k->tile_enc;
+      CV_HIP(cv::launch_round_enc(a, k->threads, st));
+    } else {
+      a.j = r - 1 - s;
+      a.tile_rows = k->tile_dec;
+      CV_HIP(cv::launch_round_dec(a, k->threads, st));
+    }
+    cur = target;
+  }
+  return CV_OK;
+}
+
+cv_status check_frames_args(const cv_key* k, const uint8_t* in, uint8_t* out, const uint32_t* s_c,
+                            size_t n) {
+  if (!k) return fail(CV_E_INVAL, "key is NULL");
+  if (n == 0) return CV_OK;
+  if (!in || !out || !s_c) return fail(CV_E_INVAL, "NULL buffer");
+  if (ranges_overlap(in, n * k->F, out, n * k->F)) return fail(CV_E_INVAL, "in and out overlap");
+  for (size_t t = 0; t < n; t++)
+    if (s_c[t] == 0) return fail(CV_E_INVAL, "confusion seed s_c must be >= 1");
+  if (n > 0xFFFFFFFFull) return fail(CV_E_INVAL, "too many frames in one call");
+  return CV_OK;
+}
+
+cv_status crypt_frames(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
+                       const uint32_t* s_c, size_t n, void* stream) {
+  cv_status s = check_frames_args(k, in, out, s_c, n);
+  if (s != CV_OK || n == 0) return s;
+  DeviceGuard dg(k->device);
+  hipStream_t st = (hipStream_t)stream;
+  const size_t B = std::min<size_t>(n, k->batch_frames);
+  if ((s = ensure_workspace(k, B)) != CV_OK) return s;
+  for (size_t f0 = 0; f0 < n; f0 += B) {
+    const uint32_t T = (uint32_t)std::min(B, n - f0);
+    if ((s = upload_shift_tables(k, s_c + f0, T, st)) != CV_OK) return s;
+    CV_HIP(cv::launch_prbg_plcm(k->d_chains, k->g.n, k->d_ks, T, st));
+    if ((s = run_rounds(k, decrypt, in + f0 * k->F, out + f0 * k->F, k->d_ks, T, st)) != CV_OK)
+      return s;
+    k->frame_index += T;
+  }
+  return CV_OK;
+}
+
+bool finite_in(double v, double lo, double hi) { return isfinite(v) && v > lo && v < hi; }
+
+}  // namespace
+
+extern "C" {
+
+int cv_spec_version(void) { return CV_SPEC_VERSION; }
+
+const char* cv_last_error(void) { return g_last_error.c_str(); }
+
+cv_status cv_keysetup(const cv_geom* geom, cv_map map, const double* p_m, size_t n_doubles,
+                      int device, cv_key** out) {
+  if (!geom || !p_m || !out) return fail(CV_E_INVAL, "NULL argument");
+  *out = nullptr;
+  const Geom g{geom->height, geom->width, geom->channels, geom->n_sub, geom->rounds};
+  if (map != CV_MAP_PLCM) return fail(CV_E_INVAL, "unknown map");
+  if (!g.H || !g.W || !g.C || !g.n || !g.r) return fail(CV_E_INVAL, "zero in geometry");
+  if (g.n > g.H) return fail(CV_E_INVAL, "more subframes than rows");
+  const uint64_t row = (uint64_t)g.W * g.C;
+  if ((uint64_t)g.H * row > 0xFFFFFFFFull / 8) return fail(CV_E_INVAL, "frame too large");
+  if (n_doubles != 4ull * g.n) return fail(CV_E_INVAL, "p_m must hold 4 doubles per subframe");
+  for (uint32_t i = 0; i < g.n; i++) {
+    const uint64_t S = (cv::band_lo(g.H, g.n, i + 1) - cv::band_lo(g.H, g.n, i)) * row;
+    if (S < 2) return fail(CV_E_INVAL, "every subframe needs at least 2 bytes");
+    const double* q = p_m + 4 * i;
+    if (!finite_in(q[0], 0.0, 1.0) || !finite_in(q[2], 0.0, 1.0))
+      return fail(CV_E_INVAL, "PLCM x0 must lie in (0,1)");
+    if (!finite_in(q[1], 0.0, 0.5) || !finite_in(q[3], 0.0, 0.5))
+      return fail(CV_E_INVAL, "PLCM p must lie in (0,1/2)");
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail(CV_E_INVAL, "no such HIP device");
+  DeviceGuard dg(device);
+  const size_t lds_max = lds_limit(device);
+  if (cv::round_lds_bytes(g, 1) > lds_max) return fail(CV_E_INVAL, "row too wide for LDS");
+
+  cv_key* k = new cv_key();
+  k->g = g;
+  k->map = map;
+  k->device = device;
+  k->F = (uint64_t)g.H * row;
+  k->pm.assign(p_m, p_m + n_doubles);
+  // launch shape: LDS tiles of up to 64 KiB (two workgroups per CU)
+  const size_t budget = std::min<size_t>(lds_max, 64 * 1024);
+  uint32_t rows_fit = 1;
+  while (rows_fit < g.H && cv::round_lds_bytes(g, rows_fit + 1) <= budget) rows_fit++;
+  uint32_t max_band_rows = 0;
+  for (uint32_t i = 0; i < g.n; i++)
+    max_band_rows = std::max<uint32_t>(
+        max_band_rows, (uint32_t)(cv::band_lo(g.H, g.n, i + 1) - cv::band_lo(g.H, g.n, i)));
+  k->max_band_rows = max_band_rows;
+  k->lds_max = lds_max;
+  k->tile_enc = std::min({rows_fit, max_band_rows, k->threads});
+  k->tile_dec = std::min({rows_fit, g.H, k->threads});
+  // batches of frames: keystream + scratch within ~1 GiB
+  const uint64_t per_frame = (uint64_t)(g.r + 1) * k->F;
+  k->batch_frames = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(256, (1ull << 30) / per_frame));
+
+  std::vector<double> state(2 * g.n);
+  std::vector<cv::PlcmChain> chains(g.n);
+  if (hipMalloc(&k->d_state, state.size() * sizeof(double)) != hipSuccess ||
+      hipMalloc(&k->d_chains, chains.size() * sizeof(cv::PlcmChain)) != hipSuccess) {
+    (void)hipGetLastError();
+    cv_key_free(k);
+    return fail(CV_E_NOMEM, "key allocation failed");
+  }
+  for (uint32_t i = 0; i < g.n; i++) {
+    const double* q = p_m + 4 * i;
+    state[2 * i] = q[0];
+    state[2 * i + 1] = q[2];
+    cv::PlcmChain& c = chains[i];
+    c.state = k->d_state + 2 * i;
+    c.p[0] = q[1];
+    c.p[1] = q[3];
+    c.h[0] = 0.5 - q[1];
+    c.h[1] = 0.5 - q[3];
+    const uint64_t lo = cv::band_lo(g.H, g.n, i), hi = cv::band_lo(g.H, g.n, i + 1);
+    c.out_off = (uint64_t)g.r * lo * row;
+    c.frame_stride = (uint64_t)g.r * k->F;
+    c.nbytes = (uint64_t)g.r * (hi - lo) * row;
+  }
+  hipError_t e = hipMemcpy(k->d_state, state.data(), state.size() * sizeof(double),
+                           hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(k->d_chains, chains.data(), chains.size() * sizeof(cv::PlcmChain),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&k->gm_done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    cv_key_free(k);
+    return hip_fail(e, "cv_keysetup");
+  }
+  *out = k;
+  return CV_OK;
+}
+
+void cv_key_free(cv_key* k) {
+  if (!k) return;
+  DeviceGuard dg(k->device);
+  (void)hipDeviceSynchronize();
+  free_workspace(k);
+  if (k->d_state) (void)hipFree(k->d_state);
+  if (k->d_chains) (void)hipFree(k->d_chains);
+  if (k->gm_done) (void)hipEventDestroy(k->gm_done);
+  delete k;
+}
+
+cv_status cv_key_get_state(const cv_key* k, double* x, size_t n_doubles, uint64_t* frame_index) {
+  if (!k || !x || !frame_index) return fail(CV_E_INVAL, "NULL argument");
+  if (n_doubles != 2ull * k->g.n) return fail(CV_E_INVAL, "state holds 2 doubles per subframe");
+  DeviceGuard dg(k->device);
+  CV_HIP(hipDeviceSynchronize());
+  CV_HIP(hipMemcpy(x, k->d_state, n_doubles * sizeof(double), hipMemcpyDeviceToHost));
+  *frame_index = k->frame_index;
+  return CV_OK;
+}
+
+cv_status cv_key_set_state(cv_key* k, const double* x, size_t n_doubles, uint64_t frame_index) {
+  if (!k || !x) return fail(CV_E_INVAL, "NULL argument");
+  if (n_doubles != 2ull * k->g.n) return fail(CV_E_INVAL, "state holds 2 doubles per subframe");
+  for (size_t i = 0; i < n_doubles; i++)
+    if (!(x[i] >= 0.0 && x[i] <= 1.0)) return fail(CV_E_INVAL, "state outside [0,1]");
+  DeviceGuard dg(k->device);
+  CV_HIP(hipDeviceSynchronize());
+  CV_HIP(hipMemcpy(k->d_state, x, n_doubles * sizeof(double), hipMemcpyHostToDevice));
+  k->frame_index = frame_index;
+  return CV_OK;
+}
+
+cv_status cv_key_set_path(cv_key* k, int path) {
+  if (!k) return fail(CV_E_INVAL, "key is NULL");
+  if (path != CV_PATH_PLAIN) return fail(CV_E_INVAL, "unknown path");
+  k->path = path;
+  return CV_OK;
+}
+
+cv_status cv_key_get_launch(const cv_key* k, cv_launch* l) {
+  if (!k || !l) return fail(CV_E_INVAL, "NULL argument");
+  l->batch_frames = k->batch_frames;
+  l->threads = k->threads;
+  l->tile_rows_enc = k->tile_enc;
+  l->tile_rows_dec = k->tile_dec;
+  return CV_OK;
+}
+
+cv_status cv_key_set_launch(cv_key* k, const cv_launch* l) {
+  if (!k || !l) return fail(CV_E_INVAL, "NULL argument");
+  if (l->batch_frames == 0) return fail(CV_E_INVAL, "batch_frames must be >= 1");
+  if (l->threads < 64 || l->threads > 1024 || l->threads % 64)
+    return fail(CV_E_INVAL, "threads must be a multiple of 64 in 64..1024");
+  const uint32_t te = std::min(l->tile_rows_enc, k->max_band_rows);
+  const uint32_t td = std::min(l->tile_rows_dec, k->g.H);
+  if (te == 0 || td == 0) return fail(CV_E_INVAL, "tile rows must be >= 1");
+  if (te > l->threads || td > l->threads) return fail(CV_E_INVAL, "tile rows exceed threads");
+  if (cv::round_lds_bytes(k->g, std::max(te, td)) > k->lds_max)
+    return fail(CV_E_INVAL, "tile does not fit in LDS");
+  k->batch_frames = l->batch_frames;
+  k->threads = l->threads;
+  k->tile_enc = te;
+  k->tile_dec = td;
+  return CV_OK;
+}
+
+cv_status cv_encrypt_frames(cv_key* k, const uint8_t* in, uint8_t* out, const uint32_t* s_c,
+                            size_t n, void* stream) {
+  return crypt_frames(k, false, in, out, s_c, n, stream);
+}
+
+cv_status cv_decrypt_frames(cv_key* k, const uint8_t* in, uint8_t* out, const uint32_t* s_c,
+                            size_t n, void* stream) {
+  return crypt_frames(k, true, in, out, s_c, n, stream);
+}
+
+cv_status cv_keystream_frames(cv_key* k, uint8_t* ks, size_t n, void* stream) {
+  if (!k) return fail(CV_E_INVAL, "key is NULL");
+  if (n == 0) return CV_OK;
+  if (!ks) return fail(CV_E_INVAL, "NULL buffer");
+  if (n > 0xFFFFFFFFull) return fail(CV_E_INVAL, "too many frames in one call");
+  DeviceGuard dg(k->device);
+  CV_HIP(cv::launch_prbg_plcm(k->d_chains, k->g.n, ks, (uint32_t)n, (hipStream_t)stream));
+  k->frame_index += n;
+  return CV_OK;
+}
+
+cv_status cv_apply_rounds(cv_key* k, int decrypt, const uint8_t* in, uint8_t* out,
+                          const uint8_t* ks, const uint32_t* s_c, size_t n, void* stream) {
+  cv_status s = check_frames_args(k, in, out, s_c, n);
+  if (s != CV_OK || n == 0) return s;
+  if (!ks) return fail(CV_E_INVAL, "NULL keystream");
+  const size_t ks_bytes = n * (uint64_t)k->g.r * k->F;
+  if (ranges_overlap(ks, ks_bytes, in, n * k->F) || ranges_overlap(ks, ks_bytes, out, n * k->F))
+    return fail(CV_E_INVAL, "keystream overlaps a frame buffer");
+  DeviceGuard dg(k->device);
+  hipStream_t st = (hipStream_t)stream;
+  const size_t B = std::min<size_t>(n, k->batch_frames);
+  if ((s = ensure_workspace(k, B)) != CV_OK) return s;
+  for (size_t f0 = 0; f0 < n; f0 += B) {
+    const uint32_t T = (uint32_t)std::min(B, n - f0);
+    if ((s = upload_shift_tables(k, s_c + f0, T, st)) != CV_OK) return s;
+    if ((s = run_rounds(k, decrypt != 0, in + f0 * k->F, out + f0 * k->F,
+                        ks + f0 * (uint64_t)k->g.r * k->F, T, st)) != CV_OK)
+      return s;
+  }
+  return CV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,62 @@
+// Internal declarations of libchaosvid shared by the HIP kernels and the
+// host runtime.  Not part of the public C ABI (that is include/chaosvid.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cv {
+
+// Geometry of one video stream.  Band (subframe) i covers rows
+// [floor(i*H/n), floor((i+1)*H/n)) -- Algorithm 2's startRow/endRow,
+// extended with floor so every row is covered when n does not divide H.
+struct Geom {
+  uint32_t H, W, C, n, r;
+};
+
+__host__ __device__ inline uint64_t band_lo(uint32_t H, uint32_t n, uint32_t i) {
+  return ((uint64_t)i * H) / n;
+}
+
+// Band holding row `row`: the largest i with floor(i*H/n) <= row.
+__host__ __device__ inline uint32_t band_of_row(uint32_t H, uint32_t n, uint32_t row) {
+  return (uint32_t)((((uint64_t)row + 1) * n - 1) / H);
+}
+
+// ---------------------------------------------------------------- PRBG ----
+// One chain = the two PLCMs of one band of one stream (Sec. 3).  Lane 2c of a
+// wavefront iterates map 1 of chain c, lane 2c+1 map 2; 32 chains/wavefront.
+struct PlcmChain {
+  double* state;          // [2]: current x of map 1, map 2 (device, updated)
+  double p[2];            // control parameters p of map 1, map 2
+  double h[2];            // 1/2 - p, rounded once (bit-identical to forming it per step)
+  uint64_t out_off;       // offset of this band's bytes in a frame's keystream
+  uint64_t frame_stride;  // bytes from one frame's keystream to the next
+  uint64_t nbytes;        // r * S_i bytes per frame
+};
+
+// Generate n_frames frames of keystream for n_chains chains into ks_base.
+hipError_t launch_prbg_plcm(const PlcmChain* d_chains, uint32_t n_chains, uint8_t* ks_base,
+                            uint32_t n_frames, hipStream_t s);
+
+// --------------------------------------------------------------- rounds ---
+// One confusion+diffusion round (or its inverse) over n_frames frames of one
+// stream.  Frames, keystream and shift tables are laid out frame after frame.
+struct RoundArgs {
+  const uint8_t* src;     // round input, frame 0
+  uint8_t* dst;           // round output, frame 0
+  const uint8_t* ks;      // keystream of frame 0: band i's r*S_i bytes at r*lo_i*W*C
+  const uint32_t* gm;     // per frame H entries: g(alpha) mod W
+  uint64_t frame_bytes;   // F = H*W*C
+  uint64_t ks_stride;     // keystream bytes per frame (r*F)
+  Geom g;
+  uint32_t j;             // round index 0..r-1
+  uint32_t tile_rows;     // rows staged in LDS at a time
+  uint32_t n_frames;
+};
+
+// LDS bytes a round kernel needs for a tile of `tile_rows` rows.
+size_t round_lds_bytes(const Geom& g, uint32_t tile_rows);
+hipError_t launch_round_enc(const RoundArgs& a, uint32_t threads, hipStream_t s);
+hipError_t launch_round_dec(const RoundArgs& a, uint32_t threads, hipStream_t s);
+
+}  // namespace cv
