@@ -83,6 +83,9 @@ typedef struct {
   uint32_t threads;        /* threads per round workgroup: 64..1024, multiple of 64 */
   uint32_t tile_rows_enc;  /* frame rows staged in LDS per step of an encryption round */
   uint32_t tile_rows_dec;  /* frame rows staged in LDS per step of a decryption round */
+  uint32_t exact_division; /* 1: keystream divisions use the IEEE division instruction
+                              sequence; 0: the reciprocal + two-FMA-correction division
+                              where it is provably correctly rounded (same bytes) */
 } cv_launch;
 
 /* Version of the cipher readings above (CV_SPEC_VERSION). */
@@ -132,6 +135,24 @@ cv_status cv_key_get_launch(const cv_key *key, cv_launch *launch);
  * needs more LDS than one workgroup may have.  Tile rows beyond a band's
  * height (encryption) or the frame height (decryption) are clamped. */
 cv_status cv_key_set_launch(cv_key *key, const cv_launch *launch);
+
+/* Per-kernel timing of a key's launches, accumulated while profiling is on:
+ * HIP events are recorded on the launch stream around every kernel. */
+typedef struct {
+  double prbg_ms;        /* keystream generator launches */
+  uint64_t prbg_launches;
+  uint64_t prbg_steps;   /* chain steps (two PLCM iterates each) generated */
+  double round_ms;       /* confusion+diffusion round launches (both directions) */
+  uint64_t round_launches;
+  uint64_t round_frames; /* frame-rounds processed */
+} cv_profile;
+
+/* Turn event profiling on (1) or off (0); turning it on clears the totals. */
+cv_status cv_key_set_profiling(cv_key *key, int on);
+
+/* Totals since profiling was turned on (synchronises the recorded events).
+ * CV_E_STATE if profiling is off. */
+cv_status cv_key_get_profile(cv_key *key, cv_profile *prof);
 
 /* Encrypt n_frames consecutive frames of the stream (Algorithm 1 and 2):
  * for every frame, generate its keystream, then r rounds of confusion

@@ -23,6 +23,7 @@ EXPORTS = (
     "cv_spec_version", "cv_last_error", "cv_keysetup", "cv_key_free", "cv_key_get_state",
     "cv_key_set_state", "cv_key_set_path", "cv_encrypt_frames", "cv_decrypt_frames",
     "cv_keystream_frames", "cv_apply_rounds", "cv_key_get_launch", "cv_key_set_launch",
+    "cv_key_set_profiling", "cv_key_get_profile",
 )
 
 
@@ -33,7 +34,14 @@ class CvGeom(ct.Structure):
 
 class CvLaunch(ct.Structure):
     _fields_ = [("batch_frames", ct.c_uint32), ("threads", ct.c_uint32),
-                ("tile_rows_enc", ct.c_uint32), ("tile_rows_dec", ct.c_uint32)]
+                ("tile_rows_enc", ct.c_uint32), ("tile_rows_dec", ct.c_uint32),
+                ("exact_division", ct.c_uint32)]
+
+
+class CvProfile(ct.Structure):
+    _fields_ = [("prbg_ms", ct.c_double), ("prbg_launches", ct.c_uint64),
+                ("prbg_steps", ct.c_uint64), ("round_ms", ct.c_double),
+                ("round_launches", ct.c_uint64), ("round_frames", ct.c_uint64)]
 
 
 class CvError(RuntimeError):
@@ -78,6 +86,10 @@ def load() -> ct.CDLL:
     L.cv_key_get_launch.argtypes = [vp, ct.POINTER(CvLaunch)]
     L.cv_key_set_launch.restype = ct.c_int
     L.cv_key_set_launch.argtypes = [vp, ct.POINTER(CvLaunch)]
+    L.cv_key_set_profiling.restype = ct.c_int
+    L.cv_key_set_profiling.argtypes = [vp, ct.c_int]
+    L.cv_key_get_profile.restype = ct.c_int
+    L.cv_key_get_profile.argtypes = [vp, ct.POINTER(CvProfile)]
     L.cv_keystream_frames.restype = ct.c_int
     L.cv_keystream_frames.argtypes = [vp, u8p, sz, vp]
     L.cv_apply_rounds.restype = ct.c_int
@@ -201,3 +213,11 @@ class Key:
         cur.update(kw)
         l = CvLaunch(**cur)
         _check(load().cv_key_set_launch(self._h, ct.byref(l)))
+
+    def set_profiling(self, on: bool):
+        _check(load().cv_key_set_profiling(self._h, int(bool(on))))
+
+    def get_profile(self) -> dict:
+        p = CvProfile()
+        _check(load().cv_key_get_profile(self._h, ct.byref(p)))
+        return {f: getattr(p, f) for f, _ in CvProfile._fields_}

@@ -28,6 +28,8 @@ struct cv_key {
   uint64_t frame_index = 0;    // frames processed so far
   std::vector<double> pm;      // the n key records as given
   double* d_state = nullptr;   // 2n: x of map 1, map 2 per band
+  bool fast = false;           // every chain qualifies for the reciprocal division
+  bool exact_division = false; // caller forces the IEEE division
   cv::PlcmChain* d_chains = nullptr;
   // workspace, grown on demand
   uint32_t batch_frames = 0;
@@ -43,6 +45,16 @@ struct cv_key {
   uint32_t tile_enc = 0, tile_dec = 0;
   uint32_t max_band_rows = 0;
   size_t lds_max = 0;
+  // event profiling
+  bool profiling = false;
+  struct Span {
+    hipEvent_t a, b;
+    int kind;  // 0 = prbg, 1 = round
+    uint64_t work;
+  };
+  std::vector<Span> spans;
+  std::vector<hipEvent_t> event_pool;
+  cv_profile prof{};
 };
 
 namespace {
@@ -88,6 +100,67 @@ void shift_table(uint32_t H, uint32_t W, uint32_t s_c, uint32_t* gm) {
     if (m < 0) m += W;
     gm[alpha] = (uint32_t)m;
   }
+}
+
+hipEvent_t pooled_event(cv_key* k) {
+  if (!k->event_pool.empty()) {
+    hipEvent_t e = k->event_pool.back();
+    k->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Fold finished spans into the totals and recycle their events.
+cv_status drain_spans(cv_key* k) {
+  for (auto& sp : k->spans) {
+    CV_HIP(hipEventSynchronize(sp.b));
+    float ms = 0.f;
+    CV_HIP(hipEventElapsedTime(&ms, sp.a, sp.b));
+    if (sp.kind == 0) {
+      k->prof.prbg_ms += ms;
+      k->prof.prbg_launches++;
+      k->prof.prbg_steps += sp.work;
+    } else {
+      k->prof.round_ms += ms;
+      k->prof.round_launches++;
+      k->prof.round_frames += sp.work;
+    }
+    k->event_pool.push_back(sp.a);
+    k->event_pool.push_back(sp.b);
+  }
+  k->spans.clear();
+  return CV_OK;
+}
+
+// Optional events around one launch: begin() before, end() after.
+struct Timed {
+  cv_key* k;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  Timed(cv_key* key, hipStream_t s) : k(key), st(s) {
+    if (k->profiling && (a = pooled_event(k)) != nullptr) (void)hipEventRecord(a, st);
+  }
+  void end(int kind, uint64_t work) {
+    if (!a) return;
+    hipEvent_t b = pooled_event(k);
+    if (!b) return;
+    (void)hipEventRecord(b, st);
+    k->spans.push_back({a, b, kind, work});
+    if (k->spans.size() > 4096) (void)drain_spans(k);
+  }
+};
+
+uint64_t prbg_steps(const cv_key* k, uint64_t frames) {
+  uint64_t steps = 0;
+  const uint64_t row = (uint64_t)k->g.W * k->g.C;
+  for (uint32_t i = 0; i < k->g.n; i++) {
+    const uint64_t S = (cv::band_lo(k->g.H, k->g.n, i + 1) - cv::band_lo(k->g.H, k->g.n, i)) * row;
+    steps += (k->g.r * S + 5) / 6;
+  }
+  return steps * frames;
 }
 
 size_t lds_limit(int device) {
@@ -170,6 +243,7 @@ cv_status run_rounds(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out, c
     uint8_t* target = ((r - 1 - s) % 2 == 0) ? out : k->d_scratch;
     a.src = cur;
     a.dst = target;
+    Timed tm(k, st);
     if (!decrypt) {
       a.j = s;
       a.tile_rows = k->tile_enc;
@@ -179,6 +253,7 @@ cv_status run_rounds(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out, c
       a.tile_rows = k->tile_dec;
       CV_HIP(cv::launch_round_dec(a, k->threads, st));
     }
+    tm.end(1, T);
     cur = target;
   }
   return CV_OK;
@@ -207,7 +282,9 @@ cv_status crypt_frames(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
   for (size_t f0 = 0; f0 < n; f0 += B) {
     const uint32_t T = (uint32_t)std::min(B, n - f0);
     if ((s = upload_shift_tables(k, s_c + f0, T, st)) != CV_OK) return s;
-    CV_HIP(cv::launch_prbg_plcm(k->d_chains, k->g.n, k->d_ks, T, st));
+    Timed tm(k, st);
+    CV_HIP(cv::launch_prbg_plcm(k->d_chains, k->g.n, k->d_ks, T, k->fast && !k->exact_division, st));
+    tm.end(0, prbg_steps(k, T));
     if ((s = run_rounds(k, decrypt, in + f0 * k->F, out + f0 * k->F, k->d_ks, T, st)) != CV_OK)
       return s;
     k->frame_index += T;
@@ -282,16 +359,20 @@ cv_status cv_keysetup(const cv_geom* geom, cv_map map, const double* p_m, size_t
     cv_key_free(k);
     return fail(CV_E_NOMEM, "key allocation failed");
   }
+  k->fast = true;
   for (uint32_t i = 0; i < g.n; i++) {
     const double* q = p_m + 4 * i;
     state[2 * i] = q[0];
     state[2 * i + 1] = q[2];
     cv::PlcmChain& c = chains[i];
     c.state = k->d_state + 2 * i;
-    c.p[0] = q[1];
-    c.p[1] = q[3];
-    c.h[0] = 0.5 - q[1];
-    c.h[1] = 0.5 - q[3];
+    for (int m = 0; m < 2; m++) {
+      c.p[m] = q[2 * m + 1];
+      c.h[m] = 0.5 - c.p[m];
+      c.ip[m] = 1.0 / c.p[m];
+      c.ih[m] = 1.0 / c.h[m];
+      k->fast = k->fast && cv::plcm_fast_ok(q[2 * m], c.p[m]);
+    }
     const uint64_t lo = cv::band_lo(g.H, g.n, i), hi = cv::band_lo(g.H, g.n, i + 1);
     c.out_off = (uint64_t)g.r * lo * row;
     c.frame_stride = (uint64_t)g.r * k->F;
@@ -315,6 +396,8 @@ void cv_key_free(cv_key* k) {
   if (!k) return;
   DeviceGuard dg(k->device);
   (void)hipDeviceSynchronize();
+  (void)drain_spans(k);
+  for (hipEvent_t e : k->event_pool) (void)hipEventDestroy(e);
   free_workspace(k);
   if (k->d_state) (void)hipFree(k->d_state);
   if (k->d_chains) (void)hipFree(k->d_chains);
@@ -341,6 +424,10 @@ cv_status cv_key_set_state(cv_key* k, const double* x, size_t n_doubles, uint64_
   CV_HIP(hipDeviceSynchronize());
   CV_HIP(hipMemcpy(k->d_state, x, n_doubles * sizeof(double), hipMemcpyHostToDevice));
   k->frame_index = frame_index;
+  bool fast = true;
+  for (uint32_t i = 0; i < k->g.n; i++)
+    for (int m = 0; m < 2; m++) fast = fast && cv::plcm_fast_ok(x[2 * i + m], k->pm[4 * i + 2 * m + 1]);
+  k->fast = fast;
   return CV_OK;
 }
 
@@ -357,12 +444,14 @@ cv_status cv_key_get_launch(const cv_key* k, cv_launch* l) {
   l->threads = k->threads;
   l->tile_rows_enc = k->tile_enc;
   l->tile_rows_dec = k->tile_dec;
+  l->exact_division = k->exact_division ? 1 : 0;
   return CV_OK;
 }
 
 cv_status cv_key_set_launch(cv_key* k, const cv_launch* l) {
   if (!k || !l) return fail(CV_E_INVAL, "NULL argument");
   if (l->batch_frames == 0) return fail(CV_E_INVAL, "batch_frames must be >= 1");
+  if (l->exact_division > 1) return fail(CV_E_INVAL, "exact_division must be 0 or 1");
   if (l->threads < 64 || l->threads > 1024 || l->threads % 64)
     return fail(CV_E_INVAL, "threads must be a multiple of 64 in 64..1024");
   const uint32_t te = std::min(l->tile_rows_enc, k->max_band_rows);
@@ -375,6 +464,27 @@ cv_status cv_key_set_launch(cv_key* k, const cv_launch* l) {
   k->threads = l->threads;
   k->tile_enc = te;
   k->tile_dec = td;
+  k->exact_division = l->exact_division != 0;
+  return CV_OK;
+}
+
+cv_status cv_key_set_profiling(cv_key* k, int on) {
+  if (!k) return fail(CV_E_INVAL, "key is NULL");
+  DeviceGuard dg(k->device);
+  cv_status s = drain_spans(k);
+  if (s != CV_OK) return s;
+  k->profiling = on != 0;
+  k->prof = cv_profile{};
+  return CV_OK;
+}
+
+cv_status cv_key_get_profile(cv_key* k, cv_profile* prof) {
+  if (!k || !prof) return fail(CV_E_INVAL, "NULL argument");
+  if (!k->profiling) return fail(CV_E_STATE, "profiling is off");
+  DeviceGuard dg(k->device);
+  cv_status s = drain_spans(k);
+  if (s != CV_OK) return s;
+  *prof = k->prof;
   return CV_OK;
 }
 
@@ -394,7 +504,10 @@ cv_status cv_keystream_frames(cv_key* k, uint8_t* ks, size_t n, void* stream) {
   if (!ks) return fail(CV_E_INVAL, "NULL buffer");
   if (n > 0xFFFFFFFFull) return fail(CV_E_INVAL, "too many frames in one call");
   DeviceGuard dg(k->device);
-  CV_HIP(cv::launch_prbg_plcm(k->d_chains, k->g.n, ks, (uint32_t)n, (hipStream_t)stream));
+  Timed tm(k, (hipStream_t)stream);
+  CV_HIP(cv::launch_prbg_plcm(k->d_chains, k->g.n, ks, (uint32_t)n, k->fast && !k->exact_division,
+                              (hipStream_t)stream));
+  tm.end(0, prbg_steps(k, n));
   k->frame_index += n;
   return CV_OK;
 }

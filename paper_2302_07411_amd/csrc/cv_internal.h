@@ -29,14 +29,23 @@ struct PlcmChain {
   double* state;          // [2]: current x of map 1, map 2 (device, updated)
   double p[2];            // control parameters p of map 1, map 2
   double h[2];            // 1/2 - p, rounded once (bit-identical to forming it per step)
+  double ip[2], ih[2];    // RN(1/p), RN(1/h) for the fast division path
   uint64_t out_off;       // offset of this band's bytes in a frame's keystream
   uint64_t frame_stride;  // bytes from one frame's keystream to the next
   uint64_t nbytes;        // r * S_i bytes per frame
 };
 
 // Generate n_frames frames of keystream for n_chains chains into ks_base.
+// `fast` selects the reciprocal division, valid only for chains that
+// satisfy plcm_fast_ok (identical bytes either way).
 hipError_t launch_prbg_plcm(const PlcmChain* d_chains, uint32_t n_chains, uint8_t* ks_base,
-                            uint32_t n_frames, hipStream_t s);
+                            uint32_t n_frames, bool fast, hipStream_t s);
+
+// Conditions under which the reciprocal division is exact for a whole orbit:
+// p >= 2^-64 and the current state x is 0 or >= 2^-800.
+inline bool plcm_fast_ok(double x, double p) {
+  return p >= 0x1p-64 && (x == 0.0 || x >= 0x1p-800);
+}
 
 // --------------------------------------------------------------- rounds ---
 // One confusion+diffusion round (or its inverse) over n_frames frames of one

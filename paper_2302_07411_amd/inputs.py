@@ -62,6 +62,29 @@ class CorrelatedVideo:
     def frames(self, t0: int, T: int) -> np.ndarray:
         return np.stack([self.frame(t0 + k) for k in range(T)])
 
+    def frames_torch(self, t0: int, T: int, device):
+        """The same recipe evaluated with torch on `device` (float32, torch's
+        own seeded normal noise), for workloads too large to generate on the
+        host.  Returns a contiguous uint8 tensor (T, H, W, C).  The values
+        differ from frames() (another noise source); each consumer uses one
+        of the two consistently."""
+        import torch
+        H, W, C = self.H, self.W, self.C
+        g = torch.Generator(device=device)
+        g.manual_seed((self.seed << 20) + t0)
+        y = torch.arange(H, device=device, dtype=torch.float32).view(1, H, 1)
+        x = torch.arange(W, device=device, dtype=torch.float32).view(1, 1, W)
+        t = torch.arange(t0, t0 + T, device=device, dtype=torch.float32).view(T, 1, 1)
+        base1 = TWO_PI * (self.f1x * x + self.f1y * y - self.v1 * t)
+        base2 = TWO_PI * (self.f2x * x - self.f2y * y + self.v2 * t)
+        out = torch.empty((T, H, W, C), dtype=torch.uint8, device=device)
+        for c in range(C):
+            v = 128.0 + 60.0 * torch.sin(base1 + float(self.phi[c])) \
+                + 40.0 * torch.sin(base2 + float(self.psi[c]))
+            v = v + 8.0 * torch.randn((T, H, W), generator=g, device=device, dtype=torch.float32)
+            out[..., c] = v.round_().clamp_(0, 255).to(torch.uint8)
+        return out
+
 
 def uniform_frames(H: int, W: int, C: int, T: int, seed: int) -> np.ndarray:
     """Independent uniform bytes (the 256x256 grayscale single-frame case)."""

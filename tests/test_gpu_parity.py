@@ -142,7 +142,7 @@ def test_state_continuation_and_checkpoint(B):
 
 
 @pytest.mark.parametrize("launch", [
-    dict(batch_frames=1), dict(batch_frames=2, threads=256), dict(threads=64, tile_rows_enc=1,
+    dict(batch_frames=1), dict(batch_frames=2, threads=256, exact_division=1), dict(threads=64, tile_rows_enc=1,
                                                                   tile_rows_dec=1),
     dict(threads=512, tile_rows_enc=3, tile_rows_dec=5), dict(threads=128, tile_rows_enc=7,
                                                               tile_rows_dec=64),
@@ -185,6 +185,48 @@ def test_special_orbits(B):
     enc = torch.empty_like(src)
     B.Key(H, W, C, n, r, pm).encrypt(src, enc, s_c)
     assert np.array_equal(_host(enc, frames.shape), want)
+
+
+def test_exact_division_path_and_tiny_keys(B):
+    """Keys outside the reciprocal-division domain (p < 2^-64 or a tiny
+    initial value) run the IEEE-division path; the same key with the path
+    forced gives the same bytes as the reciprocal path."""
+    H, W, C, n, r, T = 24, 20, 3, 4, 5, 3
+    pm = plcm_key(n, 31)
+    pm[1, 0] = 1e-300                 # tiny initial value
+    pm[2, 3] = 2.0 ** -70             # tiny control parameter
+    _, frames, s_c = _case("tiny-keys", H, W, C, n, r, T, seed=8)
+    want = oracle.PlcmKey(H, W, C, n, r, pm).encrypt(frames, s_c)
+    src = _dev(frames)
+    enc = torch.empty_like(src)
+    B.Key(H, W, C, n, r, pm).encrypt(src, enc, s_c)
+    assert np.array_equal(_host(enc, frames.shape), want)
+    pm2 = plcm_key(n, 32)
+    ref = oracle.PlcmKey(H, W, C, n, r, pm2).keystream(T)
+    for exact in (0, 1):
+        k = B.Key(H, W, C, n, r, pm2)
+        k.set_launch(exact_division=exact)
+        ks = torch.empty(T * r * H * W * C, dtype=torch.uint8, device="cuda:0")
+        k.keystream(ks, T)
+        assert np.array_equal(_host(ks, ref.shape), ref)
+
+
+def test_long_keystream(B):
+    """About 26 million chain steps (52 million divisions) against the
+    oracle: the fast division over long chaotic orbits, 32 chains in one
+    wavefront, frames straddling ring blocks."""
+    H, W, C, n, r, T = 1024, 1024, 3, 32, 5, 10
+    pm = plcm_key(n, 4242)
+    print(f"[case] long keystream H={H} W={W} C={C} n={n} T={T}", flush=True)
+    ref = oracle.PlcmKey(H, W, C, n, r, pm)
+    want = ref.keystream(T)
+    key = B.Key(H, W, C, n, r, pm)
+    ks = torch.empty(T * r * H * W * C, dtype=torch.uint8, device="cuda:0")
+    key.keystream(ks, T)
+    got = _host(ks, want.shape)
+    assert np.array_equal(got, want), f"{np.count_nonzero(got != want)} bytes differ"
+    x, _ = key.get_state()
+    assert np.array_equal(x[:, 0], ref.x1) and np.array_equal(x[:, 1], ref.x2)
 
 
 @pytest.mark.parametrize("name,H,W,C,n,r,T", [
