@@ -83,9 +83,12 @@ typedef struct {
   uint32_t threads;        /* threads per round workgroup: 64..1024, multiple of 64 */
   uint32_t tile_rows_enc;  /* frame rows staged in LDS per step of an encryption round */
   uint32_t tile_rows_dec;  /* frame rows staged in LDS per step of a decryption round */
-  uint32_t exact_division; /* 1: keystream divisions use the IEEE division instruction
-                              sequence; 0: the reciprocal + two-FMA-correction division
-                              where it is provably correctly rounded (same bytes) */
+  uint32_t prbg_variant;   /* keystream generator, all giving the same bytes:
+                              0 auto (fastest valid), 1 IEEE division instruction sequence,
+                              2 reciprocal + two FMA corrections (provably correctly rounded
+                                for keys with p >= 2^-64 and states 0 or >= 2^-800),
+                              3 as 2 with one lane per piece of the map.
+                              2 and 3 fall back to 1 for keys outside that domain. */
 } cv_launch;
 
 /* Version of the cipher readings above (CV_SPEC_VERSION). */

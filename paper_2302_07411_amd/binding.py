@@ -35,7 +35,7 @@ class CvGeom(ct.Structure):
 class CvLaunch(ct.Structure):
     _fields_ = [("batch_frames", ct.c_uint32), ("threads", ct.c_uint32),
                 ("tile_rows_enc", ct.c_uint32), ("tile_rows_dec", ct.c_uint32),
-                ("exact_division", ct.c_uint32)]
+                ("prbg_variant", ct.c_uint32)]
 
 
 class CvProfile(ct.Structure):

@@ -29,7 +29,7 @@ struct cv_key {
   std::vector<double> pm;      // the n key records as given
   double* d_state = nullptr;   // 2n: x of map 1, map 2 per band
   bool fast = false;           // every chain qualifies for the reciprocal division
-  bool exact_division = false; // caller forces the IEEE division
+  uint32_t prbg_variant = 0;   // requested generator variant (cv_launch.prbg_variant)
   cv::PlcmChain* d_chains = nullptr;
   // workspace, grown on demand
   uint32_t batch_frames = 0;
@@ -152,6 +152,14 @@ struct Timed {
     if (k->spans.size() > 4096) (void)drain_spans(k);
   }
 };
+
+// Generator variant for the next launch: the requested one, or the IEEE
+// division when the key is outside the reciprocal division's domain.
+int prbg_variant(const cv_key* k) {
+  if (!k->fast || k->prbg_variant == 1) return cv::PRBG_EXACT;
+  if (k->prbg_variant == 2) return cv::PRBG_RECIP;
+  return cv::PRBG_RECIP_PAIR;
+}
 
 uint64_t prbg_steps(const cv_key* k, uint64_t frames) {
   uint64_t steps = 0;
@@ -283,7 +291,7 @@ cv_status crypt_frames(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
     const uint32_t T = (uint32_t)std::min(B, n - f0);
     if ((s = upload_shift_tables(k, s_c + f0, T, st)) != CV_OK) return s;
     Timed tm(k, st);
-    CV_HIP(cv::launch_prbg_plcm(k->d_chains, k->g.n, k->d_ks, T, k->fast && !k->exact_division, st));
+    CV_HIP(cv::launch_prbg_plcm(k->d_chains, k->g.n, k->d_ks, T, prbg_variant(k), st));
     tm.end(0, prbg_steps(k, T));
     if ((s = run_rounds(k, decrypt, in + f0 * k->F, out + f0 * k->F, k->d_ks, T, st)) != CV_OK)
       return s;
@@ -444,14 +452,14 @@ cv_status cv_key_get_launch(const cv_key* k, cv_launch* l) {
   l->threads = k->threads;
   l->tile_rows_enc = k->tile_enc;
   l->tile_rows_dec = k->tile_dec;
-  l->exact_division = k->exact_division ? 1 : 0;
+  l->prbg_variant = k->prbg_variant;
   return CV_OK;
 }
 
 cv_status cv_key_set_launch(cv_key* k, const cv_launch* l) {
   if (!k || !l) return fail(CV_E_INVAL, "NULL argument");
   if (l->batch_frames == 0) return fail(CV_E_INVAL, "batch_frames must be >= 1");
-  if (l->exact_division > 1) return fail(CV_E_INVAL, "exact_division must be 0 or 1");
+  if (l->prbg_variant > 3) return fail(CV_E_INVAL, "prbg_variant must be 0..3");
   if (l->threads < 64 || l->threads > 1024 || l->threads % 64)
     return fail(CV_E_INVAL, "threads must be a multiple of 64 in 64..1024");
   const uint32_t te = std::min(l->tile_rows_enc, k->max_band_rows);
@@ -464,7 +472,7 @@ cv_status cv_key_set_launch(cv_key* k, const cv_launch* l) {
   k->threads = l->threads;
   k->tile_enc = te;
   k->tile_dec = td;
-  k->exact_division = l->exact_division != 0;
+  k->prbg_variant = l->prbg_variant;
   return CV_OK;
 }
 
@@ -505,7 +513,7 @@ cv_status cv_keystream_frames(cv_key* k, uint8_t* ks, size_t n, void* stream) {
   if (n > 0xFFFFFFFFull) return fail(CV_E_INVAL, "too many frames in one call");
   DeviceGuard dg(k->device);
   Timed tm(k, (hipStream_t)stream);
-  CV_HIP(cv::launch_prbg_plcm(k->d_chains, k->g.n, ks, (uint32_t)n, k->fast && !k->exact_division,
+  CV_HIP(cv::launch_prbg_plcm(k->d_chains, k->g.n, ks, (uint32_t)n, prbg_variant(k),
                               (hipStream_t)stream));
   tm.end(0, prbg_steps(k, n));
   k->frame_index += n;

@@ -35,11 +35,14 @@ struct PlcmChain {
   uint64_t nbytes;        // r * S_i bytes per frame
 };
 
+// Generator variants (identical bytes): IEEE division; reciprocal division
+// (valid only for chains that satisfy plcm_fast_ok); reciprocal division with
+// one lane per piece of Eq. (5).
+enum PrbgVariant : int { PRBG_EXACT = 0, PRBG_RECIP = 1, PRBG_RECIP_PAIR = 2 };
+
 // Generate n_frames frames of keystream for n_chains chains into ks_base.
-// `fast` selects the reciprocal division, valid only for chains that
-// satisfy plcm_fast_ok (identical bytes either way).
 hipError_t launch_prbg_plcm(const PlcmChain* d_chains, uint32_t n_chains, uint8_t* ks_base,
-                            uint32_t n_frames, bool fast, hipStream_t s);
+                            uint32_t n_frames, int variant, hipStream_t s);
 
 // Conditions under which the reciprocal division is exact for a whole orbit:
 // p >= 2^-64 and the current state x is 0 or >= 2^-800.

@@ -11,11 +11,13 @@
 // The chain is a strict serial recurrence, so the kernel is bound by the
 // latency of one step.  A workgroup is two wavefronts on different SIMDs:
 //  - the producer runs up to 32 chains, both maps of chain c in lanes 2c and
-//    2c+1 (a step costs the latency of one map), and only writes each
-//    iterate to an LDS ring -- one ds_write per step;
+//    2c+1 (a step costs the latency of one map), and only writes its
+//    iterates to an LDS ring, two steps per 16-byte write (every memory
+//    instruction costs the chain issue time, so they are kept few and wide);
 //  - the consumer turns a finished block of 32 steps into keystream bytes
-//    (pair XOR, packing, 16-byte stores) while the producer runs the next
-//    block.  One barrier per block hands the double-buffered ring over.
+//    (pair XOR, packing, 16-byte stores), the block split over all its
+//    lanes, while the producer runs the next block.  One barrier per block
+//    hands the double-buffered ring over.
 //
 // Every floating-point result equals the single correctly rounded IEEE-754
 // binary64 operation the map prescribes (round to nearest even; built with
@@ -34,6 +36,11 @@
 //    with p >= 2^-64 and every state 0 or >= 2^-800, and along any orbit
 //    from such a state every nonzero numerator stays >= 2^-800 (each step at
 //    least doubles the folded value, and y - p is a multiple of ulp(p)).
+// With the fast path, each map can also be given two lanes, one per piece of
+// Eq. (5): lane A always divides y by p, lane B always divides y-p by 1/2-p,
+// so neither selects its operands; a DPP swap then lets both lanes take the
+// candidate of the piece y actually falls in.  This shortens the dependent
+// chain of a step; 16 chains fit a wavefront.
 #include "cv_internal.h"
 
 namespace cv {
@@ -74,9 +81,38 @@ __device__ __forceinline__ double plcm_fast(double x, double p, double h, double
   return __builtin_fma(e, rcp, q);
 }
 
-template <bool kFast>
+// Value of the same 64-bit register in the adjacent lane (0<->1, 2<->3, ...),
+// DPP quad_perm(1,0,3,2); the partner lane is always active.
+__device__ __forceinline__ double swap_pair(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, 0xB1, 0xF, 0xF, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), 0xB1, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// One lane of a per-piece pair: `off`, `den`, `rcp` are this lane's piece
+// (lane A: 0, p, 1/p; lane B: p, 1/2-p, 1/(1/2-p)); `lane_b` says which.
+// Both lanes of the pair return the same next iterate.
+__device__ __forceinline__ double plcm_pair(double x, double p, double off, double den,
+                                            double rcp, bool lane_b) {
+  const double y = vmin(x, 1.0 - x);
+  const double num = y - off;  // exact 0 offset on lane A
+  double q = num * rcp;
+  double e = __builtin_fma(-den, q, num);
+  q = __builtin_fma(e, rcp, q);
+  e = __builtin_fma(-den, q, num);
+  q = __builtin_fma(e, rcp, q);
+  const double other = swap_pair(q);
+  const bool first = y < p;  // y in [0,p): first piece
+  return (first != lane_b) ? q : other;
+}
+
+// Division variants of the generator (identical bytes).
+enum : int { kExact = 0, kRecip = 1, kRecipPair = 2 };
+
+template <int kMode>
 __device__ __forceinline__ double plcm(double x, double p, double h, double ip, double ih) {
-  if constexpr (kFast) return plcm_fast(x, p, h, ip, ih);
+  if constexpr (kMode == kRecip) return plcm_fast(x, p, h, ip, ih);
   return plcm_exact(x, p, h);
 }
 
@@ -100,121 +136,161 @@ __device__ __forceinline__ ChainPlan plan(const PlcmChain& ch, uint32_t n_frames
   return c;
 }
 
-// Consumer: bytes of ring block `blk` for one chain.
-__device__ void emit_block(const double* ring, uint32_t lane, uint32_t blk, const ChainPlan& cp,
-                           uint8_t* base, uint64_t stride, uint32_t& f, uint32_t& sf,
-                           double* state) {
-  const uint32_t g0 = blk * kBlock;
-  if (g0 >= cp.total) return;
-  const double2* r2 = reinterpret_cast<const double2*>(ring);  // [step][chain] pairs
-  // state after the last step of the launch
-  const uint32_t last = cp.total - 1;
-  if (last >= g0 && last < g0 + kBlock) {
-    const double2 v = r2[(last - g0) * 32 + lane];
-    state[0] = v.x;
-    state[1] = v.y;
-  }
-  uint8_t* out = base + (uint64_t)f * stride;
-  if ((sf & 7u) == 0 && (uint64_t)(sf + kBlock) * 6 <= cp.nbytes &&
-      ((((uintptr_t)out) + (uint64_t)sf * 6) & 15u) == 0) {
-    uint4* o4 = reinterpret_cast<uint4*>(out + (uint64_t)sf * 6);
-#pragma unroll
-    for (int t = 0; t < kBlock / 8; t++) {
-      uint32_t w[12];
-#pragma unroll
-      for (int s = 0; s < 4; s++) {
-        const double2 a = r2[(t * 8 + 2 * s) * 32 + lane];
-        const double2 b = r2[(t * 8 + 2 * s + 1) * 32 + lane];
-        const uint64_t u = (uint64_t)__double_as_longlong(a.x) ^ (uint64_t)__double_as_longlong(a.y);
-        const uint64_t v = (uint64_t)__double_as_longlong(b.x) ^ (uint64_t)__double_as_longlong(b.y);
-        w[3 * s + 0] = (uint32_t)u;
-        w[3 * s + 1] = ((uint32_t)(u >> 32) & 0xFFFFu) | ((uint32_t)v << 16);
-        w[3 * s + 2] = ((uint32_t)v >> 16) | ((uint32_t)(v >> 32) << 16);
-      }
-      o4[3 * t + 0] = make_uint4(w[0], w[1], w[2], w[3]);
-      o4[3 * t + 1] = make_uint4(w[4], w[5], w[6], w[7]);
-      o4[3 * t + 2] = make_uint4(w[8], w[9], w[10], w[11]);
-    }
-    sf += kBlock;
-    if (sf == cp.spf) {
-      sf = 0;
-      f++;
-    }
-    return;
-  }
-  // general path: step by step, frame boundaries and partial last steps
-  for (uint32_t s = 0; s < (uint32_t)kBlock && g0 + s < cp.total; s++) {
-    const double2 a = r2[s * 32 + lane];
-    const uint64_t u = (uint64_t)__double_as_longlong(a.x) ^ (uint64_t)__double_as_longlong(a.y);
-    const uint64_t at = (uint64_t)sf * 6;
-    const uint64_t left = cp.nbytes - at;
-    const int take = left < 6 ? (int)left : 6;
-    uint8_t* o = base + (uint64_t)f * stride + at;
-    for (int k = 0; k < take; k++) o[k] = (uint8_t)(u >> (8 * k));
-    if (++sf == cp.spf) {
-      sf = 0;
-      f++;
-    }
+// Ring layout: per buffer kBlock/2 rows of 64 lanes, each slot 16 bytes
+// holding one producer lane's iterates of two consecutive steps.  Chain c's
+// map 1 lives in producer lane kLanes*c, map 2 in lane kLanes*c + kLanes/2.
+template <uint32_t kLanes>
+__device__ __forceinline__ uint64_t ring_xor(const double2* ring, uint32_t s, uint32_t c) {
+  const double2 a = ring[(s >> 1) * 64 + kLanes * c];
+  const double2 b = ring[(s >> 1) * 64 + kLanes * c + kLanes / 2];
+  const double x1 = (s & 1) ? a.y : a.x, x2 = (s & 1) ? b.y : b.x;
+  return (uint64_t)__double_as_longlong(x1) ^ (uint64_t)__double_as_longlong(x2);
+}
+
+// Per consumer lane: which frame and step-in-frame its next sub-block starts at.
+struct Cursor {
+  uint32_t f, sf;
+};
+
+__device__ __forceinline__ void advance(Cursor& cu, uint32_t steps, uint32_t spf) {
+  cu.sf += steps;
+  while (cu.sf >= spf) {
+    cu.sf -= spf;
+    cu.f++;
   }
 }
 
-template <bool kFast>
+// Consumer lane q (of kLanes per chain) of chain c: steps [q*kSub, (q+1)*kSub)
+// of ring block `blk` become keystream bytes.
+template <uint32_t kLanes>
+__device__ void emit_sub(const double2* ring, uint32_t c, uint32_t q, uint32_t blk,
+                         const ChainPlan& cp, uint8_t* base, uint64_t stride, Cursor& cu,
+                         double* state) {
+  constexpr uint32_t kSub = kBlock / kLanes;  // steps per consumer lane
+  const uint32_t s0 = q * kSub;
+  const uint32_t g0 = blk * kBlock + s0;     // global step of the sub-block start
+  if (g0 < cp.total) {
+    const uint32_t last = cp.total - 1;      // state after the launch's last step
+    if (last >= g0 && last < g0 + kSub) {
+      const uint32_t s = s0 + (last - g0);
+      const double2 a = ring[(s >> 1) * 64 + kLanes * c];
+      const double2 b = ring[(s >> 1) * 64 + kLanes * c + kLanes / 2];
+      state[0] = (s & 1) ? a.y : a.x;
+      state[1] = (s & 1) ? b.y : b.x;
+    }
+    uint8_t* out = base + (uint64_t)cu.f * stride + (uint64_t)cu.sf * 6;
+    if ((cu.sf & 7u) == 0 && (uint64_t)(cu.sf + kSub) * 6 <= cp.nbytes &&
+        (((uintptr_t)out) & 15u) == 0) {
+      uint4* o4 = reinterpret_cast<uint4*>(out);
+#pragma unroll
+      for (uint32_t t = 0; t < kSub / 8; t++) {
+        uint32_t w[12];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; u++) {
+          const uint64_t x = ring_xor<kLanes>(ring, s0 + 8 * t + 2 * u, c);
+          const uint64_t y = ring_xor<kLanes>(ring, s0 + 8 * t + 2 * u + 1, c);
+          w[3 * u + 0] = (uint32_t)x;
+          w[3 * u + 1] = ((uint32_t)(x >> 32) & 0xFFFFu) | ((uint32_t)y << 16);
+          w[3 * u + 2] = ((uint32_t)y >> 16) | ((uint32_t)(y >> 32) << 16);
+        }
+        o4[3 * t + 0] = make_uint4(w[0], w[1], w[2], w[3]);
+        o4[3 * t + 1] = make_uint4(w[4], w[5], w[6], w[7]);
+        o4[3 * t + 2] = make_uint4(w[8], w[9], w[10], w[11]);
+      }
+    } else {
+      // general path: step by step across frame ends and partial last steps
+      Cursor v = cu;
+      for (uint32_t s = 0; s < kSub && g0 + s < cp.total; s++) {
+        const uint64_t x = ring_xor<kLanes>(ring, s0 + s, c);
+        const uint64_t at = (uint64_t)v.sf * 6;
+        const uint64_t left = cp.nbytes - at;
+        const int take = left < 6 ? (int)left : 6;
+        uint8_t* o = base + (uint64_t)v.f * stride + at;
+        for (int k = 0; k < take; k++) o[k] = (uint8_t)(x >> (8 * k));
+        advance(v, 1, cp.spf);
+      }
+    }
+  }
+  advance(cu, kBlock, cp.spf);
+}
+
+template <int kMode>
 __global__ __launch_bounds__(128) void prbg_plcm_kernel(const PlcmChain* __restrict__ chains,
                                                          uint32_t n_chains, uint8_t* ks_base,
                                                          uint32_t n_frames) {
-  __shared__ double ring[2][kBlock * 64];  // [buf][step][lane]
+  // lanes per chain, in the producer and in the consumer: 2 (one per map) or
+  // 4 (per map, one per piece of Eq. 5)
+  constexpr uint32_t kLanes = kMode == kRecipPair ? 4 : 2;
+  constexpr uint32_t kChains = 64 / kLanes;
+  __shared__ double2 ring[2][(kBlock / 2) * 64];
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-  const uint32_t c0 = blockIdx.x * 32u;
-  const uint32_t nch = min(32u, n_chains - c0);
-
-  // chain of this lane: producer lane 2c+m -> chain c, map m; consumer lane c
-  const uint32_t my_c = wave == 0 ? (lane >> 1) : lane;
-  const bool has = my_c < nch;
+  const uint32_t c0 = blockIdx.x * kChains;
+  const uint32_t nch = min(kChains, n_chains - c0);
+  const uint32_t c = lane / kLanes;
+  const bool has = c < nch;
   PlcmChain ch{};
-  if (has) ch = chains[c0 + my_c];
+  if (has) ch = chains[c0 + c];
   const ChainPlan cp = plan(ch, n_frames);
-  const uint32_t total_max = wave_max(has ? cp.total : 0u);
+  const uint32_t total_max = wave_max(has ? cp.total : 0u);  // same in both wavefronts
   const uint32_t nblk = (total_max + kBlock - 1) / kBlock;
 
   if (wave == 0) {
-    const uint32_t m = lane & 1u;
+    const uint32_t m = (lane / (kLanes / 2)) & 1u;
     const double p = ch.p[m], h = ch.h[m], ip = ch.ip[m], ih = ch.ih[m];
     double x = has ? ch.state[m] : 0.0;
+    const bool lane_b = lane & 1u;
+    const double off = lane_b ? p : 0.0, den = lane_b ? h : p, rcp = lane_b ? ih : ip;
     for (uint32_t b = 0; b < nblk; b++) {
-      double* dst = &ring[b & 1u][lane];
+      double2* dst = &ring[b & 1u][lane];
 #pragma unroll
-      for (int s = 0; s < kBlock; s++) {
-        x = plcm<kFast>(x, p, h, ip, ih);
-        dst[s * 64] = x;
+      for (int s = 0; s < kBlock; s += 2) {
+        double x0;
+        if constexpr (kMode == kRecipPair) {
+          x0 = plcm_pair(x, p, off, den, rcp, lane_b);
+          x = plcm_pair(x0, p, off, den, rcp, lane_b);
+        } else {
+          x0 = plcm<kMode>(x, p, h, ip, ih);
+          x = plcm<kMode>(x0, p, h, ip, ih);
+        }
+        dst[(s / 2) * 64] = make_double2(x0, x);
       }
       __syncthreads();
     }
   } else {
-    uint32_t f = 0, sf = 0;
+    const uint32_t q = lane % kLanes;
+    Cursor cu{0, 0};
+    advance(cu, q * (kBlock / kLanes), cp.spf ? cp.spf : 1);
     uint8_t* base = ks_base + ch.out_off;
     for (uint32_t b = 0; b < nblk; b++) {
-      if (b > 0 && has) emit_block(ring[(b - 1) & 1u], lane, b - 1, cp, base, ch.frame_stride, f,
-                                   sf, ch.state);
+      if (b > 0 && has)
+        emit_sub<kLanes>(ring[(b - 1) & 1u], c, q, b - 1, cp, base, ch.frame_stride, cu,
+                         ch.state);
       __syncthreads();
     }
     if (nblk > 0 && has)
-      emit_block(ring[(nblk - 1) & 1u], lane, nblk - 1, cp, base, ch.frame_stride, f, sf,
-                 ch.state);
+      emit_sub<kLanes>(ring[(nblk - 1) & 1u], c, q, nblk - 1, cp, base, ch.frame_stride, cu,
+                       ch.state);
   }
 }
 
 }  // namespace
 
 hipError_t launch_prbg_plcm(const PlcmChain* d_chains, uint32_t n_chains, uint8_t* ks_base,
-                            uint32_t n_frames, bool fast, hipStream_t s) {
+                            uint32_t n_frames, int variant, hipStream_t s) {
   if (n_chains == 0 || n_frames == 0) return hipSuccess;
-  const uint32_t blocks = (n_chains + 31) / 32;
-  if (fast)
-    hipLaunchKernelGGL(prbg_plcm_kernel<true>, dim3(blocks), dim3(128), 0, s, d_chains, n_chains,
-                       ks_base, n_frames);
-  else
-    hipLaunchKernelGGL(prbg_plcm_kernel<false>, dim3(blocks), dim3(128), 0, s, d_chains, n_chains,
-                       ks_base, n_frames);
+  switch (variant) {
+    case PRBG_RECIP_PAIR:
+      hipLaunchKernelGGL(prbg_plcm_kernel<kRecipPair>, dim3((n_chains + 15) / 16), dim3(128), 0, s,
+                         d_chains, n_chains, ks_base, n_frames);
+      break;
+    case PRBG_RECIP:
+      hipLaunchKernelGGL(prbg_plcm_kernel<kRecip>, dim3((n_chains + 31) / 32), dim3(128), 0, s,
+                         d_chains, n_chains, ks_base, n_frames);
+      break;
+    default:
+      hipLaunchKernelGGL(prbg_plcm_kernel<kExact>, dim3((n_chains + 31) / 32), dim3(128), 0, s,
+                         d_chains, n_chains, ks_base, n_frames);
+  }
   return hipGetLastError();
 }
 

@@ -142,9 +142,9 @@ def test_state_continuation_and_checkpoint(B):
 
 
 @pytest.mark.parametrize("launch", [
-    dict(batch_frames=1), dict(batch_frames=2, threads=256, exact_division=1), dict(threads=64, tile_rows_enc=1,
+    dict(batch_frames=1), dict(batch_frames=2, threads=256, prbg_variant=1), dict(threads=64, tile_rows_enc=1,
                                                                   tile_rows_dec=1),
-    dict(threads=512, tile_rows_enc=3, tile_rows_dec=5), dict(threads=128, tile_rows_enc=7,
+    dict(threads=512, tile_rows_enc=3, tile_rows_dec=5, prbg_variant=2), dict(threads=128, tile_rows_enc=7,
                                                               tile_rows_dec=64),
 ])
 def test_launch_shapes_give_identical_bytes(B, launch):
@@ -203,24 +203,26 @@ def test_exact_division_path_and_tiny_keys(B):
     assert np.array_equal(_host(enc, frames.shape), want)
     pm2 = plcm_key(n, 32)
     ref = oracle.PlcmKey(H, W, C, n, r, pm2).keystream(T)
-    for exact in (0, 1):
+    for variant in (0, 1, 2, 3):
         k = B.Key(H, W, C, n, r, pm2)
-        k.set_launch(exact_division=exact)
+        k.set_launch(prbg_variant=variant)
         ks = torch.empty(T * r * H * W * C, dtype=torch.uint8, device="cuda:0")
         k.keystream(ks, T)
         assert np.array_equal(_host(ks, ref.shape), ref)
 
 
-def test_long_keystream(B):
+@pytest.mark.parametrize("variant", [2, 3])
+def test_long_keystream(B, variant):
     """About 26 million chain steps (52 million divisions) against the
-    oracle: the fast division over long chaotic orbits, 32 chains in one
-    wavefront, frames straddling ring blocks."""
+    oracle: the reciprocal division over long chaotic orbits, 32 chains (two
+    wavefronts in the per-piece variant), frames straddling ring blocks."""
     H, W, C, n, r, T = 1024, 1024, 3, 32, 5, 10
     pm = plcm_key(n, 4242)
-    print(f"[case] long keystream H={H} W={W} C={C} n={n} T={T}", flush=True)
+    print(f"[case] long keystream H={H} W={W} C={C} n={n} T={T} variant={variant}", flush=True)
     ref = oracle.PlcmKey(H, W, C, n, r, pm)
     want = ref.keystream(T)
     key = B.Key(H, W, C, n, r, pm)
+    key.set_launch(prbg_variant=variant)
     ks = torch.empty(T * r * H * W * C, dtype=torch.uint8, device="cuda:0")
     key.keystream(ks, T)
     got = _host(ks, want.shape)
