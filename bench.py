@@ -67,6 +67,8 @@ def main():
     ap.add_argument("--batch", type=int, default=48, help="frames per step (2 s of 24 FPS video)")
     ap.add_argument("--cpu-frames", type=int, default=120)
     ap.add_argument("--latency-frames", type=int, default=48)
+    ap.add_argument("--path", choices=["plain", "fused"], default="fused",
+                    help="round implementation: one launch per round, or all rounds fused")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -94,7 +96,9 @@ def main():
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
 
+    path = B.CV_PATH_FUSED if args.path == "fused" else B.CV_PATH_PLAIN
     key = B.Key(H, W, C, N_SUB, R, pm)
+    key.set_path(path)
     key.set_launch(batch_frames=batch)
     for i in range(warmup):
         sl = slice(i * batch, (i + 1) * batch)
@@ -120,6 +124,7 @@ def main():
     # plain per-frame path: one frame per call, synchronised, on a fresh key
     lat = []
     k2 = B.Key(H, W, C, N_SUB, R, pm)
+    k2.set_path(path)
     for t in range(args.latency_frames):
         t0 = time.perf_counter()
         k2.encrypt(src[t:t + 1], dst[t:t + 1], s_c[t:t + 1])
@@ -136,7 +141,16 @@ def main():
     prbg_flops = FLOPS_PER_STEP * prof["prbg_steps"] / max(1, prof["prbg_launches"])
     prbg_tflops = prbg_flops / (prbg_launch_ms * 1e-3) / 1e12
     round_launch_ms = prof["round_ms"] / max(1, prof["round_launches"])
-    round_bytes = 3 * F * prof["round_frames"] / max(1, prof["round_launches"])
+    if args.path == "fused":
+        # one launch runs all rounds: plaintext + cipher + r keystream slices per frame
+        round_bytes = (2 + R) * F * prof["round_frames"] / R / max(1, prof["round_launches"])
+        per_launch = f"{batch} frames x (2+r)F bytes (plaintext, cipher, keystream)"
+        round_kernel = "rounds_fused_kernel"
+    else:
+        # one launch per round: its input, output and keystream slice
+        round_bytes = 3 * F * prof["round_frames"] / max(1, prof["round_launches"])
+        per_launch = f"{batch} frames x 3F bytes (round input, output, keystream)"
+        round_kernel = "round_enc_pw_kernel"
     round_gbs = round_bytes / (round_launch_ms * 1e-3) / 1e9
     dominant_prbg = prof["prbg_ms"] >= prof["round_ms"]
     roof_prbg = {"bound": "alu", "achieved": prbg_tflops, "peak": FP64_PEAK_TFLOPS,
@@ -147,8 +161,8 @@ def main():
                  "ns_per_step": prof["prbg_ms"] * 1e6 / max(1, prof["prbg_steps"] / N_SUB)}
     roof_round = {"bound": "hbm", "achieved": round_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                   "frac": round_gbs / HBM_PEAK_GBS, "traffic": None,
-                  "kernel": "round_enc_kernel", "launch_ms": round_launch_ms,
-                  "per_launch": f"{batch} frames x 3F bytes (round input, output, keystream)"}
+                  "kernel": round_kernel, "launch_ms": round_launch_ms,
+                  "per_launch": per_launch}
     out = {
         "metric": METRIC,
         "value": fps,
@@ -164,7 +178,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"rgb768: {H}x{W}x{C} uint8 video, {N_SUB} subframes, {R} rounds, "
                                f"one PLCM key, {batch} frames per step",
-                   "frames": frames, "batch_frames": batch, "path": "plain"},
+                   "frames": frames, "batch_frames": batch, "path": args.path},
         "gb_per_s": fps * (2 + R) * F / 1e9,
         "pixels_per_s": fps * H * W,
         "latency_ms": {"plain_p50": pct(lat, 50), "plain_p99": pct(lat, 99),

@@ -65,7 +65,13 @@ typedef enum {
 /* Round implementation used by cv_encrypt_frames / cv_decrypt_frames.
  * Both give identical bytes. */
 typedef enum {
-  CV_PATH_PLAIN = 0 /* one kernel launch per round over the batch of frames */
+  CV_PATH_PLAIN = 0, /* one kernel launch per round over the batch of frames */
+  CV_PATH_FUSED = 1  /* all r rounds in one persistent launch per batch: groups of n
+                        workgroups (one per subframe) exchange bands through on-chip
+                        cached scratch with a group barrier per round (Algorithm 1's
+                        round loop on the device).  Needs the pixel-word conditions
+                        (C in {3,4}, W % 16 == 0, 16-byte aligned buffers); other
+                        geometries run the plain path. */
 } cv_path;
 
 /* Frame geometry: height H, width W, channels C (bytes per pixel), number of
@@ -89,6 +95,12 @@ typedef struct {
                                 for keys with p >= 2^-64 and states 0 or >= 2^-800),
                               3 as 2 with one lane per piece of the map.
                               2 and 3 fall back to 1 for keys outside that domain. */
+  uint32_t round_variant;  /* round kernels, all giving the same bytes: 0 auto, 1 byte
+                              kernels (any geometry), 2 pixel-word kernels (C in {3,4},
+                              W a multiple of 16, 16-byte aligned buffers; otherwise 1) */
+  uint32_t tile_rows_pw;   /* frame rows per LDS tile of the pixel-word kernels */
+  uint32_t fused_groups;   /* CV_PATH_FUSED: frame groups in flight (multiple of 8); 0 = as
+                              many as can be resident (reading back gives the value used) */
 } cv_launch;
 
 /* Version of the cipher readings above (CV_SPEC_VERSION). */

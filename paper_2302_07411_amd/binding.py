@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(PKG, "libchaosvid.so")
 CV_OK, CV_E_INVAL, CV_E_NOMEM, CV_E_HIP, CV_E_AGAIN, CV_E_STATE = range(6)
 CV_MAP_PLCM = 0
 CV_PATH_PLAIN = 0
+CV_PATH_FUSED = 1
 
 # every symbol include/chaosvid.h declares
 EXPORTS = (
@@ -35,7 +36,8 @@ class CvGeom(ct.Structure):
 class CvLaunch(ct.Structure):
     _fields_ = [("batch_frames", ct.c_uint32), ("threads", ct.c_uint32),
                 ("tile_rows_enc", ct.c_uint32), ("tile_rows_dec", ct.c_uint32),
-                ("prbg_variant", ct.c_uint32)]
+                ("prbg_variant", ct.c_uint32), ("round_variant", ct.c_uint32),
+                ("tile_rows_pw", ct.c_uint32), ("fused_groups", ct.c_uint32)]
 
 
 class CvProfile(ct.Structure):

@@ -30,6 +30,19 @@ struct cv_key {
   double* d_state = nullptr;   // 2n: x of map 1, map 2 per band
   bool fast = false;           // every chain qualifies for the reciprocal division
   uint32_t prbg_variant = 0;   // requested generator variant (cv_launch.prbg_variant)
+  uint32_t round_variant = 0;  // requested round kernels (cv_launch.round_variant)
+  uint32_t tile_pw = 0;        // rows per LDS tile of the pixel-word kernels
+  uint8_t* d_scratch2 = nullptr;  // second pixel-word scratch buffer
+  // fused path: per resident group two pixel-word frames, a barrier counter,
+  // and a timeout flag copied back to pinned memory after every launch
+  uint32_t fused_groups = 0;   // groups in flight (<= resident capacity)
+  uint32_t fused_cap = 0;      // resident capacity for the current launch shape
+  uint8_t* d_fscratch = nullptr;
+  uint32_t* d_counters = nullptr;
+  uint32_t* d_err = nullptr;
+  uint32_t* h_err = nullptr;
+  hipEvent_t err_copied = nullptr;
+  bool err_pending = false;
   cv::PlcmChain* d_chains = nullptr;
   // workspace, grown on demand
   uint32_t batch_frames = 0;
@@ -171,6 +184,17 @@ uint64_t prbg_steps(const cv_key* k, uint64_t frames) {
   return steps * frames;
 }
 
+// Largest pixel-word tile (rows) not above `want` that the kernels accept
+// with `threads` threads: every (row, run) pair of a gather gets a thread
+// (rows * ceil(W/H) <= threads) and the diffusion pass gives each thread 16
+// pixels (rows * W <= 16 * threads).
+uint32_t pw_tile_limit(const Geom& g, uint32_t threads, uint32_t want) {
+  const uint32_t M = (g.W + g.H - 1) / g.H;
+  uint32_t t = std::min(want, threads / M);
+  t = std::min<uint64_t>(t, (16ull * threads) / g.W);
+  return std::min(t, g.H);
+}
+
 size_t lds_limit(int device) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 64 * 1024;
@@ -185,6 +209,8 @@ bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
 void free_workspace(cv_key* k) {
   if (k->d_ks) (void)hipFree(k->d_ks);
   if (k->d_scratch) (void)hipFree(k->d_scratch);
+  if (k->d_scratch2) (void)hipFree(k->d_scratch2);
+  k->d_scratch2 = nullptr;
   if (k->d_gm) (void)hipFree(k->d_gm);
   if (k->h_gm) (void)hipHostFree(k->h_gm);
   k->d_ks = k->d_scratch = nullptr;
@@ -202,8 +228,10 @@ cv_status ensure_workspace(cv_key* k, size_t frames) {
   CV_HIP(hipDeviceSynchronize());  // older buffers may still be in use
   free_workspace(k);
   const Geom& g = k->g;
+  const uint64_t scratch = std::max<uint64_t>(k->F, (uint64_t)g.H * g.W * 4);
   if (hipMalloc(&k->d_ks, frames * (uint64_t)g.r * k->F) != hipSuccess ||
-      hipMalloc(&k->d_scratch, frames * k->F) != hipSuccess ||
+      hipMalloc(&k->d_scratch, frames * scratch) != hipSuccess ||
+      hipMalloc(&k->d_scratch2, frames * scratch) != hipSuccess ||
       hipMalloc(&k->d_gm, frames * (uint64_t)g.H * sizeof(uint32_t)) != hipSuccess ||
       hipHostMalloc(&k->h_gm, frames * (uint64_t)g.H * sizeof(uint32_t)) != hipSuccess) {
     (void)hipGetLastError();
@@ -242,8 +270,131 @@ cv::RoundArgs round_args(const cv_key* k, const uint8_t* ks, uint32_t T) {
 // r rounds over T frames (keystream already in `ks`).  Round outputs
 // alternate between `out` and the scratch buffer so that the last round
 // lands in `out` and no round reads the buffer it writes.
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+// A fused launch that timed out at a group barrier left its flag set; report
+// it on the first call after the copy of the flag has completed.
+cv_status check_async_errors(cv_key* k, bool wait) {
+  if (!k->err_pending) return CV_OK;
+  if (wait) {
+    CV_HIP(hipEventSynchronize(k->err_copied));
+  } else if (hipEventQuery(k->err_copied) != hipSuccess) {
+    (void)hipGetLastError();
+    return CV_OK;
+  }
+  k->err_pending = false;
+  if (*k->h_err) {
+    *k->h_err = 0;
+    return fail(CV_E_HIP,
+                "a fused launch timed out at a group barrier or found a group spread over "
+                "XCDs; its output is invalid");
+  }
+  return CV_OK;
+}
+
+// Resident capacity of the fused kernel for the key's shape, and the number of
+// groups to use (`want` rounded down to a multiple of 8, 0 = capacity).
+void set_fused_groups(cv_key* k, uint32_t want) {
+  const Geom& g = k->g;
+  k->fused_cap = 0;
+  if (k->tile_pw > 0 && (g.C == 3 || g.C == 4) && g.W % 16 == 0)
+    k->fused_cap = cv::rounds_fused_resident_groups(g, k->tile_pw, k->threads, k->device);
+  const uint32_t w = want / 8 * 8;
+  k->fused_groups = (w == 0 || w > k->fused_cap) ? k->fused_cap : w;
+}
+
+cv_status ensure_fused(cv_key* k) {
+  if (k->d_fscratch) return CV_OK;
+  const Geom& g = k->g;
+  const uint64_t pwf = (uint64_t)g.H * g.W * 4;
+  if (hipMalloc(&k->d_fscratch, (uint64_t)k->fused_groups * 2 * pwf) != hipSuccess ||
+      hipMalloc(&k->d_counters, 128ull * k->fused_groups) != hipSuccess) {
+    (void)hipGetLastError();
+    k->d_fscratch = nullptr;
+    return fail(CV_E_NOMEM, "fused-path workspace allocation failed");
+  }
+  if (!k->d_err) {
+    if (hipMalloc(&k->d_err, sizeof(uint32_t)) != hipSuccess ||
+        hipHostMalloc(&k->h_err, sizeof(uint32_t)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(CV_E_NOMEM, "fused-path workspace allocation failed");
+    }
+    *k->h_err = 0;
+    CV_HIP(hipMemset(k->d_err, 0, sizeof(uint32_t)));
+    CV_HIP(hipEventCreateWithFlags(&k->err_copied, hipEventDisableTiming));
+  }
+  return CV_OK;
+}
+
+cv_status run_rounds_fused(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
+                           const uint8_t* ks, uint32_t T, hipStream_t st) {
+  cv_status s = ensure_fused(k);
+  if (s != CV_OK) return s;
+  cv::RoundsFusedArgs a{};
+  a.in = in;
+  a.out = out;
+  a.ks = ks;
+  a.gm = k->d_gm;
+  a.scratch = k->d_fscratch;
+  a.counters = k->d_counters;
+  a.err = k->d_err;
+  a.g = k->g;
+  a.tile_rows = k->tile_pw;
+  a.n_frames = T;
+  a.groups = std::min<uint32_t>(k->fused_groups, ((T + 7) / 8) * 8);
+  a.spin_limit = 1u << 21;  // about two seconds of polling
+  a.decrypt = decrypt;
+  Timed tm(k, st);
+  CV_HIP(cv::launch_rounds_fused(a, k->threads, st));
+  tm.end(1, (uint64_t)T * k->g.r);
+  CV_HIP(hipMemcpyAsync(k->h_err, k->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  CV_HIP(hipEventRecord(k->err_copied, st));
+  k->err_pending = true;
+  return CV_OK;
+}
+
+// Pixel-word kernels apply: 3 or 4 channels, 16-byte rows and buffers.
+bool use_pw(const cv_key* k, const uint8_t* in, const uint8_t* out, const uint8_t* ks) {
+  if (k->round_variant == 1) return false;
+  const Geom& g = k->g;
+  return (g.C == 3 || g.C == 4) && g.W % 16 == 0 && aligned16(in) &&
+         aligned16(out) && aligned16(ks) && k->tile_pw > 0;
+}
+
+cv_status run_rounds_pw(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
+                        const uint8_t* ks, uint32_t T, hipStream_t st) {
+  const uint32_t r = k->g.r;
+  cv::RoundPwArgs a{};
+  a.ks = ks;
+  a.gm = k->d_gm;
+  a.g = k->g;
+  a.n_frames = T;
+  a.tile_rows = k->tile_pw;
+  a.decrypt = decrypt;
+  const uint8_t* cur = in;
+  for (uint32_t s = 0; s < r; s++) {
+    const bool last = s + 1 == r;
+    uint8_t* target = last ? out : (s % 2 == 0 ? k->d_scratch : k->d_scratch2);
+    a.src = cur;
+    a.dst = target;
+    a.src_packed = s == 0;
+    a.dst_packed = last;
+    a.j = decrypt ? r - 1 - s : s;
+    Timed tm(k, st);
+    CV_HIP(cv::launch_round_pw(a, k->threads, st));
+    tm.end(1, T);  // T frame-rounds
+    cur = target;
+  }
+  return CV_OK;
+}
+
 cv_status run_rounds(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out, const uint8_t* ks,
                      uint32_t T, hipStream_t st) {
+  if (use_pw(k, in, out, ks)) {
+    if (k->path == CV_PATH_FUSED && k->fused_groups > 0)
+      return run_rounds_fused(k, decrypt, in, out, ks, T, st);
+    return run_rounds_pw(k, decrypt, in, out, ks, T, st);
+  }
   const uint32_t r = k->g.r;
   cv::RoundArgs a = round_args(k, ks, T);
   const uint8_t* cur = in;
@@ -283,6 +434,7 @@ cv_status crypt_frames(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
                        const uint32_t* s_c, size_t n, void* stream) {
   cv_status s = check_frames_args(k, in, out, s_c, n);
   if (s != CV_OK || n == 0) return s;
+  if ((s = check_async_errors(k, false)) != CV_OK) return s;
   DeviceGuard dg(k->device);
   hipStream_t st = (hipStream_t)stream;
   const size_t B = std::min<size_t>(n, k->batch_frames);
@@ -355,6 +507,10 @@ cv_status cv_keysetup(const cv_geom* geom, cv_map map, const double* p_m, size_t
   k->lds_max = lds_max;
   k->tile_enc = std::min({rows_fit, max_band_rows, k->threads});
   k->tile_dec = std::min({rows_fit, g.H, k->threads});
+  uint32_t rows_pw = 0;
+  while (rows_pw < g.H && cv::round_pw_lds_bytes(g, rows_pw + 1) <= budget) rows_pw++;
+  k->tile_pw = pw_tile_limit(g, k->threads, rows_pw);
+  set_fused_groups(k, 0);
   // batches of frames: keystream + scratch within ~1 GiB
   const uint64_t per_frame = (uint64_t)(g.r + 1) * k->F;
   k->batch_frames = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(256, (1ull << 30) / per_frame));
@@ -407,6 +563,11 @@ void cv_key_free(cv_key* k) {
   (void)drain_spans(k);
   for (hipEvent_t e : k->event_pool) (void)hipEventDestroy(e);
   free_workspace(k);
+  if (k->d_fscratch) (void)hipFree(k->d_fscratch);
+  if (k->d_counters) (void)hipFree(k->d_counters);
+  if (k->d_err) (void)hipFree(k->d_err);
+  if (k->h_err) (void)hipHostFree(k->h_err);
+  if (k->err_copied) (void)hipEventDestroy(k->err_copied);
   if (k->d_state) (void)hipFree(k->d_state);
   if (k->d_chains) (void)hipFree(k->d_chains);
   if (k->gm_done) (void)hipEventDestroy(k->gm_done);
@@ -418,6 +579,8 @@ cv_status cv_key_get_state(const cv_key* k, double* x, size_t n_doubles, uint64_
   if (n_doubles != 2ull * k->g.n) return fail(CV_E_INVAL, "state holds 2 doubles per subframe");
   DeviceGuard dg(k->device);
   CV_HIP(hipDeviceSynchronize());
+  cv_status s = check_async_errors(const_cast<cv_key*>(k), true);
+  if (s != CV_OK) return s;
   CV_HIP(hipMemcpy(x, k->d_state, n_doubles * sizeof(double), hipMemcpyDeviceToHost));
   *frame_index = k->frame_index;
   return CV_OK;
@@ -441,7 +604,7 @@ cv_status cv_key_set_state(cv_key* k, const double* x, size_t n_doubles, uint64_
 
 cv_status cv_key_set_path(cv_key* k, int path) {
   if (!k) return fail(CV_E_INVAL, "key is NULL");
-  if (path != CV_PATH_PLAIN) return fail(CV_E_INVAL, "unknown path");
+  if (path != CV_PATH_PLAIN && path != CV_PATH_FUSED) return fail(CV_E_INVAL, "unknown path");
   k->path = path;
   return CV_OK;
 }
@@ -453,6 +616,9 @@ cv_status cv_key_get_launch(const cv_key* k, cv_launch* l) {
   l->tile_rows_enc = k->tile_enc;
   l->tile_rows_dec = k->tile_dec;
   l->prbg_variant = k->prbg_variant;
+  l->round_variant = k->round_variant;
+  l->tile_rows_pw = k->tile_pw;
+  l->fused_groups = k->fused_groups;
   return CV_OK;
 }
 
@@ -460,6 +626,12 @@ cv_status cv_key_set_launch(cv_key* k, const cv_launch* l) {
   if (!k || !l) return fail(CV_E_INVAL, "NULL argument");
   if (l->batch_frames == 0) return fail(CV_E_INVAL, "batch_frames must be >= 1");
   if (l->prbg_variant > 3) return fail(CV_E_INVAL, "prbg_variant must be 0..3");
+  if (l->round_variant > 2) return fail(CV_E_INVAL, "round_variant must be 0..2");
+  const uint32_t tp = pw_tile_limit(k->g, l->threads, l->tile_rows_pw);
+  if (tp == 0 && (k->g.C == 3 || k->g.C == 4))
+    return fail(CV_E_INVAL, "tile_rows_pw must be >= 1 (and the frame not too wide for threads)");
+  if (cv::round_pw_lds_bytes(k->g, tp) > k->lds_max)
+    return fail(CV_E_INVAL, "pixel-word tile does not fit in LDS");
   if (l->threads < 64 || l->threads > 1024 || l->threads % 64)
     return fail(CV_E_INVAL, "threads must be a multiple of 64 in 64..1024");
   const uint32_t te = std::min(l->tile_rows_enc, k->max_band_rows);
@@ -473,6 +645,17 @@ cv_status cv_key_set_launch(cv_key* k, const cv_launch* l) {
   k->tile_enc = te;
   k->tile_dec = td;
   k->prbg_variant = l->prbg_variant;
+  k->round_variant = l->round_variant;
+  k->tile_pw = tp;
+  // the fused workspace depends on the shape: drop it and size it anew
+  if (k->d_fscratch) {
+    CV_HIP(hipDeviceSynchronize());
+    (void)hipFree(k->d_fscratch);
+    (void)hipFree(k->d_counters);
+    k->d_fscratch = nullptr;
+    k->d_counters = nullptr;
+  }
+  set_fused_groups(k, l->fused_groups);
   return CV_OK;
 }
 
@@ -525,6 +708,7 @@ cv_status cv_apply_rounds(cv_key* k, int decrypt, const uint8_t* in, uint8_t* ou
   cv_status s = check_frames_args(k, in, out, s_c, n);
   if (s != CV_OK || n == 0) return s;
   if (!ks) return fail(CV_E_INVAL, "NULL keystream");
+  if ((s = check_async_errors(k, false)) != CV_OK) return s;
   const size_t ks_bytes = n * (uint64_t)k->g.r * k->F;
   if (ranges_overlap(ks, ks_bytes, in, n * k->F) || ranges_overlap(ks, ks_bytes, out, n * k->F))
     return fail(CV_E_INVAL, "keystream overlaps a frame buffer");

@@ -66,6 +66,46 @@ struct RoundArgs {
   uint32_t n_frames;
 };
 
+// Pixel-word rounds (C in {3,4}, W*C % 16 == 0, 16-byte aligned buffers):
+// intermediate frames hold one 32-bit word per pixel.
+struct RoundPwArgs {
+  const uint8_t* src;     // round input, frame 0 (packed HWC or pixel words)
+  uint8_t* dst;           // round output, frame 0 (packed HWC or pixel words)
+  const uint8_t* ks;      // keystream of frame 0 (packed, canonical layout)
+  const uint32_t* gm;     // per frame H entries: g(alpha) mod W
+  Geom g;
+  uint32_t j;
+  uint32_t tile_rows;
+  uint32_t n_frames;
+  bool decrypt, src_packed, dst_packed;
+};
+
+size_t round_pw_lds_bytes(const Geom& g, uint32_t tile_rows);
+hipError_t launch_round_pw(const RoundPwArgs& a, uint32_t threads, hipStream_t s);
+
+// All r rounds of a batch of frames in one persistent launch (pixel-word
+// layout conditions as above).  `scratch` holds two pixel-word frames per
+// group, `counters` 128 bytes per group, `err` one word (left nonzero if a
+// group barrier timed out or a group's workgroups ran on different XCDs).
+struct RoundsFusedArgs {
+  const uint8_t* in;
+  uint8_t* out;
+  const uint8_t* ks;
+  const uint32_t* gm;
+  uint8_t* scratch;
+  uint32_t* counters;
+  uint32_t* err;
+  Geom g;
+  uint32_t tile_rows, n_frames, groups, spin_limit;
+  bool decrypt;
+};
+
+hipError_t launch_rounds_fused(const RoundsFusedArgs& a, uint32_t threads, hipStream_t s);
+// Groups of n workgroups that can be resident at once (a multiple of 8; 0 if
+// not even one group per XCD fits).
+uint32_t rounds_fused_resident_groups(const Geom& g, uint32_t tile_rows, uint32_t threads,
+                                      int device);
+
 // LDS bytes a round kernel needs for a tile of `tile_rows` rows.
 size_t round_lds_bytes(const Geom& g, uint32_t tile_rows);
 hipError_t launch_round_enc(const RoundArgs& a, uint32_t threads, hipStream_t s);

@@ -282,3 +282,89 @@ def test_zero_frames_is_a_noop(B):
     empty = torch.empty(0, dtype=torch.uint8, device="cuda:0")
     key.encrypt(empty, empty, [])
     assert key.get_state()[1] == 0
+
+
+# Geometries the pixel-word kernels take (C in {3,4}, W % 16 == 0): wide,
+# tall, one band, bands split over several LDS tiles, 4 channels.
+PW_GEOMS = [
+    ("pw-rgb48", 48, 48, 3, 8, 5, 2),
+    ("pw-wide", 48, 64, 3, 5, 5, 2),
+    ("pw-tall", 80, 32, 3, 7, 5, 2),
+    ("pw-rgba", 33, 16, 4, 4, 3, 2),
+    ("pw-rgba-wide", 20, 48, 4, 3, 5, 2),
+    ("pw-oneband", 64, 48, 3, 1, 5, 2),
+    ("pw-rowbands", 12, 16, 3, 12, 2, 2),
+]
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("tile", [0, 1, 3])
+@pytest.mark.parametrize("geom", PW_GEOMS, ids=[g[0] for g in PW_GEOMS])
+def test_round_variants(B, geom, variant, tile):
+    """Byte kernels (1) and pixel-word kernels (2) against the oracle, with
+    the default and with tiny LDS tiles (a band over many tiles)."""
+    name, H, W, C, n, r, T = geom
+    pm, frames, s_c = _case(f"{name} round_variant={variant} tile={tile}", H, W, C, n, r, T,
+                            seed=9)
+    want = oracle.PlcmKey(H, W, C, n, r, pm).encrypt(frames, s_c)
+    launch = dict(round_variant=variant)
+    if tile:
+        launch.update(tile_rows_enc=tile, tile_rows_dec=tile, tile_rows_pw=tile)
+    src = _dev(frames)
+    enc, dec = torch.empty_like(src), torch.empty_like(src)
+    k = B.Key(H, W, C, n, r, pm)
+    k.set_launch(**launch)
+    k.encrypt(src, enc, s_c)
+    got = _host(enc, frames.shape)
+    assert np.array_equal(got, want), f"{np.count_nonzero(got != want)} bytes differ"
+    k2 = B.Key(H, W, C, n, r, pm)
+    k2.set_launch(**launch)
+    k2.decrypt(enc, dec, s_c)
+    assert np.array_equal(_host(dec, frames.shape), frames)
+
+
+@pytest.mark.parametrize("groups", [0, 8])
+@pytest.mark.parametrize("geom", PW_GEOMS, ids=[g[0] for g in PW_GEOMS])
+def test_fused_path(B, geom, groups):
+    """All r rounds in one persistent launch (groups of n workgroups with a
+    barrier per round): same bytes as the oracle.  With 8 groups and 20
+    frames every group walks several frames."""
+    name, H, W, C, n, r, _ = geom
+    T = 20
+    pm, frames, s_c = _case(f"{name} fused groups={groups}", H, W, C, n, r, T, seed=10)
+    want = oracle.PlcmKey(H, W, C, n, r, pm).encrypt(frames, s_c)
+    src = _dev(frames)
+    enc, dec = torch.empty_like(src), torch.empty_like(src)
+    k = B.Key(H, W, C, n, r, pm)
+    k.set_path(B.CV_PATH_FUSED)
+    k.set_launch(fused_groups=groups)
+    assert k.get_launch()["fused_groups"] > 0
+    k.encrypt(src, enc, s_c)
+    k.get_state()   # raises if a group barrier timed out or a group spanned XCDs
+    got = _host(enc, frames.shape)
+    assert np.array_equal(got, want), f"{np.count_nonzero(got != want)} bytes differ"
+    k2 = B.Key(H, W, C, n, r, pm)
+    k2.set_path(B.CV_PATH_FUSED)
+    k2.set_launch(fused_groups=groups)
+    k2.decrypt(enc, dec, s_c)
+    k2.get_state()
+    assert np.array_equal(_host(dec, frames.shape), frames)
+
+
+def test_fused_path_full_size(B):
+    H, W, C, n, r, T = 768, 768, 3, 16, 5, 6
+    pm = plcm_key(n, 2000 + H)
+    frames = CorrelatedVideo(H, W, C, 1000 + H).frames(0, T)
+    s_c = confusion_seeds(T, 2000 + H)
+    print("[case] fused rgb768", flush=True)
+    want = oracle.PlcmKey(H, W, C, n, r, pm).encrypt(frames, s_c)
+    src = _dev(frames)
+    enc, dec = torch.empty_like(src), torch.empty_like(src)
+    k = B.Key(H, W, C, n, r, pm)
+    k.set_path(B.CV_PATH_FUSED)
+    k.encrypt(src, enc, s_c)
+    assert np.array_equal(_host(enc, frames.shape), want)
+    k2 = B.Key(H, W, C, n, r, pm)
+    k2.set_path(B.CV_PATH_FUSED)
+    k2.decrypt(enc, dec, s_c)
+    assert torch.equal(dec, src)
