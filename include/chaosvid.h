@@ -204,6 +204,100 @@ cv_status cv_keystream_frames(cv_key *key, uint8_t *ks, size_t n_frames, void *s
 cv_status cv_apply_rounds(cv_key *key, int decrypt, const uint8_t *in, uint8_t *out,
                           const uint8_t *ks, const uint32_t *s_c, size_t n_frames, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Many streams per tick.  A batch object runs one tick of several video
+ * streams -- each with its own key, resolution and number of subframes --
+ * as one keystream launch over the band generators of all streams and one
+ * persistent rounds launch over all (stream, frame) jobs, instead of one
+ * pair of launches per stream.  This is Algorithm 1 (one master splitting
+ * every frame into subframes handled in parallel, Algorithm 2 per subframe)
+ * applied to many streams at once: a frame job is handled by a group of G
+ * workgroups on one XCD, band b by workgroup b mod G, with a group barrier
+ * between rounds (Sec. 2's round structure: every band of round j is
+ * diffused before any band of round j+1 is confused).
+ *
+ * The bytes written are identical to cv_encrypt_frames / cv_decrypt_frames
+ * on each item's key.  Items whose geometry or buffers do not meet the
+ * pixel-word conditions (C in {3,4}, W % 16 == 0, 16-byte aligned in/out)
+ * run on their key's own path within the same call, in stream order.
+ */
+typedef struct cv_batch cv_batch;
+
+/* One stream's share of a tick. */
+typedef struct {
+  cv_key *key;          /* the stream's key; advances by n_frames frames; at most once per tick */
+  const uint8_t *in;    /* device, n_frames*H*W*C bytes (HWC frames back to back) */
+  uint8_t *out;         /* device, same size; overlaps no other buffer of the tick */
+  const uint32_t *s_c;  /* host, n_frames confusion seeds, each >= 1 */
+  uint32_t n_frames;    /* 0 = the item is skipped */
+  int32_t decrypt;      /* 0: encrypt (Eq. 1 then Eq. 3 per round); 1: decrypt (Eq. 4 then Eq. 2) */
+} cv_batch_item;
+
+/* Launch shape of the batched rounds kernel; any shape gives the same bytes. */
+typedef struct {
+  uint32_t threads;     /* threads per workgroup: 256..1024, multiple of 64 */
+  uint32_t group_wgs;   /* G, workgroups per frame job: 1..64 */
+  uint32_t max_groups;  /* frame jobs in flight at once; 0 = as many as can be resident */
+  uint32_t use_graph;   /* 1: capture a tick in a HIP graph and replay it while the tick's
+                           structure (items' geometries, frame counts and launch sizes) is
+                           unchanged; 0: launch kernel by kernel */
+} cv_batch_shape;
+
+/* Counters of a batch object (host-side, no synchronisation). */
+typedef struct {
+  uint64_t ticks;               /* cv_batch_run calls that enqueued work */
+  uint64_t graph_captures;      /* ticks that captured a new graph */
+  uint64_t graph_replays;       /* ticks that replayed a captured graph */
+  uint32_t last_jobs;           /* frame jobs of the last tick on the batched kernels */
+  uint32_t last_groups;         /* groups in flight in the last tick's rounds launches */
+  uint32_t last_chains;         /* band generators of the last tick's keystream launches */
+  uint32_t last_fallback_items; /* items of the last tick that ran on their key's own path */
+} cv_batch_info;
+
+/* Create a batch object on HIP device `device` (the keys of its items must
+ * live there).  Default shape: 1024 threads, G = 16, resident capacity,
+ * graphs on.  Errors: CV_E_INVAL (NULL, no such device), CV_E_NOMEM. */
+cv_status cv_batch_create(int device, cv_batch **out);
+
+/* Release a batch object (synchronises its device).  NULL is ignored.  The
+ * keys of its items are not touched. */
+void cv_batch_free(cv_batch *batch);
+
+cv_status cv_batch_get_shape(const cv_batch *batch, cv_batch_shape *shape);
+
+/* CV_E_INVAL if threads or group_wgs is out of range or use_graph > 1. */
+cv_status cv_batch_set_shape(cv_batch *batch, const cv_batch_shape *shape);
+
+/* Encrypt or decrypt one tick: every item's n_frames frames, with keystream
+ * generation and r rounds (Algorithms 1-2), on `stream`.  The whole tick is
+ * checked before anything is enqueued: on error no key advances.  Errors:
+ * CV_E_INVAL (NULL pointers with n_frames > 0, a key twice, a key on
+ * another device, an s_c of 0, overlapping buffers), CV_E_NOMEM, CV_E_HIP
+ * (including a group barrier timeout of an earlier tick, which leaves that
+ * tick's output invalid and every later call on this batch failing).
+ * Calls on one batch are ordered with each other even across streams. */
+cv_status cv_batch_run(cv_batch *batch, const cv_batch_item *items, size_t n_items,
+                       void *stream);
+
+/* Wait for the batch's last tick and report its asynchronous errors. */
+cv_status cv_batch_sync(cv_batch *batch);
+
+cv_status cv_batch_get_info(const cv_batch *batch, cv_batch_info *info);
+
+/* Time the rounds kernel of the tick `items` describes for candidate shapes
+ * (threads 512 and 1024; G from 2 to 32) and keep the fastest.  Keys are not
+ * advanced and no keystream is generated: the out buffers of the items
+ * receive meaningless bytes.  `best` (may be NULL) receives the chosen shape.
+ * Same argument errors as cv_batch_run. */
+cv_status cv_batch_autotune(cv_batch *batch, const cv_batch_item *items, size_t n_items,
+                            void *stream, cv_batch_shape *best);
+
+/* Event timing of the batch's keystream and rounds launches while on (the
+ * totals use cv_profile's fields; round_frames counts frame-rounds).  With
+ * profiling on, ticks are launched kernel by kernel, not as graphs. */
+cv_status cv_batch_set_profiling(cv_batch *batch, int on);
+cv_status cv_batch_get_profile(cv_batch *batch, cv_profile *prof);
+
 #ifdef __cplusplus
 }
 #endif

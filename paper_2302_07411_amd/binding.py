@@ -24,7 +24,9 @@ EXPORTS = (
     "cv_spec_version", "cv_last_error", "cv_keysetup", "cv_key_free", "cv_key_get_state",
     "cv_key_set_state", "cv_key_set_path", "cv_encrypt_frames", "cv_decrypt_frames",
     "cv_keystream_frames", "cv_apply_rounds", "cv_key_get_launch", "cv_key_set_launch",
-    "cv_key_set_profiling", "cv_key_get_profile",
+    "cv_key_set_profiling", "cv_key_get_profile", "cv_batch_create", "cv_batch_free",
+    "cv_batch_get_shape", "cv_batch_set_shape", "cv_batch_run", "cv_batch_sync",
+    "cv_batch_get_info", "cv_batch_autotune", "cv_batch_set_profiling", "cv_batch_get_profile",
 )
 
 
@@ -44,6 +46,24 @@ class CvProfile(ct.Structure):
     _fields_ = [("prbg_ms", ct.c_double), ("prbg_launches", ct.c_uint64),
                 ("prbg_steps", ct.c_uint64), ("round_ms", ct.c_double),
                 ("round_launches", ct.c_uint64), ("round_frames", ct.c_uint64)]
+
+
+class CvBatchItem(ct.Structure):
+    _fields_ = [("key", ct.c_void_p), ("in_", ct.c_void_p), ("out", ct.c_void_p),
+                ("s_c", ct.POINTER(ct.c_uint32)), ("n_frames", ct.c_uint32),
+                ("decrypt", ct.c_int32)]
+
+
+class CvBatchShape(ct.Structure):
+    _fields_ = [("threads", ct.c_uint32), ("group_wgs", ct.c_uint32),
+                ("max_groups", ct.c_uint32), ("use_graph", ct.c_uint32)]
+
+
+class CvBatchInfo(ct.Structure):
+    _fields_ = [("ticks", ct.c_uint64), ("graph_captures", ct.c_uint64),
+                ("graph_replays", ct.c_uint64), ("last_jobs", ct.c_uint32),
+                ("last_groups", ct.c_uint32), ("last_chains", ct.c_uint32),
+                ("last_fallback_items", ct.c_uint32)]
 
 
 class CvError(RuntimeError):
@@ -96,6 +116,26 @@ def load() -> ct.CDLL:
     L.cv_keystream_frames.argtypes = [vp, u8p, sz, vp]
     L.cv_apply_rounds.restype = ct.c_int
     L.cv_apply_rounds.argtypes = [vp, ct.c_int, u8p, u8p, u8p, ct.POINTER(ct.c_uint32), sz, vp]
+    L.cv_batch_create.restype = ct.c_int
+    L.cv_batch_create.argtypes = [ct.c_int, ct.POINTER(vp)]
+    L.cv_batch_free.restype = None
+    L.cv_batch_free.argtypes = [vp]
+    L.cv_batch_get_shape.restype = ct.c_int
+    L.cv_batch_get_shape.argtypes = [vp, ct.POINTER(CvBatchShape)]
+    L.cv_batch_set_shape.restype = ct.c_int
+    L.cv_batch_set_shape.argtypes = [vp, ct.POINTER(CvBatchShape)]
+    L.cv_batch_run.restype = ct.c_int
+    L.cv_batch_run.argtypes = [vp, ct.POINTER(CvBatchItem), sz, vp]
+    L.cv_batch_sync.restype = ct.c_int
+    L.cv_batch_sync.argtypes = [vp]
+    L.cv_batch_get_info.restype = ct.c_int
+    L.cv_batch_get_info.argtypes = [vp, ct.POINTER(CvBatchInfo)]
+    L.cv_batch_autotune.restype = ct.c_int
+    L.cv_batch_autotune.argtypes = [vp, ct.POINTER(CvBatchItem), sz, vp, ct.POINTER(CvBatchShape)]
+    L.cv_batch_set_profiling.restype = ct.c_int
+    L.cv_batch_set_profiling.argtypes = [vp, ct.c_int]
+    L.cv_batch_get_profile.restype = ct.c_int
+    L.cv_batch_get_profile.argtypes = [vp, ct.POINTER(CvProfile)]
     _lib = L
     return L
 
@@ -222,4 +262,77 @@ class Key:
     def get_profile(self) -> dict:
         p = CvProfile()
         _check(load().cv_key_get_profile(self._h, ct.byref(p)))
+        return {f: getattr(p, f) for f, _ in CvProfile._fields_}
+
+
+class Batch:
+    """Many streams per tick (cv_batch_*).  An item is a tuple
+    (key, src, dst, s_c) or (key, src, dst, s_c, decrypt)."""
+
+    def __init__(self, device: int = 0):
+        h = ct.c_void_p()
+        _check(load().cv_batch_create(device, ct.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().cv_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _items(items):
+        arr = (CvBatchItem * max(1, len(items)))()
+        keep = []
+        for i, it in enumerate(items):
+            key, src, dst, s_c = it[:4]
+            dec = int(bool(it[4])) if len(it) > 4 else 0
+            n = key._nframes(src)
+            if dst.numel() != src.numel():
+                raise ValueError("dst size differs from src")
+            seeds, p = _seeds(s_c, n)
+            keep.append(seeds)
+            arr[i] = CvBatchItem(key._h.value, _ptr(src) if n else None, _ptr(dst) if n else None,
+                                 p, n, dec)
+        return arr, keep
+
+    def run(self, items, stream=None):
+        arr, keep = self._items(items)
+        _check(load().cv_batch_run(self._h, arr, len(items), _stream(stream)))
+
+    def sync(self):
+        _check(load().cv_batch_sync(self._h))
+
+    def autotune(self, items, stream=None) -> dict:
+        arr, keep = self._items(items)
+        best = CvBatchShape()
+        _check(load().cv_batch_autotune(self._h, arr, len(items), _stream(stream), ct.byref(best)))
+        return {f: getattr(best, f) for f, _ in CvBatchShape._fields_}
+
+    def get_shape(self) -> dict:
+        s = CvBatchShape()
+        _check(load().cv_batch_get_shape(self._h, ct.byref(s)))
+        return {f: getattr(s, f) for f, _ in CvBatchShape._fields_}
+
+    def set_shape(self, **kw):
+        cur = self.get_shape()
+        cur.update(kw)
+        _check(load().cv_batch_set_shape(self._h, ct.byref(CvBatchShape(**cur))))
+
+    def info(self) -> dict:
+        i = CvBatchInfo()
+        _check(load().cv_batch_get_info(self._h, ct.byref(i)))
+        return {f: getattr(i, f) for f, _ in CvBatchInfo._fields_}
+
+    def set_profiling(self, on: bool):
+        _check(load().cv_batch_set_profiling(self._h, int(bool(on))))
+
+    def get_profile(self) -> dict:
+        p = CvProfile()
+        _check(load().cv_batch_get_profile(self._h, ct.byref(p)))
         return {f: getattr(p, f) for f, _ in CvProfile._fields_}

@@ -14,63 +14,11 @@
 #include <string>
 #include <vector>
 
-#include "chaosvid.h"
-#include "cv_internal.h"
+#include "runtime.h"
 
-using cv::Geom;
 
-struct cv_key {
-  Geom g{};
-  cv_map map = CV_MAP_PLCM;
-  int device = 0;
-  int path = CV_PATH_PLAIN;
-  uint64_t F = 0;              // bytes per frame
-  uint64_t frame_index = 0;    // frames processed so far
-  std::vector<double> pm;      // the n key records as given
-  double* d_state = nullptr;   // 2n: x of map 1, map 2 per band
-  bool fast = false;           // every chain qualifies for the reciprocal division
-  uint32_t prbg_variant = 0;   // requested generator variant (cv_launch.prbg_variant)
-  uint32_t round_variant = 0;  // requested round kernels (cv_launch.round_variant)
-  uint32_t tile_pw = 0;        // rows per LDS tile of the pixel-word kernels
-  uint8_t* d_scratch2 = nullptr;  // second pixel-word scratch buffer
-  // fused path: per resident group two pixel-word frames, a barrier counter,
-  // and a timeout flag copied back to pinned memory after every launch
-  uint32_t fused_groups = 0;   // groups in flight (<= resident capacity)
-  uint32_t fused_cap = 0;      // resident capacity for the current launch shape
-  uint8_t* d_fscratch = nullptr;
-  uint32_t* d_counters = nullptr;
-  uint32_t* d_err = nullptr;
-  uint32_t* h_err = nullptr;
-  hipEvent_t err_copied = nullptr;
-  bool err_pending = false;
-  cv::PlcmChain* d_chains = nullptr;
-  // workspace, grown on demand
-  uint32_t batch_frames = 0;
-  uint8_t* d_ks = nullptr;
-  uint8_t* d_scratch = nullptr;
-  uint32_t* d_gm = nullptr;
-  uint32_t* h_gm = nullptr;    // pinned staging of the shift tables
-  size_t ws_frames = 0;
-  hipEvent_t gm_done = nullptr;
-  bool gm_pending = false;
-  // launch shape
-  uint32_t threads = 1024;
-  uint32_t tile_enc = 0, tile_dec = 0;
-  uint32_t max_band_rows = 0;
-  size_t lds_max = 0;
-  // event profiling
-  bool profiling = false;
-  struct Span {
-    hipEvent_t a, b;
-    int kind;  // 0 = prbg, 1 = round
-    uint64_t work;
-  };
-  std::vector<Span> spans;
-  std::vector<hipEvent_t> event_pool;
-  cv_profile prof{};
-};
-
-namespace {
+namespace cv {
+namespace rt {
 
 thread_local std::string g_last_error;
 
@@ -83,24 +31,7 @@ cv_status hip_fail(hipError_t e, const char* what) {
   return fail(CV_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define CV_HIP(call)                                     \
-  do {                                                   \
-    hipError_t e_ = (call);                              \
-    if (e_ != hipSuccess) return hip_fail(e_, #call);    \
-  } while (0)
 
-// Switch to the key's device for the lifetime of a call.
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
 
 // Sec. 2, Eq. (1): g(alpha) = floor(s_c * sin((2*pi*alpha)/H)), binary64,
 // left to right, reduced mod W for the kernels (beta = (o + g) mod W).
@@ -193,6 +124,13 @@ uint32_t pw_tile_limit(const Geom& g, uint32_t threads, uint32_t want) {
   uint32_t t = std::min(want, threads / M);
   t = std::min<uint64_t>(t, (16ull * threads) / g.W);
   return std::min(t, g.H);
+}
+
+uint32_t pw_tile_rows(const Geom& g, uint32_t threads, size_t lds_max) {
+  const size_t budget = std::min<size_t>(lds_max, 64 * 1024);
+  uint32_t rows = 0;
+  while (rows < g.H && cv::round_pw_lds_bytes(g, rows + 1) <= budget) rows++;
+  return pw_tile_limit(g, threads, rows);
 }
 
 size_t lds_limit(int device) {
@@ -454,7 +392,10 @@ cv_status crypt_frames(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
 
 bool finite_in(double v, double lo, double hi) { return isfinite(v) && v > lo && v < hi; }
 
-}  // namespace
+}  // namespace rt
+}  // namespace cv
+
+using namespace cv::rt;
 
 extern "C" {
 
@@ -507,9 +448,7 @@ cv_status cv_keysetup(const cv_geom* geom, cv_map map, const double* p_m, size_t
   k->lds_max = lds_max;
   k->tile_enc = std::min({rows_fit, max_band_rows, k->threads});
   k->tile_dec = std::min({rows_fit, g.H, k->threads});
-  uint32_t rows_pw = 0;
-  while (rows_pw < g.H && cv::round_pw_lds_bytes(g, rows_pw + 1) <= budget) rows_pw++;
-  k->tile_pw = pw_tile_limit(g, k->threads, rows_pw);
+  k->tile_pw = pw_tile_rows(g, k->threads, lds_max);
   set_fused_groups(k, 0);
   // batches of frames: keystream + scratch within ~1 GiB
   const uint64_t per_frame = (uint64_t)(g.r + 1) * k->F;
@@ -548,6 +487,7 @@ cv_status cv_keysetup(const cv_geom* geom, cv_map map, const double* p_m, size_t
     e = hipMemcpy(k->d_chains, chains.data(), chains.size() * sizeof(cv::PlcmChain),
                   hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&k->gm_done, hipEventDisableTiming);
+  k->h_chains = chains;
   if (e != hipSuccess) {
     cv_key_free(k);
     return hip_fail(e, "cv_keysetup");

@@ -1,0 +1,784 @@
+// Host side of multi-stream batches (declarations and contract in
+// include/chaosvid.h): one tick of many video streams as one keystream
+// launch per generator variant and one persistent rounds launch per channel
+// count, with every table the tick needs sent to the device in one copy.
+//
+// A tick is planned on the host:
+//  - chains: every band generator of every item (Sec. 3, Eq. 5), with its
+//    output placed in one keystream workspace shared by the tick; chains are
+//    sorted by length so that a wavefront holds chains of similar length;
+//  - jobs: one per (item, frame), assigned to groups of G workgroups longest
+//    first, each to the group with the least work so far;
+//  - shift tables of Eq. (1), one per frame.
+// The tables are written into a pinned staging buffer (two, used in turn so
+// that the host can plan tick t+1 while tick t runs) and copied to the device
+// with one copy.  When the tick's structure repeats, the whole sequence --
+// copy, keystream launches, rounds launches, error-flag read-back -- is
+// replayed from a HIP graph captured the first time.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <array>
+#include <string>
+#include <vector>
+
+#include "runtime.h"
+
+using namespace cv::rt;
+
+namespace {
+
+constexpr uint32_t kSpinLimit = 1u << 21;  // about two seconds of polling per barrier
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Everything that the launches of a tick take as arguments; two ticks with
+// equal signatures enqueue the same work on different table contents.
+struct Signature {
+  size_t blob_bytes = 0;
+  uint8_t* d_blob = nullptr;
+  uint8_t* d_ks = nullptr;
+  uint8_t* d_scratch = nullptr;
+  uint32_t* d_counters = nullptr;
+  uint32_t n_chains[3] = {0, 0, 0};
+  size_t chain_off[3] = {0, 0, 0};
+  uint32_t groups[2] = {0, 0};  // C = 3, C = 4
+  uint32_t G = 0, threads = 0;
+  size_t lds[2] = {0, 0};
+  size_t job_off[2] = {0, 0}, gj_off[2] = {0, 0}, go_off[2] = {0, 0};
+  uint64_t scratch_stride = 0;
+  bool operator==(const Signature& o) const {
+    bool eq = blob_bytes == o.blob_bytes && d_blob == o.d_blob && d_ks == o.d_ks &&
+              d_scratch == o.d_scratch && d_counters == o.d_counters && G == o.G &&
+              threads == o.threads && scratch_stride == o.scratch_stride;
+    for (int v = 0; v < 3; v++) eq = eq && n_chains[v] == o.n_chains[v] && chain_off[v] == o.chain_off[v];
+    for (int c = 0; c < 2; c++)
+      eq = eq && groups[c] == o.groups[c] && lds[c] == o.lds[c] && job_off[c] == o.job_off[c] &&
+           gj_off[c] == o.gj_off[c] && go_off[c] == o.go_off[c];
+    return eq;
+  }
+};
+
+// One pinned staging buffer with the graph that copies from it.
+struct Slot {
+  uint8_t* h_blob = nullptr;
+  size_t cap = 0;
+  hipEvent_t copied = nullptr;  // the tick that read h_blob has copied it
+  bool pending = false;
+  hipGraphExec_t exec = nullptr;
+  Signature sig;
+  bool has_sig = false;
+};
+
+struct Span {
+  hipEvent_t a, b;
+  int kind;  // 0 = keystream, 1 = rounds
+  uint64_t work;
+};
+
+}  // namespace
+
+struct cv_batch {
+  int device = 0;
+  cv_batch_shape shape{1024, 16, 0, 1};
+  size_t lds_max = 0;
+  hipStream_t cap = nullptr;  // private stream that graphs are captured on
+  std::array<Slot, 2> slot;
+  uint32_t turn = 0;
+  uint8_t* d_blob = nullptr;
+  size_t blob_cap = 0;
+  uint8_t* d_ks = nullptr;
+  size_t ks_cap = 0;
+  uint8_t* d_scratch = nullptr;
+  size_t scratch_cap = 0;
+  uint32_t* d_counters = nullptr;
+  size_t counters_cap = 0;  // groups
+  uint32_t* d_err = nullptr;
+  uint32_t* h_err = nullptr;  // pinned copy of d_err, written at the end of every tick
+  bool failed = false;        // a tick timed out: d_err stays set
+  hipEvent_t done = nullptr;  // end of the last tick
+  hipStream_t last_stream = nullptr;
+  bool ran = false;
+  cv_batch_info info{};
+  bool profiling = false;
+  std::vector<Span> spans;
+  std::vector<hipEvent_t> event_pool;
+  cv_profile prof{};
+};
+
+namespace {
+
+// ------------------------------------------------------------ the plan ---
+struct Plan {
+  std::vector<cv::PlcmChain> chains[3];  // by generator variant
+  std::vector<cv::BatchJob> jobs[2];     // by C (3, 4)
+  std::vector<uint32_t> group_jobs[2], group_off[2];
+  std::vector<uint64_t> gm_off;          // per eligible item: offset of its tables in gm
+  std::vector<uint32_t> gm;              // shift tables of every frame
+  std::vector<size_t> fallback;          // items on their key's own path
+  std::vector<size_t> eligible;
+  std::vector<uint64_t> ks_off;          // per eligible item
+  uint64_t ks_bytes = 0, scratch_stride = 0;
+  uint32_t groups[2] = {0, 0};
+  size_t lds[2] = {0, 0};
+  uint64_t steps = 0, frame_rounds = 0;
+};
+
+cv_status check_items(const cv_batch* b, const cv_batch_item* items, size_t n_items) {
+  if (n_items && !items) return fail(CV_E_INVAL, "items is NULL");
+  struct Range {
+    uintptr_t lo, hi;
+    bool out;
+  };
+  std::vector<Range> ranges;
+  std::vector<const cv_key*> keys;
+  for (size_t i = 0; i < n_items; i++) {
+    const cv_batch_item& it = items[i];
+    if (!it.key) return fail(CV_E_INVAL, "item key is NULL");
+    if (it.n_frames == 0) continue;
+    if (it.key->device != b->device) return fail(CV_E_INVAL, "item key lives on another device");
+    if (it.decrypt != 0 && it.decrypt != 1) return fail(CV_E_INVAL, "item decrypt must be 0 or 1");
+    cv_status s = check_frames_args(it.key, it.in, it.out, it.s_c, it.n_frames);
+    if (s != CV_OK) return s;
+    // one keystream launch covers the item's frames: a chain's steps must fit 31 bits
+    for (const cv::PlcmChain& c : it.key->h_chains)
+      if ((c.nbytes + 5) / 6 * (uint64_t)it.n_frames >= (1ull << 31))
+        return fail(CV_E_INVAL, "too many frames of one stream in one tick");
+    const uint64_t bytes = (uint64_t)it.n_frames * it.key->F;
+    ranges.push_back({(uintptr_t)it.in, (uintptr_t)it.in + bytes, false});
+    ranges.push_back({(uintptr_t)it.out, (uintptr_t)it.out + bytes, true});
+    keys.push_back(it.key);
+  }
+  std::sort(keys.begin(), keys.end());
+  if (std::adjacent_find(keys.begin(), keys.end()) != keys.end())
+    return fail(CV_E_INVAL, "a key appears in more than one item of the tick");
+  // an output may overlap nothing; inputs may overlap each other
+  std::sort(ranges.begin(), ranges.end(), [](const Range& x, const Range& y) { return x.lo < y.lo; });
+  uintptr_t end_all = 0, end_out = 0;
+  for (const Range& r : ranges) {
+    if ((r.out && r.lo < end_all) || (!r.out && r.lo < end_out))
+      return fail(CV_E_INVAL, "an output buffer overlaps another buffer of the tick");
+    end_all = std::max(end_all, r.hi);
+    if (r.out) end_out = std::max(end_out, r.hi);
+  }
+  return CV_OK;
+}
+
+bool batch_eligible(const cv_batch* b, const cv_batch_item& it) {
+  const Geom& g = it.key->g;
+  if (!((g.C == 3 || g.C == 4) && g.W % 16 == 0 && aligned16(it.in) && aligned16(it.out)))
+    return false;
+  const uint32_t t = pw_tile_rows(g, b->shape.threads, b->lds_max);
+  return t > 0 && cv::round_pw_lds_bytes(g, t) <= b->lds_max;
+}
+
+// Work of one job on the critical path of its group: r rounds, each
+// ceil(n/G) bands of at most max_band_rows rows per workgroup.
+uint64_t job_cost(const cv_key* k, uint32_t G) {
+  return (uint64_t)k->g.r * ((k->g.n + G - 1) / G) * k->max_band_rows * k->g.W;
+}
+
+// Build every table of the tick except device addresses that depend on the
+// workspace (filled in by fill_blob).  `rounds_only` skips the generators.
+cv_status make_plan(cv_batch* b, const cv_batch_item* items, size_t n_items, bool rounds_only,
+                    Plan& P) {
+  const uint32_t G = b->shape.group_wgs, threads = b->shape.threads;
+  uint64_t ks = 0, gm = 0, pwf_max = 0;
+  for (size_t i = 0; i < n_items; i++) {
+    const cv_batch_item& it = items[i];
+    if (it.n_frames == 0) continue;
+    if (!batch_eligible(b, it)) {
+      P.fallback.push_back(i);
+      continue;
+    }
+    const cv_key* k = it.key;
+    P.eligible.push_back(i);
+    P.ks_off.push_back(ks);
+    P.gm_off.push_back(gm);
+    ks += (uint64_t)it.n_frames * k->g.r * k->F;
+    gm += (uint64_t)it.n_frames * k->g.H;
+    pwf_max = std::max<uint64_t>(pwf_max, (uint64_t)k->g.H * k->g.W * 4);
+  }
+  P.ks_bytes = ks;
+  P.scratch_stride = align_up(pwf_max, 256);
+  P.gm.resize(gm);
+  for (size_t e = 0; e < P.eligible.size(); e++) {
+    const cv_batch_item& it = items[P.eligible[e]];
+    const cv_key* k = it.key;
+    const Geom& g = k->g;
+    for (uint32_t t = 0; t < it.n_frames; t++)
+      shift_table(g.H, g.W, it.s_c[t], P.gm.data() + P.gm_off[e] + (uint64_t)t * g.H);
+    if (!rounds_only) {
+      const int v = prbg_variant(k);
+      for (const cv::PlcmChain& c0 : k->h_chains) {
+        cv::PlcmChain c = c0;
+        c.out_off = P.ks_off[e] + c0.out_off;
+        c.frames = it.n_frames;
+        P.chains[v].push_back(c);
+      }
+      P.steps += prbg_steps(k, it.n_frames);
+    }
+    P.frame_rounds += (uint64_t)it.n_frames * g.r;
+  }
+  for (auto& cs : P.chains)
+    std::stable_sort(cs.begin(), cs.end(), [](const cv::PlcmChain& x, const cv::PlcmChain& y) {
+      return x.nbytes * x.frames > y.nbytes * y.frames;
+    });
+  // jobs per channel count, longest first onto the least loaded group
+  for (int ci = 0; ci < 2; ci++) {
+    const uint32_t C = 3 + ci;
+    std::vector<std::pair<uint64_t, uint32_t>> order;  // (cost, job)
+    size_t lds = 0;
+    for (size_t e = 0; e < P.eligible.size(); e++) {
+      const cv_batch_item& it = items[P.eligible[e]];
+      const cv_key* k = it.key;
+      if (k->g.C != C) continue;
+      const uint32_t tile = pw_tile_rows(k->g, threads, b->lds_max);
+      lds = std::max(lds, cv::round_pw_lds_bytes(k->g, tile));
+      for (uint32_t t = 0; t < it.n_frames; t++) {
+        cv::BatchJob J{};
+        J.in = it.in + (uint64_t)t * k->F;
+        J.out = it.out + (uint64_t)t * k->F;
+        J.in_last = it.in + (uint64_t)it.n_frames * k->F - 4;
+        // device addresses of ks and gm are offsets until finish_plan
+        J.ks = (const uint8_t*)(uintptr_t)(P.ks_off[e] + (uint64_t)t * k->g.r * k->F);
+        J.gm = (const uint32_t*)(uintptr_t)((P.gm_off[e] + (uint64_t)t * k->g.H) * 4);
+        J.g = k->g;
+        J.decrypt = (uint32_t)it.decrypt;
+        J.tile_rows = tile;
+        order.push_back({job_cost(k, G), (uint32_t)P.jobs[ci].size()});
+        P.jobs[ci].push_back(J);
+      }
+    }
+    if (P.jobs[ci].empty()) continue;
+    const uint32_t cap = cv::batch_resident_groups(C, G, threads, lds, b->device);
+    if (cap == 0) return fail(CV_E_INVAL, "batch launch shape does not fit on the device");
+    uint32_t groups = std::min<uint64_t>(cap, P.jobs[ci].size());
+    if (b->shape.max_groups) groups = std::min(groups, b->shape.max_groups);
+    std::stable_sort(order.begin(), order.end(),
+                     [](const auto& x, const auto& y) { return x.first > y.first; });
+    std::vector<std::vector<uint32_t>> per(groups);
+    std::vector<std::pair<uint64_t, uint32_t>> heap;  // (load, group), min-heap
+    for (uint32_t q = 0; q < groups; q++) heap.push_back({0, q});
+    auto later = [](const auto& x, const auto& y) { return x > y; };
+    for (const auto& o : order) {
+      std::pop_heap(heap.begin(), heap.end(), later);
+      heap.back().first += o.first;
+      per[heap.back().second].push_back(o.second);
+      std::push_heap(heap.begin(), heap.end(), later);
+    }
+    P.group_off[ci].push_back(0);
+    for (auto& v : per) {
+      P.group_jobs[ci].insert(P.group_jobs[ci].end(), v.begin(), v.end());
+      P.group_off[ci].push_back((uint32_t)P.group_jobs[ci].size());
+    }
+    P.groups[ci] = groups;
+    P.lds[ci] = lds;
+  }
+  return CV_OK;
+}
+
+// --------------------------------------------------------- workspace ---
+cv_status grow(uint8_t** p, size_t* cap, size_t want, const char* what) {
+  if (want <= *cap) return CV_OK;
+  CV_HIP(hipDeviceSynchronize());  // the old buffer may still be in use
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  *cap = 0;
+  const size_t sz = align_up(want + want / 4, 1 << 20);
+  if (hipMalloc(p, sz) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(CV_E_NOMEM, std::string(what) + " allocation failed");
+  }
+  *cap = sz;
+  return CV_OK;
+}
+
+void drop_graphs(cv_batch* b) {
+  for (Slot& s : b->slot) {
+    if (s.exec) (void)hipGraphExecDestroy(s.exec);
+    s.exec = nullptr;
+    s.has_sig = false;
+  }
+}
+
+// Layout of the blob: chains (3 variants), jobs, group tables, shift tables.
+struct Layout {
+  size_t chain_off[3], job_off[2], gj_off[2], go_off[2], gm_off, bytes;
+};
+
+Layout layout(const Plan& P) {
+  Layout L{};
+  size_t o = 0;
+  for (int v = 0; v < 3; v++) {
+    L.chain_off[v] = o;
+    o = align_up(o + P.chains[v].size() * sizeof(cv::PlcmChain), 16);
+  }
+  for (int c = 0; c < 2; c++) {
+    L.job_off[c] = o;
+    o = align_up(o + P.jobs[c].size() * sizeof(cv::BatchJob), 16);
+    L.gj_off[c] = o;
+    o = align_up(o + P.group_jobs[c].size() * 4, 16);
+    L.go_off[c] = o;
+    o = align_up(o + P.group_off[c].size() * 4, 16);
+  }
+  L.gm_off = o;
+  L.bytes = align_up(o + P.gm.size() * 4, 256);
+  return L;
+}
+
+cv_status ensure_pinned(Slot& s, size_t bytes) {
+  if (bytes <= s.cap) return CV_OK;
+  if (s.pending) {
+    CV_HIP(hipEventSynchronize(s.copied));
+    s.pending = false;
+  }
+  if (s.h_blob) (void)hipHostFree(s.h_blob);
+  s.h_blob = nullptr;
+  s.cap = 0;
+  const size_t sz = align_up(bytes + bytes / 4, 1 << 16);
+  if (hipHostMalloc(&s.h_blob, sz) != hipSuccess) {
+    (void)hipGetLastError();
+    s.h_blob = nullptr;
+    return fail(CV_E_NOMEM, "pinned staging allocation failed");
+  }
+  s.cap = sz;
+  if (s.exec) (void)hipGraphExecDestroy(s.exec);  // it copies from the old buffer
+  s.exec = nullptr;
+  s.has_sig = false;
+  return CV_OK;
+}
+
+// Write the tables into the slot's staging buffer with device addresses.
+void fill_blob(const cv_batch* b, const Plan& P, const Layout& L, uint8_t* h) {
+  for (int v = 0; v < 3; v++)
+    if (!P.chains[v].empty())
+      memcpy(h + L.chain_off[v], P.chains[v].data(), P.chains[v].size() * sizeof(cv::PlcmChain));
+  const uint8_t* d_gm = b->d_blob + L.gm_off;
+  for (int c = 0; c < 2; c++) {
+    cv::BatchJob* J = (cv::BatchJob*)(h + L.job_off[c]);
+    for (size_t q = 0; q < P.jobs[c].size(); q++) {
+      J[q] = P.jobs[c][q];
+      J[q].ks = b->d_ks + (uintptr_t)P.jobs[c][q].ks;
+      J[q].gm = (const uint32_t*)(d_gm + (uintptr_t)P.jobs[c][q].gm);
+    }
+    if (!P.group_jobs[c].empty())
+      memcpy(h + L.gj_off[c], P.group_jobs[c].data(), P.group_jobs[c].size() * 4);
+    if (!P.group_off[c].empty())
+      memcpy(h + L.go_off[c], P.group_off[c].data(), P.group_off[c].size() * 4);
+  }
+  if (!P.gm.empty()) memcpy(h + L.gm_off, P.gm.data(), P.gm.size() * 4);
+}
+
+Signature signature(const cv_batch* b, const Plan& P, const Layout& L) {
+  Signature s;
+  s.blob_bytes = L.bytes;
+  s.d_blob = b->d_blob;
+  s.d_ks = b->d_ks;
+  s.d_scratch = b->d_scratch;
+  s.d_counters = b->d_counters;
+  for (int v = 0; v < 3; v++) {
+    s.n_chains[v] = (uint32_t)P.chains[v].size();
+    s.chain_off[v] = L.chain_off[v];
+  }
+  for (int c = 0; c < 2; c++) {
+    s.groups[c] = P.groups[c];
+    s.lds[c] = P.lds[c];
+    s.job_off[c] = L.job_off[c];
+    s.gj_off[c] = L.gj_off[c];
+    s.go_off[c] = L.go_off[c];
+  }
+  s.G = b->shape.group_wgs;
+  s.threads = b->shape.threads;
+  s.scratch_stride = P.scratch_stride;
+  return s;
+}
+
+hipEvent_t pooled(cv_batch* b) {
+  if (!b->event_pool.empty()) {
+    hipEvent_t e = b->event_pool.back();
+    b->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+cv_status drain(cv_batch* b) {
+  for (Span& sp : b->spans) {
+    CV_HIP(hipEventSynchronize(sp.b));
+    float ms = 0.f;
+    CV_HIP(hipEventElapsedTime(&ms, sp.a, sp.b));
+    if (sp.kind == 0) {
+      b->prof.prbg_ms += ms;
+      b->prof.prbg_launches++;
+      b->prof.prbg_steps += sp.work;
+    } else {
+      b->prof.round_ms += ms;
+      b->prof.round_launches++;
+      b->prof.round_frames += sp.work;
+    }
+    b->event_pool.push_back(sp.a);
+    b->event_pool.push_back(sp.b);
+  }
+  b->spans.clear();
+  return CV_OK;
+}
+
+// Enqueue the tick (copy, launches, flag read-back) on stream st.  With
+// `timed`, every launch is bracketed by events (not allowed while capturing).
+cv_status enqueue_tick(cv_batch* b, const Plan& P, const Layout& L, const Slot& s, hipStream_t st,
+                       bool timed, bool rounds_only) {
+  CV_HIP(hipMemcpyAsync(b->d_blob, s.h_blob, L.bytes, hipMemcpyHostToDevice, st));
+  hipEvent_t ta = nullptr;
+  if (timed && !rounds_only && (ta = pooled(b))) CV_HIP(hipEventRecord(ta, st));
+  if (!rounds_only)
+    for (int v = 0; v < 3; v++)
+      if (!P.chains[v].empty())
+        CV_HIP(cv::launch_prbg_plcm((const cv::PlcmChain*)(b->d_blob + L.chain_off[v]),
+                                    (uint32_t)P.chains[v].size(), b->d_ks, 0, v, st));
+  if (ta) {
+    hipEvent_t tb = pooled(b);
+    if (tb) {
+      CV_HIP(hipEventRecord(tb, st));
+      b->spans.push_back({ta, tb, 0, P.steps});
+    }
+  }
+  ta = nullptr;
+  if (timed && (ta = pooled(b))) CV_HIP(hipEventRecord(ta, st));
+  for (int c = 0; c < 2; c++) {
+    if (P.jobs[c].empty()) continue;
+    cv::BatchArgs a{};
+    a.jobs = (const cv::BatchJob*)(b->d_blob + L.job_off[c]);
+    a.group_jobs = (const uint32_t*)(b->d_blob + L.gj_off[c]);
+    a.group_off = (const uint32_t*)(b->d_blob + L.go_off[c]);
+    a.scratch = b->d_scratch;
+    a.scratch_stride = P.scratch_stride;
+    a.counters = b->d_counters;
+    a.err = b->d_err;
+    a.G = b->shape.group_wgs;
+    a.groups = P.groups[c];
+    a.spin_limit = kSpinLimit;
+    CV_HIP(cv::launch_batch_rounds(a, 3 + c, b->shape.threads, P.lds[c], st));
+  }
+  if (ta) {
+    hipEvent_t tb = pooled(b);
+    if (tb) {
+      CV_HIP(hipEventRecord(tb, st));
+      b->spans.push_back({ta, tb, 1, P.frame_rounds});
+    }
+  }
+  CV_HIP(hipMemcpyAsync(b->h_err, b->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  return CV_OK;
+}
+
+// A tick that timed out at a group barrier (or found a group spread over
+// XCDs) set the flag; the copy at the end of every tick brings it back.
+cv_status check_flag(cv_batch* b, bool wait) {
+  if (b->failed) return fail(CV_E_HIP, "an earlier tick of this batch timed out at a group barrier");
+  if (!b->ran) return CV_OK;
+  if (wait) {
+    CV_HIP(hipEventSynchronize(b->done));
+  } else if (hipEventQuery(b->done) != hipSuccess) {
+    (void)hipGetLastError();
+    return CV_OK;
+  }
+  if (*b->h_err) {
+    b->failed = true;
+    return fail(CV_E_HIP,
+                "a batch tick timed out at a group barrier or found a group spread over XCDs; "
+                "its output is invalid");
+  }
+  return CV_OK;
+}
+
+cv_status prepare(cv_batch* b, const cv_batch_item* items, size_t n_items, bool rounds_only,
+                  Plan& P, Layout& L) {
+  cv_status s = make_plan(b, items, n_items, rounds_only, P);
+  if (s != CV_OK) return s;
+  L = layout(P);
+  const uint32_t gmax = std::max(P.groups[0], P.groups[1]);
+  if ((s = grow(&b->d_blob, &b->blob_cap, L.bytes, "batch table")) != CV_OK) return s;
+  if ((s = grow(&b->d_ks, &b->ks_cap, std::max<uint64_t>(P.ks_bytes, 16), "batch keystream")) != CV_OK)
+    return s;
+  if ((s = grow(&b->d_scratch, &b->scratch_cap, std::max<uint64_t>(2 * P.scratch_stride * gmax, 256),
+                "batch scratch")) != CV_OK)
+    return s;
+  size_t cbytes = b->counters_cap * 128;
+  if ((s = grow((uint8_t**)&b->d_counters, &cbytes, 128ull * std::max<uint32_t>(gmax, 8),
+                "batch counters")) != CV_OK)
+    return s;
+  b->counters_cap = cbytes / 128;
+  return CV_OK;
+}
+
+// Order this call's stream after the batch's previous tick.
+cv_status order_after_last(cv_batch* b, hipStream_t st) {
+  if (b->ran && st != b->last_stream) CV_HIP(hipStreamWaitEvent(st, b->done, 0));
+  return CV_OK;
+}
+
+cv_status run_tick(cv_batch* b, const cv_batch_item* items, size_t n_items, hipStream_t st) {
+  Plan P;
+  Layout L;
+  cv_status s = prepare(b, items, n_items, false, P, L);
+  if (s != CV_OK) return s;
+  if ((s = order_after_last(b, st)) != CV_OK) return s;
+  // items outside the pixel-word conditions: their key's own path
+  for (size_t i : P.fallback) {
+    const cv_batch_item& it = items[i];
+    if ((s = crypt_frames(it.key, it.decrypt != 0, it.in, it.out, it.s_c, it.n_frames, st)) != CV_OK)
+      return s;
+  }
+  b->info.last_fallback_items = (uint32_t)P.fallback.size();
+  b->info.last_jobs = (uint32_t)(P.jobs[0].size() + P.jobs[1].size());
+  b->info.last_groups = P.groups[0] + P.groups[1];
+  b->info.last_chains = (uint32_t)(P.chains[0].size() + P.chains[1].size() + P.chains[2].size());
+  if (P.eligible.empty()) return CV_OK;
+
+  Slot& sl = b->slot[b->turn];
+  b->turn ^= 1;
+  if ((s = ensure_pinned(sl, L.bytes)) != CV_OK) return s;
+  if (sl.pending) {  // the tick before last may still be copying from this buffer
+    CV_HIP(hipEventSynchronize(sl.copied));
+    sl.pending = false;
+  }
+  fill_blob(b, P, L, sl.h_blob);
+  const Signature sig = signature(b, P, L);
+  if (b->profiling || !b->shape.use_graph) {
+    if ((s = enqueue_tick(b, P, L, sl, st, b->profiling, false)) != CV_OK) return s;
+  } else {
+    if (!(sl.has_sig && sl.sig == sig)) {
+      if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+      sl.exec = nullptr;
+      sl.has_sig = false;
+      CV_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+      s = enqueue_tick(b, P, L, sl, b->cap, false, false);
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamEndCapture(b->cap, &graph);
+      if (s != CV_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+      }
+      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+      e = hipGraphInstantiate(&sl.exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) {
+        sl.exec = nullptr;
+        return hip_fail(e, "hipGraphInstantiate");
+      }
+      sl.sig = sig;
+      sl.has_sig = true;
+      b->info.graph_captures++;
+    } else {
+      b->info.graph_replays++;
+    }
+    CV_HIP(hipGraphLaunch(sl.exec, st));
+  }
+  CV_HIP(hipEventRecord(sl.copied, st));
+  sl.pending = true;
+  for (size_t i : P.eligible) items[i].key->frame_index += items[i].n_frames;
+  return CV_OK;
+}
+
+void release(cv_batch* b) {
+  drop_graphs(b);
+  for (Slot& s : b->slot) {
+    if (s.h_blob) (void)hipHostFree(s.h_blob);
+    if (s.copied) (void)hipEventDestroy(s.copied);
+  }
+  for (Span& sp : b->spans) {
+    b->event_pool.push_back(sp.a);
+    b->event_pool.push_back(sp.b);
+  }
+  for (hipEvent_t e : b->event_pool) (void)hipEventDestroy(e);
+  if (b->d_blob) (void)hipFree(b->d_blob);
+  if (b->d_ks) (void)hipFree(b->d_ks);
+  if (b->d_scratch) (void)hipFree(b->d_scratch);
+  if (b->d_counters) (void)hipFree(b->d_counters);
+  if (b->d_err) (void)hipFree(b->d_err);
+  if (b->h_err) (void)hipHostFree(b->h_err);
+  if (b->done) (void)hipEventDestroy(b->done);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  delete b;
+}
+
+cv_status check_shape(const cv_batch_shape& s) {
+  if (s.threads < 256 || s.threads > 1024 || s.threads % 64)
+    return fail(CV_E_INVAL, "threads must be a multiple of 64 in 256..1024");
+  if (s.group_wgs < 1 || s.group_wgs > 64) return fail(CV_E_INVAL, "group_wgs must be in 1..64");
+  if (s.use_graph > 1) return fail(CV_E_INVAL, "use_graph must be 0 or 1");
+  return CV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cv_status cv_batch_create(int device, cv_batch** out) {
+  if (!out) return fail(CV_E_INVAL, "NULL argument");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail(CV_E_INVAL, "no such HIP device");
+  DeviceGuard dg(device);
+  cv_batch* b = new cv_batch();
+  b->device = device;
+  b->lds_max = lds_limit(device);
+  hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+  for (Slot& s : b->slot)
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s.copied, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipMalloc(&b->d_err, sizeof(uint32_t));
+  if (e == hipSuccess) e = hipHostMalloc(&b->h_err, sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemset(b->d_err, 0, sizeof(uint32_t));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    release(b);
+    return fail(e == hipErrorOutOfMemory ? CV_E_NOMEM : CV_E_HIP, "cv_batch_create failed");
+  }
+  *b->h_err = 0;
+  *out = b;
+  return CV_OK;
+}
+
+void cv_batch_free(cv_batch* b) {
+  if (!b) return;
+  DeviceGuard dg(b->device);
+  (void)hipDeviceSynchronize();
+  release(b);
+}
+
+cv_status cv_batch_get_shape(const cv_batch* b, cv_batch_shape* shape) {
+  if (!b || !shape) return fail(CV_E_INVAL, "NULL argument");
+  *shape = b->shape;
+  return CV_OK;
+}
+
+cv_status cv_batch_set_shape(cv_batch* b, const cv_batch_shape* shape) {
+  if (!b || !shape) return fail(CV_E_INVAL, "NULL argument");
+  cv_status s = check_shape(*shape);
+  if (s != CV_OK) return s;
+  b->shape = *shape;
+  return CV_OK;
+}
+
+cv_status cv_batch_run(cv_batch* b, const cv_batch_item* items, size_t n_items, void* stream) {
+  if (!b) return fail(CV_E_INVAL, "batch is NULL");
+  cv_status s = check_items(b, items, n_items);
+  if (s != CV_OK) return s;
+  for (size_t i = 0; i < n_items; i++)
+    if (items[i].n_frames && (s = check_async_errors(items[i].key, false)) != CV_OK) return s;
+  if ((s = check_flag(b, false)) != CV_OK) return s;
+  DeviceGuard dg(b->device);
+  hipStream_t st = (hipStream_t)stream;
+  if ((s = run_tick(b, items, n_items, st)) != CV_OK) return s;
+  CV_HIP(hipEventRecord(b->done, st));
+  b->last_stream = st;
+  b->ran = true;
+  b->info.ticks++;
+  return CV_OK;
+}
+
+cv_status cv_batch_sync(cv_batch* b) {
+  if (!b) return fail(CV_E_INVAL, "batch is NULL");
+  DeviceGuard dg(b->device);
+  return check_flag(b, true);
+}
+
+cv_status cv_batch_get_info(const cv_batch* b, cv_batch_info* info) {
+  if (!b || !info) return fail(CV_E_INVAL, "NULL argument");
+  *info = b->info;
+  return CV_OK;
+}
+
+cv_status cv_batch_autotune(cv_batch* b, const cv_batch_item* items, size_t n_items, void* stream,
+                            cv_batch_shape* best) {
+  if (!b) return fail(CV_E_INVAL, "batch is NULL");
+  cv_status s = check_items(b, items, n_items);
+  if (s != CV_OK) return s;
+  if ((s = check_flag(b, false)) != CV_OK) return s;
+  DeviceGuard dg(b->device);
+  hipStream_t st = (hipStream_t)stream;
+  if ((s = order_after_last(b, st)) != CV_OK) return s;
+  const cv_batch_shape keep = b->shape;
+  const bool prof = b->profiling;
+  b->profiling = true;  // time each rounds launch
+  cv_batch_shape win = keep;
+  double win_ms = -1.0;
+  const uint32_t threads_c[] = {512, 1024}, G_c[] = {2, 4, 8, 16, 32};
+  for (uint32_t th : threads_c) {
+    for (uint32_t G : G_c) {
+      b->shape = keep;
+      b->shape.threads = th;
+      b->shape.group_wgs = G;
+      Plan P;
+      Layout L;
+      if ((s = prepare(b, items, n_items, true, P, L)) != CV_OK) break;
+      if (P.jobs[0].empty() && P.jobs[1].empty()) break;
+      Slot& sl = b->slot[0];
+      if ((s = ensure_pinned(sl, L.bytes)) != CV_OK) break;
+      if (sl.pending) {
+        CV_HIP(hipEventSynchronize(sl.copied));
+        sl.pending = false;
+      }
+      fill_blob(b, P, L, sl.h_blob);
+      if ((s = drain(b)) != CV_OK) break;
+      b->prof = cv_profile{};
+      for (int rep = 0; rep < 4 && s == CV_OK; rep++) s = enqueue_tick(b, P, L, sl, st, true, true);
+      if (s != CV_OK) break;
+      CV_HIP(hipEventRecord(sl.copied, st));
+      sl.pending = true;
+      // the first launch warms up; the rest are timed
+      if (!b->spans.empty()) {
+        Span first = b->spans.front();
+        b->spans.erase(b->spans.begin());
+        if ((s = drain(b)) != CV_OK) break;
+        b->event_pool.push_back(first.a);
+        b->event_pool.push_back(first.b);
+      }
+      const double ms = b->prof.round_ms / std::max<uint64_t>(1, b->prof.round_launches);
+      if (win_ms < 0 || ms < win_ms) {
+        win_ms = ms;
+        win = b->shape;
+      }
+    }
+    if (s != CV_OK) break;
+  }
+  CV_HIP(hipEventRecord(b->done, st));
+  b->last_stream = st;
+  b->ran = true;
+  cv_status s2 = drain(b);
+  b->profiling = prof;
+  b->prof = cv_profile{};
+  b->shape = s == CV_OK ? win : keep;
+  if (s != CV_OK) return s;
+  if (s2 != CV_OK) return s2;
+  if ((s = check_flag(b, true)) != CV_OK) return s;
+  if (best) *best = b->shape;
+  return CV_OK;
+}
+
+cv_status cv_batch_set_profiling(cv_batch* b, int on) {
+  if (!b) return fail(CV_E_INVAL, "batch is NULL");
+  DeviceGuard dg(b->device);
+  cv_status s = drain(b);
+  if (s != CV_OK) return s;
+  b->profiling = on != 0;
+  b->prof = cv_profile{};
+  return CV_OK;
+}
+
+cv_status cv_batch_get_profile(cv_batch* b, cv_profile* prof) {
+  if (!b || !prof) return fail(CV_E_INVAL, "NULL argument");
+  if (!b->profiling) return fail(CV_E_STATE, "profiling is off");
+  DeviceGuard dg(b->device);
+  cv_status s = drain(b);
+  if (s != CV_OK) return s;
+  *prof = b->prof;
+  return CV_OK;
+}
+
+}  // extern "C"

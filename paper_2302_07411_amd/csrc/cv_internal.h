@@ -33,6 +33,8 @@ struct PlcmChain {
   uint64_t out_off;       // offset of this band's bytes in a frame's keystream
   uint64_t frame_stride;  // bytes from one frame's keystream to the next
   uint64_t nbytes;        // r * S_i bytes per frame
+  uint32_t frames;        // frames of this chain when the launch passes n_frames = 0
+  uint32_t pad;
 };
 
 // Generator variants (identical bytes): IEEE division; reciprocal division
@@ -40,7 +42,8 @@ struct PlcmChain {
 // one lane per piece of Eq. (5).
 enum PrbgVariant : int { PRBG_EXACT = 0, PRBG_RECIP = 1, PRBG_RECIP_PAIR = 2 };
 
-// Generate n_frames frames of keystream for n_chains chains into ks_base.
+// Generate n_frames frames of keystream for n_chains chains into ks_base
+// (n_frames = 0: every chain generates its own `frames`).
 hipError_t launch_prbg_plcm(const PlcmChain* d_chains, uint32_t n_chains, uint8_t* ks_base,
                             uint32_t n_frames, int variant, hipStream_t s);
 
@@ -105,6 +108,34 @@ hipError_t launch_rounds_fused(const RoundsFusedArgs& a, uint32_t threads, hipSt
 // not even one group per XCD fits).
 uint32_t rounds_fused_resident_groups(const Geom& g, uint32_t tile_rows, uint32_t threads,
                                       int device);
+
+// ------------------------------------------------------------- batch ----
+// One (stream, frame) of a multi-stream tick.
+struct BatchJob {
+  const uint8_t* in;        // packed frame
+  uint8_t* out;             // packed frame
+  const uint8_t* in_last;   // last readable dword of the stream's input buffer
+  const uint8_t* ks;        // this frame's keystream (canonical layout)
+  const uint32_t* gm;       // this frame's g(alpha) mod W
+  Geom g;
+  uint32_t decrypt;
+  uint32_t tile_rows;       // pixel-word tile rows for this geometry
+};
+
+struct BatchArgs {
+  const BatchJob* jobs;
+  const uint32_t* group_jobs;  // job indices, group after group
+  const uint32_t* group_off;   // groups + 1 offsets into group_jobs
+  uint8_t* scratch;            // per group two pixel-word frames of scratch_stride bytes
+  uint64_t scratch_stride;
+  uint32_t* counters;          // 128 bytes per group
+  uint32_t* err;
+  uint32_t G, groups, spin_limit;
+};
+
+hipError_t launch_batch_rounds(const BatchArgs& a, uint32_t C, uint32_t threads, size_t lds,
+                               hipStream_t s);
+uint32_t batch_resident_groups(uint32_t C, uint32_t G, uint32_t threads, size_t lds, int device);
 
 // LDS bytes a round kernel needs for a tile of `tile_rows` rows.
 size_t round_lds_bytes(const Geom& g, uint32_t tile_rows);

@@ -130,6 +130,7 @@ struct ChainPlan {
 
 __device__ __forceinline__ ChainPlan plan(const PlcmChain& ch, uint32_t n_frames) {
   ChainPlan c;
+  if (n_frames == 0) n_frames = ch.frames;
   c.nbytes = ch.nbytes;
   c.spf = (uint32_t)((ch.nbytes + 5) / 6);
   c.total = c.spf * n_frames;
@@ -277,7 +278,7 @@ __global__ __launch_bounds__(128) void prbg_plcm_kernel(const PlcmChain* __restr
 
 hipError_t launch_prbg_plcm(const PlcmChain* d_chains, uint32_t n_chains, uint8_t* ks_base,
                             uint32_t n_frames, int variant, hipStream_t s) {
-  if (n_chains == 0 || n_frames == 0) return hipSuccess;
+  if (n_chains == 0) return hipSuccess;
   switch (variant) {
     case PRBG_RECIP_PAIR:
       hipLaunchKernelGGL(prbg_plcm_kernel<kRecipPair>, dim3((n_chains + 15) / 16), dim3(128), 0, s,

@@ -1,0 +1,113 @@
+// Host-side runtime state of libchaosvid shared by the C-ABI translation
+// units (abi.cpp: keys; batch_host.cpp: multi-stream batches).
+#pragma once
+#include <string>
+#include <vector>
+
+#include "chaosvid.h"
+#include "cv_internal.h"
+
+using cv::Geom;
+
+// One video stream's key: device-resident generator state plus the
+// workspace its calls reuse.
+struct cv_key {
+  Geom g{};
+  cv_map map = CV_MAP_PLCM;
+  int device = 0;
+  int path = CV_PATH_PLAIN;
+  uint64_t F = 0;              // bytes per frame
+  uint64_t frame_index = 0;    // frames processed so far
+  std::vector<double> pm;      // the n key records as given
+  double* d_state = nullptr;   // 2n: x of map 1, map 2 per band
+  bool fast = false;           // every chain qualifies for the reciprocal division
+  uint32_t prbg_variant = 0;   // requested generator variant (cv_launch.prbg_variant)
+  uint32_t round_variant = 0;  // requested round kernels (cv_launch.round_variant)
+  uint32_t tile_pw = 0;        // rows per LDS tile of the pixel-word kernels
+  uint8_t* d_scratch2 = nullptr;  // second pixel-word scratch buffer
+  // fused path: per resident group two pixel-word frames, a barrier counter,
+  // and a timeout flag copied back to pinned memory after every launch
+  uint32_t fused_groups = 0;   // groups in flight (<= resident capacity)
+  uint32_t fused_cap = 0;      // resident capacity for the current launch shape
+  uint8_t* d_fscratch = nullptr;
+  uint32_t* d_counters = nullptr;
+  uint32_t* d_err = nullptr;
+  uint32_t* h_err = nullptr;
+  hipEvent_t err_copied = nullptr;
+  bool err_pending = false;
+  cv::PlcmChain* d_chains = nullptr;
+  std::vector<cv::PlcmChain> h_chains;  // host copy (tables of multi-stream batches)
+  // workspace, grown on demand
+  uint32_t batch_frames = 0;
+  uint8_t* d_ks = nullptr;
+  uint8_t* d_scratch = nullptr;
+  uint32_t* d_gm = nullptr;
+  uint32_t* h_gm = nullptr;    // pinned staging of the shift tables
+  size_t ws_frames = 0;
+  hipEvent_t gm_done = nullptr;
+  bool gm_pending = false;
+  // launch shape
+  uint32_t threads = 1024;
+  uint32_t tile_enc = 0, tile_dec = 0;
+  uint32_t max_band_rows = 0;
+  size_t lds_max = 0;
+  // event profiling
+  bool profiling = false;
+  struct Span {
+    hipEvent_t a, b;
+    int kind;  // 0 = prbg, 1 = round
+    uint64_t work;
+  };
+  std::vector<Span> spans;
+  std::vector<hipEvent_t> event_pool;
+  cv_profile prof{};
+};
+
+namespace cv {
+namespace rt {
+
+cv_status fail(cv_status s, const std::string& msg);
+cv_status hip_fail(hipError_t e, const char* what);
+
+#define CV_HIP(call)                                     \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);    \
+  } while (0)
+
+// Switch to the key's device for the lifetime of a call.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+// Row shifts of Eq. (1) for one frame, reduced mod W.
+void shift_table(uint32_t H, uint32_t W, uint32_t s_c, uint32_t* gm);
+bool aligned16(const void* p);
+bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb);
+// Generator variant a launch of this key uses.
+int prbg_variant(const cv_key* k);
+// Largest pixel-word tile (rows) <= want accepted with `threads` threads.
+uint32_t pw_tile_limit(const Geom& g, uint32_t threads, uint32_t want);
+size_t lds_limit(int device);
+cv_status check_async_errors(cv_key* k, bool wait);
+// Chain steps of `frames` frames over all bands of the key.
+uint64_t prbg_steps(const cv_key* k, uint64_t frames);
+// Validates the buffers and seeds of an encrypt/decrypt call.
+cv_status check_frames_args(const cv_key* k, const uint8_t* in, uint8_t* out, const uint32_t* s_c,
+                            size_t n);
+// Pixel-word LDS tile rows for geometry g with `threads` threads (0 = none).
+uint32_t pw_tile_rows(const Geom& g, uint32_t threads, size_t lds_max);
+// Encrypt or decrypt n frames of one key on its own path (plain or fused).
+cv_status crypt_frames(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
+                       const uint32_t* s_c, size_t n, void* stream);
+
+}  // namespace rt
+}  // namespace cv

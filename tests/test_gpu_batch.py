@@ -1,0 +1,270 @@
+"""GPU parity of multi-stream batches (cv_batch_*): one tick of many
+streams with different resolutions, subframe counts, frame counts and
+directions must give, byte for byte, what the CPU oracle gives for every
+stream on its own -- tick after tick, with graph capture and replay, for
+every launch shape, and next to streams that run on their key's own path."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_07411_amd.inputs import (CorrelatedVideo, confusion_seeds, plcm_key,
+                                         uniform_frames)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# (name, H, W, C, n, r, T per tick)
+STREAMS = [
+    ("b-rgb48", 48, 48, 3, 8, 5, 2),
+    ("b-wide", 48, 64, 3, 5, 5, 1),
+    ("b-tall", 80, 32, 3, 7, 5, 3),
+    ("b-rgba", 33, 16, 4, 4, 3, 2),
+    ("b-oneband", 64, 48, 3, 1, 5, 1),
+    ("b-rowbands", 12, 16, 3, 12, 2, 2),
+    ("b-n32", 96, 96, 3, 32, 5, 1),       # more bands than workgroups per group
+    ("b-odd", 31, 17, 3, 7, 4, 2),        # W % 16 != 0: runs on the key's own path
+    ("b-gray", 32, 32, 1, 4, 5, 1),       # C = 1: runs on the key's own path
+    ("b-tinykey", 24, 32, 3, 4, 5, 2),    # outside the reciprocal division's domain
+]
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2302_07411_amd import binding
+    binding.load()
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return binding
+
+
+def _dev(a: np.ndarray):
+    return torch.from_numpy(np.ascontiguousarray(a).reshape(-1)).to("cuda:0")
+
+
+def _host(t, shape):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().reshape(shape)
+
+
+def _pm(i, n, name):
+    pm = plcm_key(n, 7000 + 13 * i)
+    if name == "b-tinykey":
+        pm[1, 0] = 1e-300
+        pm[2, 3] = 2.0 ** -70
+    return pm
+
+
+class Stream:
+    def __init__(self, B, i, spec, decrypt):
+        self.name, self.H, self.W, self.C, self.n, self.r, self.T = spec
+        self.i, self.decrypt = i, decrypt
+        self.pm = _pm(i, self.n, self.name)
+        self.key = B.Key(self.H, self.W, self.C, self.n, self.r, self.pm)
+        self.ref = oracle.PlcmKey(self.H, self.W, self.C, self.n, self.r, self.pm)
+
+    def tick(self, t):
+        shape = (self.T, self.H, self.W, self.C)
+        frames = uniform_frames(self.H, self.W, self.C, self.T, 100 * self.i + t)
+        s_c = confusion_seeds(self.T, 500 * self.i + t)
+        want = (self.ref.decrypt if self.decrypt else self.ref.encrypt)(frames, s_c)
+        src = _dev(frames)
+        dst = torch.empty_like(src)
+        return (self.key, src, dst, s_c, self.decrypt), want, shape
+
+
+def _check_tick(items, wants, shapes, label):
+    torch.cuda.synchronize()
+    for it, want, shape in zip(items, wants, shapes):
+        got = _host(it[2], shape)
+        assert np.array_equal(got, want), \
+            f"{label}: {np.count_nonzero(got != want)} bytes differ"
+
+
+def _streams(B, specs=STREAMS):
+    return [Stream(B, i, s, decrypt=i % 3 == 2) for i, s in enumerate(specs)]
+
+
+@pytest.mark.parametrize("use_graph", [1, 0])
+def test_batch_ticks_match_oracle(B, use_graph):
+    """Three ticks of ten streams (mixed sizes, n, frame counts, directions,
+    two on their key's own path, one on the IEEE-division generator): every
+    tick's bytes equal the oracle's; the structure repeats, so ticks 2 and
+    3 replay the graph captured by tick 1."""
+    streams = _streams(B)
+    b = B.Batch()
+    b.set_shape(use_graph=use_graph)
+    for t in range(3):
+        print(f"[case] batch tick {t} use_graph={use_graph}", flush=True)
+        parts = [s.tick(t) for s in streams]
+        items = [p[0] for p in parts]
+        b.run(items)
+        b.sync()
+        _check_tick(items, [p[1] for p in parts], [p[2] for p in parts],
+                    f"tick {t} graph={use_graph}")
+        info = b.info()
+        assert info["last_fallback_items"] == 2
+        assert info["last_jobs"] == sum(s.T for s in streams if s.name not in ("b-odd", "b-gray"))
+    info = b.info()
+    assert info["ticks"] == 3
+    if use_graph:
+        assert info["graph_captures"] == 2 and info["graph_replays"] == 1  # two staging slots
+    else:
+        assert info["graph_captures"] == 0
+    for s in streams:
+        x, fi = s.key.get_state()
+        assert fi == 3 * s.T
+        assert np.array_equal(x[:, 0], s.ref.x1) and np.array_equal(x[:, 1], s.ref.x2)
+    b.close()
+
+
+@pytest.mark.parametrize("threads,G,max_groups", [
+    (1024, 16, 0), (1024, 1, 0), (256, 3, 0), (512, 32, 0), (1024, 8, 1), (768, 5, 9),
+])
+def test_batch_launch_shapes(B, threads, G, max_groups):
+    """Every launch shape gives the oracle's bytes: one workgroup per job,
+    more workgroups than bands, a single group walking every job."""
+    specs = [s for s in STREAMS if s[3] in (3, 4) and s[2] % 16 == 0]
+    streams = _streams(B, specs)
+    b = B.Batch()
+    b.set_shape(threads=threads, group_wgs=G, max_groups=max_groups)
+    for t in range(2):
+        print(f"[case] batch shape threads={threads} G={G} max_groups={max_groups} tick {t}",
+              flush=True)
+        parts = [s.tick(t) for s in streams]
+        items = [p[0] for p in parts]
+        b.run(items)
+        b.sync()
+        _check_tick(items, [p[1] for p in parts], [p[2] for p in parts], f"G={G} tick {t}")
+    b.close()
+
+
+def test_batch_round_trip_and_changing_structure(B):
+    """Encrypt in one tick, decrypt in the next with fresh keys; ticks with
+    different item sets re-capture; a skipped item (0 frames) does not
+    advance its key."""
+    specs = [s for s in STREAMS if s[3] in (3, 4) and s[2] % 16 == 0]
+    b = B.Batch()
+    enc_keys, dec_keys, data = [], [], []
+    for i, (name, H, W, C, n, r, T) in enumerate(specs):
+        pm = _pm(i, n, name)
+        enc_keys.append(B.Key(H, W, C, n, r, pm))
+        dec_keys.append(B.Key(H, W, C, n, r, pm))
+        frames = uniform_frames(H, W, C, T, 900 + i)
+        data.append((frames, confusion_seeds(T, 950 + i)))
+    srcs = [_dev(f) for f, _ in data]
+    encs = [torch.empty_like(s) for s in srcs]
+    decs = [torch.empty_like(s) for s in srcs]
+    print("[case] batch round trip", flush=True)
+    b.run([(k, s, e, sc) for k, s, e, (_, sc) in zip(enc_keys, srcs, encs, data)])
+    b.run([(k, e, d, sc, 1) for k, e, d, (_, sc) in zip(dec_keys, encs, decs, data)])
+    b.sync()
+    for s, d in zip(srcs, decs):
+        assert torch.equal(s, d)
+    # a subset with one empty item
+    k0, s0 = enc_keys[0], srcs[0]
+    x_before, fi_before = enc_keys[1].get_state()
+    empty = torch.empty(0, dtype=torch.uint8, device="cuda:0")
+    out0 = torch.empty_like(s0)
+    b.run([(k0, s0, out0, data[0][1]), (enc_keys[1], empty, empty, [])])
+    b.sync()
+    x_after, fi_after = enc_keys[1].get_state()
+    assert fi_after == fi_before and np.array_equal(x_before, x_after)
+    name, H, W, C, n, r, T = specs[0]
+    ref = oracle.PlcmKey(H, W, C, n, r, _pm(0, n, name))
+    ref.encrypt(data[0][0], data[0][1])
+    want = ref.encrypt(data[0][0], data[0][1])
+    assert np.array_equal(_host(out0, (T, H, W, C)), want)
+    assert b.info()["graph_captures"] == 3
+    b.close()
+
+
+def test_batch_full_size_streams(B):
+    """Eight streams at real sizes in one tick -- 768x768x3 with 16
+    subframes, 480x480x3 with 8, 1024x1024x3 with 32 -- against solo
+    encryption of each stream on its own key (itself checked against the
+    oracle in the single-stream tests), plus one stream against the oracle."""
+    specs = [(768, 768, 3, 16), (480, 480, 3, 8), (768, 768, 3, 16), (1024, 1024, 3, 32),
+             (480, 480, 3, 8), (768, 768, 3, 16), (768, 768, 3, 16), (480, 480, 3, 8)]
+    b = B.Batch()
+    items, solo_out, keys = [], [], []
+    print("[case] batch full-size 8 streams", flush=True)
+    for i, (H, W, C, n) in enumerate(specs):
+        T = 2
+        pm = plcm_key(n, 8100 + i)
+        frames = torch.from_numpy(CorrelatedVideo(H, W, C, 8200 + i).frames(0, T).reshape(-1))
+        src = frames.to("cuda:0")
+        s_c = confusion_seeds(T, 8300 + i)
+        dst = torch.empty_like(src)
+        solo = torch.empty_like(src)
+        B.Key(H, W, C, n, 5, pm).encrypt(src, solo, s_c)
+        key = B.Key(H, W, C, n, 5, pm)
+        keys.append(key)
+        items.append((key, src, dst, s_c))
+        solo_out.append(solo)
+    b.run(items)
+    b.sync()
+    for i, (it, solo) in enumerate(zip(items, solo_out)):
+        assert torch.equal(it[2], solo), f"stream {i} differs from its solo encryption"
+    H, W, C, n = specs[1]
+    T = 2
+    want = oracle.PlcmKey(H, W, C, n, 5, plcm_key(n, 8101)).encrypt(
+        CorrelatedVideo(H, W, C, 8201).frames(0, T), confusion_seeds(T, 8301))
+    assert np.array_equal(_host(items[1][2], want.shape), want)
+    b.close()
+
+
+def test_batch_autotune_and_profile(B):
+    """The tuner picks a shape without advancing any key; ticks with the
+    chosen shape still match the oracle; profiling counts launches."""
+    specs = [s for s in STREAMS if s[3] in (3, 4) and s[2] % 16 == 0]
+    streams = _streams(B, specs)
+    b = B.Batch()
+    parts = [s.tick(0) for s in streams]
+    items = [p[0] for p in parts]
+    states = [s.key.get_state() for s in streams]
+    print("[case] batch autotune", flush=True)
+    best = b.autotune(items)
+    assert best["threads"] in (512, 1024) and best["group_wgs"] in (2, 4, 8, 16, 32)
+    assert b.get_shape() == best
+    for s, (x, fi) in zip(streams, states):
+        x2, fi2 = s.key.get_state()
+        assert fi2 == fi and np.array_equal(x, x2)
+    b.set_profiling(True)
+    b.run(items)
+    b.sync()
+    _check_tick(items, [p[1] for p in parts], [p[2] for p in parts], "after autotune")
+    prof = b.get_profile()
+    assert prof["round_launches"] >= 1 and prof["prbg_launches"] >= 1
+    assert prof["round_frames"] == sum(s.T * s.r for s in streams)
+    b.close()
+
+
+def test_batch_errors_leave_keys_unchanged(B):
+    H, W, C, n, r = 48, 48, 3, 8, 5
+    ka = B.Key(H, W, C, n, r, plcm_key(n, 1))
+    kb = B.Key(H, W, C, n, r, plcm_key(n, 2))
+    src = _dev(uniform_frames(H, W, C, 2, 3))
+    out1, out2 = torch.empty_like(src), torch.empty_like(src)
+    b = B.Batch()
+    bad = [
+        [(ka, src, out1, [1, 2]), (ka, src, out2, [1, 2])],   # a key twice
+        [(ka, src, out1, [1, 2]), (kb, src, out1, [1, 2])],   # outputs overlap
+        [(ka, src, out1, [1, 2]), (kb, out1, out2, [1, 2])],  # an output is another input
+        [(ka, src, out1, [1, 0])],                            # s_c = 0
+        [(ka, src, src, [1, 2])],                             # in == out
+    ]
+    for items in bad:
+        with pytest.raises(B.CvError) as e:
+            b.run(items)
+        assert e.value.status == B.CV_E_INVAL
+    for k in (ka, kb):
+        _, fi = k.get_state()
+        assert fi == 0
+    with pytest.raises(B.CvError):
+        b.set_shape(threads=100)
+    with pytest.raises(B.CvError):
+        b.set_shape(group_wgs=0)
+    b.run([])  # an empty tick is a no-op
+    b.sync()
+    b.close()
