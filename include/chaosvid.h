@@ -298,6 +298,81 @@ cv_status cv_batch_autotune(cv_batch *batch, const cv_batch_item *items, size_t 
 cv_status cv_batch_set_profiling(cv_batch *batch, int on);
 cv_status cv_batch_get_profile(cv_batch *batch, cv_profile *prof);
 
+/* ------------------------------------------------------------------------
+ * Serving.  A server owns a worker thread that runs many live video streams
+ * on one device: every stream keeps a ring of keystream frames generated
+ * ahead of its frames' arrival (the keystream depends only on the key
+ * state, Algorithm 2), and frames submitted by any stream are collected
+ * into ticks of the batched rounds kernel as soon as their keystream is
+ * ready (continuous batching).  A frame's latency is then the wait for the
+ * next tick plus the r rounds, not the sequential generator chain.  The
+ * real-time criterion of the paper is 24 frames per second per stream.
+ *
+ * Streams are admitted while the server's device-memory budget holds their
+ * keystream rings (ring_frames * r*H*W*C bytes each); frame and output
+ * buffers are the caller's.  The bytes of every frame are identical to
+ * cv_encrypt_frames / cv_decrypt_frames on a key built from the same p_m.
+ */
+typedef struct cv_server cv_server;
+typedef struct cv_stream cv_stream;
+
+/* Start a server on `device` with `hbm_budget` bytes of device memory for
+ * keystream rings (0 = a quarter of the free memory).  Ring depth 3
+ * frames and 8 queued frames per stream unless cv_server_tune says
+ * otherwise.  Errors: CV_E_INVAL (NULL, no such device), CV_E_NOMEM. */
+cv_status cv_server_create(int device, size_t hbm_budget, cv_server **out);
+
+/* Ring depth (keystream frames generated ahead, >= 1) and queue depth
+ * (frames a stream may have submitted and not finished, >= 1) for streams
+ * opened after the call.  CV_E_INVAL if 0 or above 64. */
+cv_status cv_server_tune(cv_server *server, uint32_t ring_frames, uint32_t queue_frames);
+
+/* Stop the worker after the submitted frames are done, close every stream
+ * and release the server.  NULL is ignored. */
+void cv_server_free(cv_server *server);
+
+/* Block until every submitted frame of every stream is done.  Returns the
+ * error that stopped the server, if any. */
+cv_status cv_server_drain(cv_server *server);
+
+typedef struct {
+  uint64_t frames_done;         /* frames whose rounds have completed */
+  uint64_t rounds_ticks;        /* batched rounds launches */
+  uint64_t keystream_launches;  /* keystream generation launches */
+  uint64_t keystream_frames;    /* stream-frames of keystream generated */
+  uint32_t open_streams;
+  uint32_t pad;
+  uint64_t hbm_used, hbm_budget; /* keystream ring bytes in use / allowed */
+} cv_server_stats;
+
+cv_status cv_server_get_stats(cv_server *server, cv_server_stats *stats);
+
+/* Open a stream (one direction: decrypt = 0 encrypts, 1 decrypts) with its
+ * own key (same geometry, map and p_m rules and errors as cv_keysetup).
+ * Keystream generation for its first frames starts at once.  CV_E_AGAIN
+ * if the budget cannot hold its ring or 4096 streams are open. */
+cv_status cv_stream_open(cv_server *server, const cv_geom *geom, cv_map map, const double *p_m,
+                         size_t n_doubles, int decrypt, cv_stream **out);
+
+/* Queue the stream's next frame: `frame` and `out` are device buffers of
+ * H*W*C bytes that must stay valid, and not be written, until the frame is
+ * done; `out` must not overlap another frame buffer in flight.  s_c >= 1
+ * is the frame's confusion seed.  *ticket receives the frame's number in
+ * the stream (0, 1, 2, ...).  CV_E_AGAIN if queue_frames frames are in
+ * flight; CV_E_INVAL for NULL buffers, frame == out or s_c = 0; CV_E_HIP
+ * if the server stopped on an error. */
+cv_status cv_stream_submit(cv_stream *stream, const uint8_t *frame, uint8_t *out, uint32_t s_c,
+                           uint64_t *ticket);
+
+/* *done = 1 once frame `ticket` is in its output buffer; *latency_ms (may
+ * be NULL) then receives the time from its submission to the worker seeing
+ * its tick complete (or -1 for tickets more than 4096 frames old).
+ * CV_E_INVAL for a ticket not yet issued. */
+cv_status cv_stream_poll(cv_stream *stream, uint64_t ticket, int *done, double *latency_ms);
+
+/* Wait for the stream's frames, then release the stream and its key. */
+cv_status cv_stream_close(cv_stream *stream);
+
 #ifdef __cplusplus
 }
 #endif

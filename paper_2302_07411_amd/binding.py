@@ -27,6 +27,9 @@ EXPORTS = (
     "cv_key_set_profiling", "cv_key_get_profile", "cv_batch_create", "cv_batch_free",
     "cv_batch_get_shape", "cv_batch_set_shape", "cv_batch_run", "cv_batch_sync",
     "cv_batch_get_info", "cv_batch_autotune", "cv_batch_set_profiling", "cv_batch_get_profile",
+    "cv_server_create", "cv_server_tune", "cv_server_free", "cv_server_drain",
+    "cv_server_get_stats", "cv_stream_open", "cv_stream_submit", "cv_stream_poll",
+    "cv_stream_close",
 )
 
 
@@ -64,6 +67,13 @@ class CvBatchInfo(ct.Structure):
                 ("graph_replays", ct.c_uint64), ("last_jobs", ct.c_uint32),
                 ("last_groups", ct.c_uint32), ("last_chains", ct.c_uint32),
                 ("last_fallback_items", ct.c_uint32)]
+
+
+class CvServerStats(ct.Structure):
+    _fields_ = [("frames_done", ct.c_uint64), ("rounds_ticks", ct.c_uint64),
+                ("keystream_launches", ct.c_uint64), ("keystream_frames", ct.c_uint64),
+                ("open_streams", ct.c_uint32), ("pad", ct.c_uint32),
+                ("hbm_used", ct.c_uint64), ("hbm_budget", ct.c_uint64)]
 
 
 class CvError(RuntimeError):
@@ -136,6 +146,25 @@ def load() -> ct.CDLL:
     L.cv_batch_set_profiling.argtypes = [vp, ct.c_int]
     L.cv_batch_get_profile.restype = ct.c_int
     L.cv_batch_get_profile.argtypes = [vp, ct.POINTER(CvProfile)]
+    L.cv_server_create.restype = ct.c_int
+    L.cv_server_create.argtypes = [ct.c_int, sz, ct.POINTER(vp)]
+    L.cv_server_tune.restype = ct.c_int
+    L.cv_server_tune.argtypes = [vp, ct.c_uint32, ct.c_uint32]
+    L.cv_server_free.restype = None
+    L.cv_server_free.argtypes = [vp]
+    L.cv_server_drain.restype = ct.c_int
+    L.cv_server_drain.argtypes = [vp]
+    L.cv_server_get_stats.restype = ct.c_int
+    L.cv_server_get_stats.argtypes = [vp, ct.POINTER(CvServerStats)]
+    L.cv_stream_open.restype = ct.c_int
+    L.cv_stream_open.argtypes = [vp, ct.POINTER(CvGeom), ct.c_int, ct.POINTER(ct.c_double), sz,
+                                 ct.c_int, ct.POINTER(vp)]
+    L.cv_stream_submit.restype = ct.c_int
+    L.cv_stream_submit.argtypes = [vp, u8p, u8p, ct.c_uint32, ct.POINTER(ct.c_uint64)]
+    L.cv_stream_poll.restype = ct.c_int
+    L.cv_stream_poll.argtypes = [vp, ct.c_uint64, ct.POINTER(ct.c_int), ct.POINTER(ct.c_double)]
+    L.cv_stream_close.restype = ct.c_int
+    L.cv_stream_close.argtypes = [vp]
     _lib = L
     return L
 
@@ -336,3 +365,87 @@ class Batch:
         p = CvProfile()
         _check(load().cv_batch_get_profile(self._h, ct.byref(p)))
         return {f: getattr(p, f) for f, _ in CvProfile._fields_}
+
+
+class Server:
+    """Serving loop (cv_server_*): live streams whose frames are batched into
+    rounds ticks by a worker thread, keystream generated ahead."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0, ring_frames: int = None,
+                 queue_frames: int = None):
+        h = ct.c_void_p()
+        _check(load().cv_server_create(device, hbm_budget, ct.byref(h)))
+        self._h = h
+        self._streams = []
+        if ring_frames is not None or queue_frames is not None:
+            _check(load().cv_server_tune(self._h, ring_frames or 3, queue_frames or 8))
+
+    def open(self, H, W, C, n, r, pm, decrypt: bool = False) -> "ServerStream":
+        pm = np.ascontiguousarray(np.asarray(pm, np.float64).reshape(-1))
+        g = CvGeom(H, W, C, n, r)
+        h = ct.c_void_p()
+        _check(load().cv_stream_open(self._h, ct.byref(g), CV_MAP_PLCM,
+                                     pm.ctypes.data_as(ct.POINTER(ct.c_double)), pm.size,
+                                     int(bool(decrypt)), ct.byref(h)))
+        st = ServerStream(self, h, H * W * C)
+        self._streams.append(st)
+        return st
+
+    def drain(self):
+        _check(load().cv_server_drain(self._h))
+
+    def stats(self) -> dict:
+        st = CvServerStats()
+        _check(load().cv_server_get_stats(self._h, ct.byref(st)))
+        return {f: getattr(st, f) for f, _ in CvServerStats._fields_ if f != "pad"}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().cv_server_free(self._h)
+            self._h = None
+            for st in self._streams:
+                st._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ServerStream:
+    def __init__(self, server, h, frame_bytes):
+        self.server, self._h, self.frame_bytes = server, h, frame_bytes
+
+    def submit(self, frame, out, s_c: int) -> int:
+        """Queue one frame; returns its ticket.  Raises CvError with status
+        CV_E_AGAIN when the stream's queue is full."""
+        if frame.numel() != self.frame_bytes or out.numel() != self.frame_bytes:
+            raise ValueError("frame and out must hold one frame")
+        t = ct.c_uint64()
+        _check(load().cv_stream_submit(self._h, _ptr(frame), _ptr(out), int(s_c), ct.byref(t)))
+        return t.value
+
+    def try_submit(self, frame, out, s_c: int):
+        """As submit, but returns None instead of raising when the queue is full."""
+        t = ct.c_uint64()
+        st = load().cv_stream_submit(self._h, _ptr(frame), _ptr(out), int(s_c), ct.byref(t))
+        if st == CV_E_AGAIN:
+            return None
+        _check(st)
+        return t.value
+
+    def poll(self, ticket: int):
+        """(done, latency_ms) of a submitted frame."""
+        d, lat = ct.c_int(), ct.c_double()
+        _check(load().cv_stream_poll(self._h, ticket, ct.byref(d), ct.byref(lat)))
+        return bool(d.value), lat.value
+
+    def close(self):
+        if self._h is not None:
+            _check(load().cv_stream_close(self._h))
+            self._h = None
+            try:
+                self.server._streams.remove(self)
+            except ValueError:
+                pass

@@ -291,6 +291,14 @@ cv_status run_rounds_fused(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* 
   return CV_OK;
 }
 
+bool pw_eligible(const cv_key* k, const uint8_t* in, const uint8_t* out, uint32_t threads,
+                 size_t lds_max) {
+  const Geom& g = k->g;
+  if (!((g.C == 3 || g.C == 4) && g.W % 16 == 0 && aligned16(in) && aligned16(out))) return false;
+  const uint32_t t = pw_tile_rows(g, threads, lds_max);
+  return t > 0 && cv::round_pw_lds_bytes(g, t) <= lds_max;
+}
+
 // Pixel-word kernels apply: 3 or 4 channels, 16-byte rows and buffers.
 bool use_pw(const cv_key* k, const uint8_t* in, const uint8_t* out, const uint8_t* ks) {
   if (k->round_variant == 1) return false;

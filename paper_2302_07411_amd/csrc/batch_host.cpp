@@ -112,14 +112,10 @@ namespace {
 // ------------------------------------------------------------ the plan ---
 struct Plan {
   std::vector<cv::PlcmChain> chains[3];  // by generator variant
-  std::vector<cv::BatchJob> jobs[2];     // by C (3, 4)
+  std::vector<cv::BatchJob> jobs[2];     // by C (3, 4); ks and gm hold offsets until fill_blob
   std::vector<uint32_t> group_jobs[2], group_off[2];
-  std::vector<uint64_t> gm_off;          // per eligible item: offset of its tables in gm
-  std::vector<uint32_t> gm;              // shift tables of every frame
-  std::vector<size_t> fallback;          // items on their key's own path
-  std::vector<size_t> eligible;
-  std::vector<uint64_t> ks_off;          // per eligible item
-  uint64_t ks_bytes = 0, scratch_stride = 0;
+  std::vector<uint32_t> gm;              // shift tables of every frame job
+  uint64_t scratch_stride = 0;
   uint32_t groups[2] = {0, 0};
   size_t lds[2] = {0, 0};
   uint64_t steps = 0, frame_rounds = 0;
@@ -165,104 +161,77 @@ cv_status check_items(const cv_batch* b, const cv_batch_item* items, size_t n_it
   return CV_OK;
 }
 
-bool batch_eligible(const cv_batch* b, const cv_batch_item& it) {
-  const Geom& g = it.key->g;
-  if (!((g.C == 3 || g.C == 4) && g.W % 16 == 0 && aligned16(it.in) && aligned16(it.out)))
-    return false;
-  const uint32_t t = pw_tile_rows(g, b->shape.threads, b->lds_max);
-  return t > 0 && cv::round_pw_lds_bytes(g, t) <= b->lds_max;
-}
-
 // Work of one job on the critical path of its group: r rounds, each
 // ceil(n/G) bands of at most max_band_rows rows per workgroup.
 uint64_t job_cost(const cv_key* k, uint32_t G) {
   return (uint64_t)k->g.r * ((k->g.n + G - 1) / G) * k->max_band_rows * k->g.W;
 }
 
-// Build every table of the tick except device addresses that depend on the
-// workspace (filled in by fill_blob).  `rounds_only` skips the generators.
-cv_status make_plan(cv_batch* b, const cv_batch_item* items, size_t n_items, bool rounds_only,
-                    Plan& P) {
+// Tables of one tick: the chains of `cj` and the frame jobs of `fj`.
+cv_status plan_tick(const cv_batch* b, const std::vector<ChainJob>& cj,
+                    const std::vector<FrameJob>& fj, Plan& P) {
   const uint32_t G = b->shape.group_wgs, threads = b->shape.threads;
-  uint64_t ks = 0, gm = 0, pwf_max = 0;
-  for (size_t i = 0; i < n_items; i++) {
-    const cv_batch_item& it = items[i];
-    if (it.n_frames == 0) continue;
-    if (!batch_eligible(b, it)) {
-      P.fallback.push_back(i);
-      continue;
+  for (const ChainJob& c : cj) {
+    const int v = prbg_variant(c.k);
+    for (const cv::PlcmChain& c0 : c.k->h_chains) {
+      cv::PlcmChain ch = c0;
+      ch.out_off = c.ks_off + c0.out_off;
+      ch.frame_stride = c.frame_stride ? c.frame_stride : c0.frame_stride;
+      ch.frames = c.frames;
+      P.chains[v].push_back(ch);
     }
-    const cv_key* k = it.key;
-    P.eligible.push_back(i);
-    P.ks_off.push_back(ks);
-    P.gm_off.push_back(gm);
-    ks += (uint64_t)it.n_frames * k->g.r * k->F;
-    gm += (uint64_t)it.n_frames * k->g.H;
-    pwf_max = std::max<uint64_t>(pwf_max, (uint64_t)k->g.H * k->g.W * 4);
-  }
-  P.ks_bytes = ks;
-  P.scratch_stride = align_up(pwf_max, 256);
-  P.gm.resize(gm);
-  for (size_t e = 0; e < P.eligible.size(); e++) {
-    const cv_batch_item& it = items[P.eligible[e]];
-    const cv_key* k = it.key;
-    const Geom& g = k->g;
-    for (uint32_t t = 0; t < it.n_frames; t++)
-      shift_table(g.H, g.W, it.s_c[t], P.gm.data() + P.gm_off[e] + (uint64_t)t * g.H);
-    if (!rounds_only) {
-      const int v = prbg_variant(k);
-      for (const cv::PlcmChain& c0 : k->h_chains) {
-        cv::PlcmChain c = c0;
-        c.out_off = P.ks_off[e] + c0.out_off;
-        c.frames = it.n_frames;
-        P.chains[v].push_back(c);
-      }
-      P.steps += prbg_steps(k, it.n_frames);
-    }
-    P.frame_rounds += (uint64_t)it.n_frames * g.r;
+    P.steps += prbg_steps(c.k, c.frames);
   }
   for (auto& cs : P.chains)
     std::stable_sort(cs.begin(), cs.end(), [](const cv::PlcmChain& x, const cv::PlcmChain& y) {
       return x.nbytes * x.frames > y.nbytes * y.frames;
     });
-  // jobs per channel count, longest first onto the least loaded group
+  uint64_t gm = 0, pwf_max = 0;
+  for (const FrameJob& f : fj) {
+    gm += f.k->g.H;
+    pwf_max = std::max<uint64_t>(pwf_max, (uint64_t)f.k->g.H * f.k->g.W * 4);
+  }
+  P.scratch_stride = align_up(pwf_max, 256);
+  P.gm.resize(gm);
+  gm = 0;
+  std::vector<std::pair<uint64_t, uint32_t>> order[2];  // (cost, job) per C
+  for (const FrameJob& f : fj) {
+    const Geom& g = f.k->g;
+    shift_table(g.H, g.W, f.s_c, P.gm.data() + gm);
+    const int ci = g.C == 4;
+    const uint32_t tile = pw_tile_rows(g, threads, b->lds_max);
+    if (tile == 0) return fail(CV_E_INVAL, "frame too wide for the batch's workgroup size");
+    P.lds[ci] = std::max(P.lds[ci], cv::round_pw_lds_bytes(g, tile));
+    cv::BatchJob J{};
+    J.in = f.in;
+    J.out = f.out;
+    J.in_last = f.in_last;
+    // offsets of the keystream (from the tick's base) and of the shift table (from the
+    // table area), turned into device addresses by fill_blob
+    J.ks = (const uint8_t*)(uintptr_t)f.ks_off;
+    J.gm = (const uint32_t*)(uintptr_t)(gm * 4);
+    J.g = g;
+    J.decrypt = f.decrypt;
+    J.tile_rows = tile;
+    order[ci].push_back({job_cost(f.k, G), (uint32_t)P.jobs[ci].size()});
+    P.jobs[ci].push_back(J);
+    P.frame_rounds += g.r;
+    gm += g.H;
+  }
+  // per channel count: longest job first onto the least loaded group
   for (int ci = 0; ci < 2; ci++) {
-    const uint32_t C = 3 + ci;
-    std::vector<std::pair<uint64_t, uint32_t>> order;  // (cost, job)
-    size_t lds = 0;
-    for (size_t e = 0; e < P.eligible.size(); e++) {
-      const cv_batch_item& it = items[P.eligible[e]];
-      const cv_key* k = it.key;
-      if (k->g.C != C) continue;
-      const uint32_t tile = pw_tile_rows(k->g, threads, b->lds_max);
-      lds = std::max(lds, cv::round_pw_lds_bytes(k->g, tile));
-      for (uint32_t t = 0; t < it.n_frames; t++) {
-        cv::BatchJob J{};
-        J.in = it.in + (uint64_t)t * k->F;
-        J.out = it.out + (uint64_t)t * k->F;
-        J.in_last = it.in + (uint64_t)it.n_frames * k->F - 4;
-        // device addresses of ks and gm are offsets until finish_plan
-        J.ks = (const uint8_t*)(uintptr_t)(P.ks_off[e] + (uint64_t)t * k->g.r * k->F);
-        J.gm = (const uint32_t*)(uintptr_t)((P.gm_off[e] + (uint64_t)t * k->g.H) * 4);
-        J.g = k->g;
-        J.decrypt = (uint32_t)it.decrypt;
-        J.tile_rows = tile;
-        order.push_back({job_cost(k, G), (uint32_t)P.jobs[ci].size()});
-        P.jobs[ci].push_back(J);
-      }
-    }
     if (P.jobs[ci].empty()) continue;
-    const uint32_t cap = cv::batch_resident_groups(C, G, threads, lds, b->device);
+    const uint32_t cap = cv::batch_resident_groups(3 + ci, G, threads, P.lds[ci], b->device);
     if (cap == 0) return fail(CV_E_INVAL, "batch launch shape does not fit on the device");
     uint32_t groups = std::min<uint64_t>(cap, P.jobs[ci].size());
     if (b->shape.max_groups) groups = std::min(groups, b->shape.max_groups);
-    std::stable_sort(order.begin(), order.end(),
+    std::stable_sort(order[ci].begin(), order[ci].end(),
                      [](const auto& x, const auto& y) { return x.first > y.first; });
     std::vector<std::vector<uint32_t>> per(groups);
     std::vector<std::pair<uint64_t, uint32_t>> heap;  // (load, group), min-heap
     for (uint32_t q = 0; q < groups; q++) heap.push_back({0, q});
     auto later = [](const auto& x, const auto& y) { return x > y; };
-    for (const auto& o : order) {
+    for (const auto& o : order[ci]) {
       std::pop_heap(heap.begin(), heap.end(), later);
       heap.back().first += o.first;
       per[heap.back().second].push_back(o.second);
@@ -274,7 +243,6 @@ cv_status make_plan(cv_batch* b, const cv_batch_item* items, size_t n_items, boo
       P.group_off[ci].push_back((uint32_t)P.group_jobs[ci].size());
     }
     P.groups[ci] = groups;
-    P.lds[ci] = lds;
   }
   return CV_OK;
 }
@@ -352,7 +320,8 @@ cv_status ensure_pinned(Slot& s, size_t bytes) {
 }
 
 // Write the tables into the slot's staging buffer with device addresses.
-void fill_blob(const cv_batch* b, const Plan& P, const Layout& L, uint8_t* h) {
+void fill_blob(const cv_batch* b, const Plan& P, const Layout& L, uint8_t* h,
+               const uint8_t* ks_base) {
   for (int v = 0; v < 3; v++)
     if (!P.chains[v].empty())
       memcpy(h + L.chain_off[v], P.chains[v].data(), P.chains[v].size() * sizeof(cv::PlcmChain));
@@ -361,7 +330,7 @@ void fill_blob(const cv_batch* b, const Plan& P, const Layout& L, uint8_t* h) {
     cv::BatchJob* J = (cv::BatchJob*)(h + L.job_off[c]);
     for (size_t q = 0; q < P.jobs[c].size(); q++) {
       J[q] = P.jobs[c][q];
-      J[q].ks = b->d_ks + (uintptr_t)P.jobs[c][q].ks;
+      J[q].ks = ks_base + (uintptr_t)P.jobs[c][q].ks;
       J[q].gm = (const uint32_t*)(d_gm + (uintptr_t)P.jobs[c][q].gm);
     }
     if (!P.group_jobs[c].empty())
@@ -372,11 +341,11 @@ void fill_blob(const cv_batch* b, const Plan& P, const Layout& L, uint8_t* h) {
   if (!P.gm.empty()) memcpy(h + L.gm_off, P.gm.data(), P.gm.size() * 4);
 }
 
-Signature signature(const cv_batch* b, const Plan& P, const Layout& L) {
+Signature signature(const cv_batch* b, const Plan& P, const Layout& L, uint8_t* ks_base) {
   Signature s;
   s.blob_bytes = L.bytes;
   s.d_blob = b->d_blob;
-  s.d_ks = b->d_ks;
+  s.d_ks = ks_base;
   s.d_scratch = b->d_scratch;
   s.d_counters = b->d_counters;
   for (int v = 0; v < 3; v++) {
@@ -430,15 +399,16 @@ cv_status drain(cv_batch* b) {
 // Enqueue the tick (copy, launches, flag read-back) on stream st.  With
 // `timed`, every launch is bracketed by events (not allowed while capturing).
 cv_status enqueue_tick(cv_batch* b, const Plan& P, const Layout& L, const Slot& s, hipStream_t st,
-                       bool timed, bool rounds_only) {
+                       bool timed, uint8_t* ks_base) {
   CV_HIP(hipMemcpyAsync(b->d_blob, s.h_blob, L.bytes, hipMemcpyHostToDevice, st));
+  const bool has_chains = !P.chains[0].empty() || !P.chains[1].empty() || !P.chains[2].empty();
+  const bool has_jobs = !P.jobs[0].empty() || !P.jobs[1].empty();
   hipEvent_t ta = nullptr;
-  if (timed && !rounds_only && (ta = pooled(b))) CV_HIP(hipEventRecord(ta, st));
-  if (!rounds_only)
-    for (int v = 0; v < 3; v++)
-      if (!P.chains[v].empty())
-        CV_HIP(cv::launch_prbg_plcm((const cv::PlcmChain*)(b->d_blob + L.chain_off[v]),
-                                    (uint32_t)P.chains[v].size(), b->d_ks, 0, v, st));
+  if (timed && has_chains && (ta = pooled(b))) CV_HIP(hipEventRecord(ta, st));
+  for (int v = 0; v < 3; v++)
+    if (!P.chains[v].empty())
+      CV_HIP(cv::launch_prbg_plcm((const cv::PlcmChain*)(b->d_blob + L.chain_off[v]),
+                                  (uint32_t)P.chains[v].size(), ks_base, 0, v, st));
   if (ta) {
     hipEvent_t tb = pooled(b);
     if (tb) {
@@ -447,7 +417,7 @@ cv_status enqueue_tick(cv_batch* b, const Plan& P, const Layout& L, const Slot& 
     }
   }
   ta = nullptr;
-  if (timed && (ta = pooled(b))) CV_HIP(hipEventRecord(ta, st));
+  if (timed && has_jobs && (ta = pooled(b))) CV_HIP(hipEventRecord(ta, st));
   for (int c = 0; c < 2; c++) {
     if (P.jobs[c].empty()) continue;
     cv::BatchArgs a{};
@@ -494,15 +464,13 @@ cv_status check_flag(cv_batch* b, bool wait) {
   return CV_OK;
 }
 
-cv_status prepare(cv_batch* b, const cv_batch_item* items, size_t n_items, bool rounds_only,
+cv_status prepare(cv_batch* b, const std::vector<ChainJob>& cj, const std::vector<FrameJob>& fj,
                   Plan& P, Layout& L) {
-  cv_status s = make_plan(b, items, n_items, rounds_only, P);
+  cv_status s = plan_tick(b, cj, fj, P);
   if (s != CV_OK) return s;
   L = layout(P);
   const uint32_t gmax = std::max(P.groups[0], P.groups[1]);
   if ((s = grow(&b->d_blob, &b->blob_cap, L.bytes, "batch table")) != CV_OK) return s;
-  if ((s = grow(&b->d_ks, &b->ks_cap, std::max<uint64_t>(P.ks_bytes, 16), "batch keystream")) != CV_OK)
-    return s;
   if ((s = grow(&b->d_scratch, &b->scratch_cap, std::max<uint64_t>(2 * P.scratch_stride * gmax, 256),
                 "batch scratch")) != CV_OK)
     return s;
@@ -520,68 +488,138 @@ cv_status order_after_last(cv_batch* b, hipStream_t st) {
   return CV_OK;
 }
 
-cv_status run_tick(cv_batch* b, const cv_batch_item* items, size_t n_items, hipStream_t st) {
-  Plan P;
-  Layout L;
-  cv_status s = prepare(b, items, n_items, false, P, L);
-  if (s != CV_OK) return s;
-  if ((s = order_after_last(b, st)) != CV_OK) return s;
-  // items outside the pixel-word conditions: their key's own path
-  for (size_t i : P.fallback) {
-    const cv_batch_item& it = items[i];
-    if ((s = crypt_frames(it.key, it.decrypt != 0, it.in, it.out, it.s_c, it.n_frames, st)) != CV_OK)
-      return s;
-  }
-  b->info.last_fallback_items = (uint32_t)P.fallback.size();
-  b->info.last_jobs = (uint32_t)(P.jobs[0].size() + P.jobs[1].size());
-  b->info.last_groups = P.groups[0] + P.groups[1];
-  b->info.last_chains = (uint32_t)(P.chains[0].size() + P.chains[1].size() + P.chains[2].size());
-  if (P.eligible.empty()) return CV_OK;
-
+// Staging slot for the next tick, free for the host to write.
+cv_status next_slot(cv_batch* b, size_t bytes, Slot** out) {
   Slot& sl = b->slot[b->turn];
   b->turn ^= 1;
-  if ((s = ensure_pinned(sl, L.bytes)) != CV_OK) return s;
+  cv_status s = ensure_pinned(sl, bytes);
+  if (s != CV_OK) return s;
   if (sl.pending) {  // the tick before last may still be copying from this buffer
     CV_HIP(hipEventSynchronize(sl.copied));
     sl.pending = false;
   }
-  fill_blob(b, P, L, sl.h_blob);
-  const Signature sig = signature(b, P, L);
-  if (b->profiling || !b->shape.use_graph) {
-    if ((s = enqueue_tick(b, P, L, sl, st, b->profiling, false)) != CV_OK) return s;
-  } else {
-    if (!(sl.has_sig && sl.sig == sig)) {
-      if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
-      sl.exec = nullptr;
-      sl.has_sig = false;
-      CV_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-      s = enqueue_tick(b, P, L, sl, b->cap, false, false);
-      hipGraph_t graph = nullptr;
-      hipError_t e = hipStreamEndCapture(b->cap, &graph);
-      if (s != CV_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return s;
-      }
-      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-      e = hipGraphInstantiate(&sl.exec, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (e != hipSuccess) {
-        sl.exec = nullptr;
-        return hip_fail(e, "hipGraphInstantiate");
-      }
-      sl.sig = sig;
-      sl.has_sig = true;
-      b->info.graph_captures++;
-    } else {
-      b->info.graph_replays++;
-    }
-    CV_HIP(hipGraphLaunch(sl.exec, st));
-  }
-  CV_HIP(hipEventRecord(sl.copied, st));
-  sl.pending = true;
-  for (size_t i : P.eligible) items[i].key->frame_index += items[i].n_frames;
+  *out = &sl;
   return CV_OK;
 }
+
+// Capture the tick into the slot's graph (when its signature changed) and launch it.
+cv_status launch_graph(cv_batch* b, const Plan& P, const Layout& L, Slot& sl, uint8_t* ks_base,
+                       hipStream_t st) {
+  const Signature sig = signature(b, P, L, ks_base);
+  if (!(sl.has_sig && sl.sig == sig)) {
+    if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+    sl.exec = nullptr;
+    sl.has_sig = false;
+    CV_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    cv_status s = enqueue_tick(b, P, L, sl, b->cap, false, ks_base);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap, &graph);
+    if (s != CV_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&sl.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      sl.exec = nullptr;
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    sl.sig = sig;
+    sl.has_sig = true;
+    b->info.graph_captures++;
+  } else {
+    b->info.graph_replays++;
+  }
+  CV_HIP(hipGraphLaunch(sl.exec, st));
+  return CV_OK;
+}
+
+// Items outside the pixel-word conditions run on their key's own path.
+bool item_eligible(const cv_batch* b, const cv_batch_item& it) {
+  return pw_eligible(it.key, it.in, it.out, b->shape.threads, b->lds_max);
+}
+
+// Chains and frame jobs of the items that take the batched kernels, with
+// their keystream laid out item after item from offset 0; the others are
+// listed in `fallback`.
+void collect(const cv_batch* b, const cv_batch_item* items, size_t n_items,
+             std::vector<ChainJob>& cj, std::vector<FrameJob>& fj, std::vector<size_t>& fallback,
+             std::vector<size_t>& eligible, uint64_t& ks) {
+  ks = 0;
+  for (size_t i = 0; i < n_items; i++) {
+    const cv_batch_item& it = items[i];
+    if (it.n_frames == 0) continue;
+    if (!item_eligible(b, it)) {
+      fallback.push_back(i);
+      continue;
+    }
+    eligible.push_back(i);
+    const cv_key* k = it.key;
+    const uint64_t rF = (uint64_t)k->g.r * k->F;
+    cj.push_back({k, ks, 0, it.n_frames});
+    for (uint32_t t = 0; t < it.n_frames; t++)
+      fj.push_back({k, it.in + (uint64_t)t * k->F, it.out + (uint64_t)t * k->F,
+                    it.in + (uint64_t)it.n_frames * k->F - 4, ks + t * rF, it.s_c[t],
+                    (uint32_t)it.decrypt});
+    ks += it.n_frames * rF;
+  }
+}
+
+cv_status run_tick(cv_batch* b, const cv_batch_item* items, size_t n_items, hipStream_t st) {
+  std::vector<ChainJob> cj;
+  std::vector<FrameJob> fj;
+  std::vector<size_t> fallback, eligible;
+  uint64_t ks = 0;
+  collect(b, items, n_items, cj, fj, fallback, eligible, ks);
+  cv_status s = grow(&b->d_ks, &b->ks_cap, std::max<uint64_t>(ks, 16), "batch keystream");
+  if (s != CV_OK) return s;
+  if ((s = order_after_last(b, st)) != CV_OK) return s;
+  for (size_t i : fallback) {
+    const cv_batch_item& it = items[i];
+    if ((s = crypt_frames(it.key, it.decrypt != 0, it.in, it.out, it.s_c, it.n_frames, st)) != CV_OK)
+      return s;
+  }
+  b->info.last_fallback_items = (uint32_t)fallback.size();
+  if ((s = batch_enqueue(b, cj, fj, b->d_ks, st)) != CV_OK) return s;
+  for (size_t i : eligible) items[i].key->frame_index += items[i].n_frames;
+  return CV_OK;
+}
+
+}  // namespace
+
+namespace cv {
+namespace rt {
+
+cv_status batch_enqueue(cv_batch* b, const std::vector<ChainJob>& cj, const std::vector<FrameJob>& fj,
+                        uint8_t* ks_base, hipStream_t st) {
+  Plan P;
+  Layout L;
+  cv_status s = prepare(b, cj, fj, P, L);
+  if (s != CV_OK) return s;
+  b->info.last_jobs = (uint32_t)(P.jobs[0].size() + P.jobs[1].size());
+  b->info.last_groups = P.groups[0] + P.groups[1];
+  b->info.last_chains = (uint32_t)(P.chains[0].size() + P.chains[1].size() + P.chains[2].size());
+  if (cj.empty() && fj.empty()) return CV_OK;
+  Slot* sp = nullptr;
+  if ((s = next_slot(b, L.bytes, &sp)) != CV_OK) return s;
+  fill_blob(b, P, L, sp->h_blob, ks_base);
+  if (b->profiling || !b->shape.use_graph)
+    s = enqueue_tick(b, P, L, *sp, st, b->profiling, ks_base);
+  else
+    s = launch_graph(b, P, L, *sp, ks_base, st);
+  if (s != CV_OK) return s;
+  CV_HIP(hipEventRecord(sp->copied, st));
+  sp->pending = true;
+  return CV_OK;
+}
+
+bool batch_flag_set(const cv_batch* b) { return b->failed || *b->h_err != 0; }
+
+}  // namespace rt
+}  // namespace cv
+
+namespace {
 
 void release(cv_batch* b) {
   drop_graphs(b);
@@ -714,20 +752,24 @@ cv_status cv_batch_autotune(cv_batch* b, const cv_batch_item* items, size_t n_it
       b->shape = keep;
       b->shape.threads = th;
       b->shape.group_wgs = G;
+      std::vector<ChainJob> cj;
+      std::vector<FrameJob> fj;
+      std::vector<size_t> fallback, eligible;
+      uint64_t ks = 0;
+      collect(b, items, n_items, cj, fj, fallback, eligible, ks);
+      if ((s = grow(&b->d_ks, &b->ks_cap, std::max<uint64_t>(ks, 16), "batch keystream")) != CV_OK)
+        break;
       Plan P;
       Layout L;
-      if ((s = prepare(b, items, n_items, true, P, L)) != CV_OK) break;
+      if ((s = prepare(b, {}, fj, P, L)) != CV_OK) break;
       if (P.jobs[0].empty() && P.jobs[1].empty()) break;
-      Slot& sl = b->slot[0];
-      if ((s = ensure_pinned(sl, L.bytes)) != CV_OK) break;
-      if (sl.pending) {
-        CV_HIP(hipEventSynchronize(sl.copied));
-        sl.pending = false;
-      }
-      fill_blob(b, P, L, sl.h_blob);
+      Slot* sp = nullptr;
+      if ((s = next_slot(b, L.bytes, &sp)) != CV_OK) break;
+      Slot& sl = *sp;
+      fill_blob(b, P, L, sl.h_blob, b->d_ks);
       if ((s = drain(b)) != CV_OK) break;
       b->prof = cv_profile{};
-      for (int rep = 0; rep < 4 && s == CV_OK; rep++) s = enqueue_tick(b, P, L, sl, st, true, true);
+      for (int rep = 0; rep < 4 && s == CV_OK; rep++) s = enqueue_tick(b, P, L, sl, st, true, b->d_ks);
       if (s != CV_OK) break;
       CV_HIP(hipEventRecord(sl.copied, st));
       sl.pending = true;

@@ -109,5 +109,39 @@ uint32_t pw_tile_rows(const Geom& g, uint32_t threads, size_t lds_max);
 cv_status crypt_frames(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
                        const uint32_t* s_c, size_t n, void* stream);
 
+// Pixel-word kernels apply to this key and buffers with `threads` threads.
+bool pw_eligible(const cv_key* k, const uint8_t* in, const uint8_t* out, uint32_t threads,
+                 size_t lds_max);
+// Key-path helpers (plain or fused rounds of one key, its workspace).
+cv_status ensure_workspace(cv_key* k, size_t frames);
+cv_status upload_shift_tables(cv_key* k, const uint32_t* s_c, size_t T, hipStream_t st);
+cv_status run_rounds(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out, const uint8_t* ks,
+                     uint32_t T, hipStream_t st);
+
+// Work of one multi-stream tick.  Keystream locations are byte offsets from
+// the tick's keystream base.
+struct ChainJob {
+  const cv_key* k;
+  uint64_t ks_off;        // frame 0 of this key's keystream (canonical per-frame layout)
+  uint64_t frame_stride;  // bytes from one frame's keystream to the next (0 = r*F)
+  uint32_t frames;        // frames to generate (advances the key's generators)
+};
+struct FrameJob {
+  const cv_key* k;
+  const uint8_t* in;       // packed frame
+  uint8_t* out;            // packed frame
+  const uint8_t* in_last;  // last readable dword of the buffer `in` lies in
+  uint64_t ks_off;         // this frame's keystream
+  uint32_t s_c;            // confusion seed of this frame
+  uint32_t decrypt;
+};
+// Enqueue keystream generation for `cj` and the rounds of `fj` (whose
+// keystream is generated by this tick or was generated earlier) on st.
+// Every frame job must satisfy pw_eligible for the batch's shape.
+cv_status batch_enqueue(cv_batch* b, const std::vector<ChainJob>& cj, const std::vector<FrameJob>& fj,
+                        uint8_t* ks_base, hipStream_t st);
+// Read-back of the batch's timeout flag as of its last completed tick.
+bool batch_flag_set(const cv_batch* b);
+
 }  // namespace rt
 }  // namespace cv

@@ -1,0 +1,566 @@
+// Serving loop of libchaosvid (declarations and contract in
+// include/chaosvid.h): many live streams on one device, driven by one
+// worker thread.
+//
+// Per stream, the worker keeps a ring of `ring_frames` keystream frames in
+// a device arena.  The keystream of frame f depends only on the key's
+// generator state (Algorithm 2), so it is produced before the frame
+// arrives: the worker keeps one keystream launch in flight on its own HIP
+// stream, covering every stream with a free ring slot, and gives streams
+// with short generator chains several frames per launch so that no chain
+// waits long for the longest one.  Frames submitted by the caller queue per
+// stream; whenever fewer than two rounds ticks are in flight, the worker
+// takes every queued frame whose keystream is ready, from every stream, into
+// one tick of the batched rounds kernel on a second HIP stream (continuous
+// batching).  A frame's ring slot is reused once its tick has completed.
+//
+// Locking: one mutex guards the stream table and every counter; HIP calls
+// are made by the worker with the mutex released, on job lists it copied
+// out under the mutex.  Callers' threads never make HIP calls except in
+// cv_stream_open (key setup) and cv_stream_close / cv_server_free.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "runtime.h"
+
+using namespace cv::rt;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+constexpr uint32_t kLatencyLog = 4096;   // per-stream latencies kept for polling
+constexpr uint32_t kMaxStreams = 4096;
+constexpr uint32_t kMaxTicksInFlight = 2;
+constexpr uint32_t kThreads = 1024;      // rounds workgroup size
+
+// First-fit sub-allocator of the keystream arena (offsets, 256-byte units).
+class Arena {
+ public:
+  void reset(size_t cap) {
+    cap_ = cap;
+    free_.clear();
+    if (cap) free_[0] = cap;
+    used_ = 0;
+  }
+  // Offset of a block of `n` bytes, or SIZE_MAX if none is free.
+  size_t alloc(size_t n) {
+    n = (n + 255) / 256 * 256;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < n) continue;
+      const size_t off = it->first, left = it->second - n;
+      free_.erase(it);
+      if (left) free_[off + n] = left;
+      used_ += n;
+      return off;
+    }
+    return SIZE_MAX;
+  }
+  void release(size_t off, size_t n) {
+    n = (n + 255) / 256 * 256;
+    used_ -= n;
+    auto it = free_.emplace(off, n).first;
+    auto next = std::next(it);
+    if (next != free_.end() && it->first + it->second == next->first) {
+      it->second += next->second;
+      free_.erase(next);
+    }
+    if (it != free_.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == it->first) {
+        prev->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t used() const { return used_; }
+  size_t cap() const { return cap_; }
+
+ private:
+  size_t cap_ = 0, used_ = 0;
+  std::map<size_t, size_t> free_;  // offset -> bytes
+};
+
+struct Pending {
+  uint64_t ticket;
+  const uint8_t* in;
+  uint8_t* out;
+  uint32_t s_c;
+  Clock::time_point t_submit;
+};
+
+struct Part {
+  cv_stream* st;
+  uint64_t ticket;
+  Clock::time_point t_submit;
+};
+
+struct Tick {
+  hipEvent_t ev = nullptr;
+  bool batched = false;
+  std::vector<Part> parts;
+};
+
+}  // namespace
+
+struct cv_stream {
+  cv_server* srv = nullptr;
+  cv_key* key = nullptr;
+  bool decrypt = false;
+  uint32_t D = 0;             // ring depth (frames)
+  uint32_t Q = 0;             // queue depth (frames in flight)
+  uint64_t rF = 0;            // keystream bytes per frame
+  uint64_t steps_per_frame = 0;  // longest chain's steps per frame
+  size_t ring_off = 0, ring_bytes = 0;
+  bool pw = false;            // geometry takes the batched kernels
+  // counters (server mutex)
+  uint64_t submitted = 0;     // tickets issued
+  uint64_t ks_issued = 0;     // keystream frames launched
+  uint64_t ks_ready = 0;      // keystream frames generated
+  uint64_t dispatched = 0;    // frames handed to rounds ticks
+  uint64_t completed = 0;     // frames done
+  std::deque<Pending> queue;  // submitted, not yet dispatched
+  std::vector<double> lat;    // latency (ms) of ticket t at t % kLatencyLog
+  bool closing = false;
+  bool in_ks_launch = false;
+};
+
+struct cv_server {
+  int device = 0;
+  size_t lds_max = 0;
+  uint32_t ring_frames = 3, queue_frames = 8;
+  uint8_t* arena_mem = nullptr;
+  Arena arena;
+  cv_batch* rb = nullptr;  // rounds ticks
+  cv_batch* kb = nullptr;  // keystream launches
+  hipStream_t s_rounds = nullptr, s_ks = nullptr;
+  hipEvent_t ks_ev = nullptr;
+  std::vector<hipEvent_t> ev_pool;
+  std::mutex mu;
+  std::condition_variable work_cv, done_cv;
+  std::thread worker;
+  bool stop = false;
+  cv_status err = CV_OK;
+  std::string err_msg;
+  std::vector<cv_stream*> streams;
+  std::vector<std::pair<cv_stream*, uint32_t>> ks_launch;  // in flight
+  bool ks_busy = false;
+  std::deque<Tick> ticks;
+  cv_server_stats stats{};
+};
+
+namespace {
+
+// Set the server's sticky error (mutex held).
+void set_error(cv_server* S, cv_status s, const std::string& msg) {
+  if (S->err == CV_OK) {
+    S->err = s;
+    S->err_msg = msg;
+  }
+  S->done_cv.notify_all();
+}
+
+hipEvent_t take_event(cv_server* S) {
+  if (!S->ev_pool.empty()) {
+    hipEvent_t e = S->ev_pool.back();
+    S->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  return hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess ? e : nullptr;
+}
+
+// Frames of keystream to generate for each stream in the next launch (mutex held).
+void plan_keystream(cv_server* S, std::vector<ChainJob>& cj) {
+  uint64_t longest = 0;
+  for (cv_stream* st : S->streams)
+    if (!st->closing && st->ks_issued - st->completed < st->D)
+      longest = std::max(longest, st->steps_per_frame);
+  for (cv_stream* st : S->streams) {
+    if (st->closing) continue;
+    const uint64_t free = st->D - (st->ks_issued - st->completed);
+    if (free == 0) continue;
+    const uint64_t contiguous = st->D - st->ks_issued % st->D;  // no wrap within a launch
+    const uint64_t share = std::max<uint64_t>(1, longest / std::max<uint64_t>(1, st->steps_per_frame));
+    const uint32_t k = (uint32_t)std::min({free, contiguous, share});
+    cj.push_back({st->key, st->ring_off + (st->ks_issued % st->D) * st->rF, 0, k});
+    S->ks_launch.push_back({st, k});
+    st->ks_issued += k;
+    st->in_ks_launch = true;
+  }
+}
+
+// Queued frames with keystream ready, from every stream (mutex held).
+void plan_rounds(cv_server* S, std::vector<FrameJob>& fj, std::vector<Pending>& solo,
+                 std::vector<cv_stream*>& solo_st, Tick& t) {
+  for (cv_stream* st : S->streams) {
+    while (!st->queue.empty() && st->queue.front().ticket < st->ks_ready) {
+      const Pending p = st->queue.front();
+      st->queue.pop_front();
+      const cv_key* k = st->key;
+      const uint64_t ks_off = st->ring_off + (p.ticket % st->D) * st->rF;
+      if (st->pw && pw_eligible(k, p.in, p.out, kThreads, S->lds_max)) {
+        fj.push_back({k, p.in, p.out, p.in + k->F - 4, ks_off, p.s_c, (uint32_t)st->decrypt});
+      } else {
+        solo.push_back(p);
+        solo_st.push_back(st);
+      }
+      t.parts.push_back({st, p.ticket, p.t_submit});
+      st->dispatched++;
+    }
+  }
+}
+
+// Rounds of frames outside the batched kernels' conditions, on their key's path.
+cv_status run_solo(cv_server* S, const std::vector<Pending>& solo,
+                   const std::vector<cv_stream*>& solo_st) {
+  for (size_t i = 0; i < solo.size(); i++) {
+    cv_stream* st = solo_st[i];
+    const Pending& p = solo[i];
+    cv_status s = ensure_workspace(st->key, 1);
+    if (s == CV_OK) s = upload_shift_tables(st->key, &p.s_c, 1, S->s_rounds);
+    if (s == CV_OK)
+      s = run_rounds(st->key, st->decrypt, p.in, p.out,
+                     S->arena_mem + st->ring_off + (p.ticket % st->D) * st->rF, 1, S->s_rounds);
+    if (s != CV_OK) return s;
+  }
+  return CV_OK;
+}
+
+// Release a stream's ring (mutex held) and then, with the mutex released,
+// its key.
+void free_stream(cv_server* S, cv_stream* st, std::unique_lock<std::mutex>* lk) {
+  S->arena.release(st->ring_off, st->ring_bytes);
+  if (lk) lk->unlock();
+  cv_key_free(st->key);
+  delete st;
+  if (lk) lk->lock();
+}
+
+void worker_main(cv_server* S) {
+  (void)hipSetDevice(S->device);
+  std::unique_lock<std::mutex> lk(S->mu);
+  for (;;) {
+    bool progressed = false;
+    // keystream launch done: its frames become usable
+    if (S->ks_busy && hipEventQuery(S->ks_ev) == hipSuccess) {
+      for (auto& [st, k] : S->ks_launch) {
+        st->ks_ready += k;
+        st->in_ks_launch = false;
+      }
+      S->ks_launch.clear();
+      S->ks_busy = false;
+      progressed = true;
+    }
+    // rounds ticks done, in order
+    while (!S->ticks.empty() && hipEventQuery(S->ticks.front().ev) == hipSuccess) {
+      Tick& t = S->ticks.front();
+      if (t.batched && batch_flag_set(S->rb))
+        set_error(S, CV_E_HIP, "a rounds tick timed out at a group barrier; its frames are invalid");
+      const Clock::time_point now = Clock::now();
+      for (const Part& p : t.parts) {
+        p.st->lat[p.ticket % kLatencyLog] =
+            std::chrono::duration<double, std::milli>(now - p.t_submit).count();
+        p.st->completed++;
+      }
+      S->stats.frames_done += t.parts.size();
+      S->ev_pool.push_back(t.ev);
+      S->ticks.pop_front();
+      progressed = true;
+      S->done_cv.notify_all();
+    }
+    (void)hipGetLastError();  // a query of an unfinished event leaves hipErrorNotReady behind
+    // streams being closed: free once nothing of theirs is in flight
+    for (size_t i = 0; i < S->streams.size();) {
+      cv_stream* st = S->streams[i];
+      if (st->closing && st->completed == st->submitted && !st->in_ks_launch) {
+        S->streams.erase(S->streams.begin() + i);
+        free_stream(S, st, &lk);
+        S->done_cv.notify_all();
+        progressed = true;
+        continue;
+      }
+      i++;
+    }
+    if (S->err == CV_OK && S->ticks.size() < kMaxTicksInFlight) {
+      std::vector<FrameJob> fj;
+      std::vector<Pending> solo;
+      std::vector<cv_stream*> solo_st;
+      Tick t;
+      plan_rounds(S, fj, solo, solo_st, t);
+      if (!t.parts.empty()) {
+        t.ev = take_event(S);
+        t.batched = !fj.empty();
+        lk.unlock();
+        cv_status s = run_solo(S, solo, solo_st);
+        if (s == CV_OK && !fj.empty()) s = batch_enqueue(S->rb, {}, fj, S->arena_mem, S->s_rounds);
+        std::string msg = s != CV_OK ? cv_last_error() : "";
+        hipError_t e = t.ev ? hipEventRecord(t.ev, S->s_rounds) : hipErrorOutOfMemory;
+        lk.lock();
+        if (s != CV_OK) set_error(S, s, msg);
+        else if (e != hipSuccess) set_error(S, CV_E_HIP, "event record failed");
+        else {
+          S->ticks.push_back(std::move(t));
+          S->stats.rounds_ticks++;
+        }
+        progressed = true;
+      }
+    }
+    if (S->err == CV_OK && !S->ks_busy && !S->stop) {
+      std::vector<ChainJob> cj;
+      plan_keystream(S, cj);
+      if (!cj.empty()) {
+        uint64_t frames = 0;
+        for (auto& c : cj) frames += c.frames;
+        lk.unlock();
+        cv_status s = batch_enqueue(S->kb, cj, {}, S->arena_mem, S->s_ks);
+        std::string msg = s != CV_OK ? cv_last_error() : "";
+        hipError_t e = hipEventRecord(S->ks_ev, S->s_ks);
+        lk.lock();
+        if (s != CV_OK) set_error(S, s, msg);
+        else if (e != hipSuccess) set_error(S, CV_E_HIP, "event record failed");
+        S->ks_busy = true;
+        S->stats.keystream_launches++;
+        S->stats.keystream_frames += frames;
+        progressed = true;
+      }
+    }
+    if (S->err != CV_OK) {
+      // nothing more will complete: release waiters
+      S->done_cv.notify_all();
+    }
+    const bool idle = S->ticks.empty() && !S->ks_busy;
+    if (S->stop && idle) break;
+    if (S->stop && S->err != CV_OK) {
+      lk.unlock();
+      (void)hipDeviceSynchronize();
+      lk.lock();
+      break;
+    }
+    if (!progressed) {
+      if (idle && !S->stop)
+        S->work_cv.wait_for(lk, std::chrono::milliseconds(2));
+      else
+        S->work_cv.wait_for(lk, std::chrono::microseconds(50));
+    }
+  }
+}
+
+cv_status server_error(const cv_server* S) {
+  return S->err == CV_OK ? CV_OK : fail(S->err, "server stopped: " + S->err_msg);
+}
+
+void destroy(cv_server* S) {
+  if (S->worker.joinable()) {
+    {
+      std::lock_guard<std::mutex> g(S->mu);
+      S->stop = true;
+    }
+    S->work_cv.notify_all();
+    S->worker.join();
+  }
+  DeviceGuard dg(S->device);
+  (void)hipDeviceSynchronize();
+  for (cv_stream* st : S->streams) free_stream(S, st, nullptr);
+  S->streams.clear();
+  for (Tick& t : S->ticks) S->ev_pool.push_back(t.ev);
+  for (hipEvent_t e : S->ev_pool)
+    if (e) (void)hipEventDestroy(e);
+  if (S->ks_ev) (void)hipEventDestroy(S->ks_ev);
+  cv_batch_free(S->rb);
+  cv_batch_free(S->kb);
+  if (S->s_rounds) (void)hipStreamDestroy(S->s_rounds);
+  if (S->s_ks) (void)hipStreamDestroy(S->s_ks);
+  if (S->arena_mem) (void)hipFree(S->arena_mem);
+  delete S;
+}
+
+}  // namespace
+
+extern "C" {
+
+cv_status cv_server_create(int device, size_t hbm_budget, cv_server** out) {
+  if (!out) return fail(CV_E_INVAL, "NULL argument");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail(CV_E_INVAL, "no such HIP device");
+  DeviceGuard dg(device);
+  if (hbm_budget == 0) {
+    size_t free_b = 0, total = 0;
+    CV_HIP(hipMemGetInfo(&free_b, &total));
+    hbm_budget = free_b / 4;
+  }
+  hbm_budget = hbm_budget / 256 * 256;
+  if (hbm_budget == 0) return fail(CV_E_INVAL, "hbm_budget below 256 bytes");
+  cv_server* S = new cv_server();
+  S->device = device;
+  S->lds_max = lds_limit(device);
+  cv_status s = cv_batch_create(device, &S->rb);
+  if (s == CV_OK) s = cv_batch_create(device, &S->kb);
+  if (s != CV_OK) {
+    destroy(S);
+    return s;
+  }
+  // ticks change shape every time: launch kernel by kernel; groups of 8
+  // workgroups leave room on every CU for the keystream launch alongside
+  cv_batch_shape shape{kThreads, 8, 0, 0};
+  (void)cv_batch_set_shape(S->rb, &shape);
+  (void)cv_batch_set_shape(S->kb, &shape);
+  hipError_t e = hipStreamCreateWithFlags(&S->s_rounds, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->s_ks, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ks_ev, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    destroy(S);
+    return hip_fail(e, "cv_server_create");
+  }
+  if (hipMalloc(&S->arena_mem, hbm_budget) != hipSuccess) {
+    (void)hipGetLastError();
+    destroy(S);
+    return fail(CV_E_NOMEM, "keystream arena allocation failed");
+  }
+  S->arena.reset(hbm_budget);
+  S->stats.hbm_budget = hbm_budget;
+  S->worker = std::thread(worker_main, S);
+  *out = S;
+  return CV_OK;
+}
+
+cv_status cv_server_tune(cv_server* S, uint32_t ring_frames, uint32_t queue_frames) {
+  if (!S) return fail(CV_E_INVAL, "server is NULL");
+  if (ring_frames < 1 || ring_frames > 64 || queue_frames < 1 || queue_frames > 64)
+    return fail(CV_E_INVAL, "ring_frames and queue_frames must be in 1..64");
+  std::lock_guard<std::mutex> g(S->mu);
+  S->ring_frames = ring_frames;
+  S->queue_frames = queue_frames;
+  return CV_OK;
+}
+
+void cv_server_free(cv_server* S) {
+  if (!S) return;
+  (void)cv_server_drain(S);
+  destroy(S);
+}
+
+cv_status cv_server_drain(cv_server* S) {
+  if (!S) return fail(CV_E_INVAL, "server is NULL");
+  std::unique_lock<std::mutex> lk(S->mu);
+  S->done_cv.wait(lk, [&] {
+    if (S->err != CV_OK) return true;
+    for (cv_stream* st : S->streams)
+      if (st->completed != st->submitted) return false;
+    return true;
+  });
+  return server_error(S);
+}
+
+cv_status cv_server_get_stats(cv_server* S, cv_server_stats* stats) {
+  if (!S || !stats) return fail(CV_E_INVAL, "NULL argument");
+  std::lock_guard<std::mutex> g(S->mu);
+  *stats = S->stats;
+  stats->open_streams = (uint32_t)S->streams.size();
+  stats->hbm_used = S->arena.used();
+  return CV_OK;
+}
+
+cv_status cv_stream_open(cv_server* S, const cv_geom* geom, cv_map map, const double* p_m,
+                         size_t n_doubles, int decrypt, cv_stream** out) {
+  if (!S || !out) return fail(CV_E_INVAL, "NULL argument");
+  *out = nullptr;
+  if (decrypt != 0 && decrypt != 1) return fail(CV_E_INVAL, "decrypt must be 0 or 1");
+  cv_key* k = nullptr;
+  cv_status s = cv_keysetup(geom, map, p_m, n_doubles, S->device, &k);
+  if (s != CV_OK) return s;
+  cv_stream* st = new cv_stream();
+  st->srv = S;
+  st->key = k;
+  st->decrypt = decrypt != 0;
+  st->rF = (uint64_t)k->g.r * k->F;
+  for (const cv::PlcmChain& c : k->h_chains)
+    st->steps_per_frame = std::max<uint64_t>(st->steps_per_frame, (c.nbytes + 5) / 6);
+  st->pw = (k->g.C == 3 || k->g.C == 4) && k->g.W % 16 == 0;
+  st->lat.assign(kLatencyLog, -1.0);
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    if ((s = server_error(S)) == CV_OK) {
+      st->D = S->ring_frames;
+      st->Q = S->queue_frames;
+      st->ring_bytes = st->D * st->rF;
+      if (S->streams.size() >= kMaxStreams) {
+        s = fail(CV_E_AGAIN, "too many open streams");
+      } else if ((st->ring_off = S->arena.alloc(st->ring_bytes)) == SIZE_MAX) {
+        s = fail(CV_E_AGAIN, "the server's device-memory budget cannot hold this stream's "
+                             "keystream ring now");
+      } else {
+        S->streams.push_back(st);
+      }
+    }
+  }
+  if (s != CV_OK) {
+    cv_key_free(k);
+    delete st;
+    return s;
+  }
+  S->work_cv.notify_all();
+  *out = st;
+  return CV_OK;
+}
+
+cv_status cv_stream_submit(cv_stream* st, const uint8_t* frame, uint8_t* out, uint32_t s_c,
+                           uint64_t* ticket) {
+  if (!st || !frame || !out || !ticket) return fail(CV_E_INVAL, "NULL argument");
+  if (s_c == 0) return fail(CV_E_INVAL, "confusion seed s_c must be >= 1");
+  if (ranges_overlap(frame, st->key->F, out, st->key->F)) return fail(CV_E_INVAL, "frame and out overlap");
+  cv_server* S = st->srv;
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    cv_status s = server_error(S);
+    if (s != CV_OK) return s;
+    if (st->closing) return fail(CV_E_STATE, "stream is closing");
+    if (st->submitted - st->completed >= st->Q) return fail(CV_E_AGAIN, "stream queue is full");
+    *ticket = st->submitted;
+    st->queue.push_back({st->submitted, frame, out, s_c, Clock::now()});
+    st->submitted++;
+  }
+  S->work_cv.notify_all();
+  return CV_OK;
+}
+
+cv_status cv_stream_poll(cv_stream* st, uint64_t ticket, int* done, double* latency_ms) {
+  if (!st || !done) return fail(CV_E_INVAL, "NULL argument");
+  cv_server* S = st->srv;
+  std::lock_guard<std::mutex> g(S->mu);
+  if (ticket >= st->submitted) return fail(CV_E_INVAL, "ticket not issued");
+  *done = ticket < st->completed;
+  if (latency_ms)
+    *latency_ms = (*done && ticket + kLatencyLog >= st->completed) ? st->lat[ticket % kLatencyLog]
+                                                                   : -1.0;
+  if (!*done) return server_error(S);
+  return CV_OK;
+}
+
+cv_status cv_stream_close(cv_stream* st) {
+  if (!st) return fail(CV_E_INVAL, "stream is NULL");
+  cv_server* S = st->srv;
+  std::unique_lock<std::mutex> lk(S->mu);
+  st->closing = true;
+  S->work_cv.notify_all();
+  // the worker frees the stream once its frames and keystream launch are done
+  S->done_cv.wait(lk, [&] {
+    return S->err != CV_OK ||
+           std::find(S->streams.begin(), S->streams.end(), st) == S->streams.end();
+  });
+  if (S->err != CV_OK) return server_error(S);  // freed with the server
+  return CV_OK;
+}
+
+}  // extern "C"
