@@ -15,7 +15,20 @@ launch stream; `roofline_rounds` is the same for the round kernel.
 `cpu_baseline` times the plain CPU oracle on the first frames of the same
 video and checks the GPU output of those frames against it byte for byte.
 
+Two more workloads are reported beside it:
+  `batched`: 64 streams of mixed resolution (480^2, 576^2, 768^2,
+  1920x1080) and subframe count (8/16/32), one frame per stream per tick,
+  each tick one keystream launch and one persistent rounds launch (shape
+  chosen by the autotuner), against the plain path (one call per stream
+  and frame) on the same streams; a sample of streams checked against the
+  oracle.
+  `served`: 256 live streams, Poisson arrivals at 24 frames/s each,
+  480^2 ... 3840x2160, 20% decrypting, through the serving loop for
+  --serve-seconds of wall time; per-frame latency from arrival to
+  completion, p50/p99 against the 41.7 ms deadline.
+
     python bench.py [--steps K] [--warmup W] [--batch B] [--cpu-frames N]
+                    [--no-batched] [--no-served] [--serve-seconds S]
 """
 import argparse
 import json
@@ -77,6 +90,170 @@ def cpu_baseline(src, dst, s_c, n_frames, pm):
             "parity_mismatched_bytes": mismatches}
 
 
+def bench_batched(B, torch, np, args):
+    """64 streams, one frame each per tick, batched kernels vs the plain path."""
+    import oracle
+    from paper_2302_07411_amd.inputs import (CorrelatedVideo, batched_streams, confusion_seeds,
+                                             plcm_key)
+    dev = torch.device("cuda:0")
+    specs = batched_streams(64, 4004)
+    ticks, warm = args.batched_ticks, 2
+    keys, srcs, outs, seeds, pms = [], [], [], [], []
+    for i, (h, w, c, n) in enumerate(specs):
+        pm = plcm_key(n, 6000 + i)
+        pms.append(pm)
+        keys.append(B.Key(h, w, c, n, R, pm))
+        srcs.append(CorrelatedVideo(h, w, c, 7000 + i).frames_torch(0, 1, dev).reshape(-1))
+        outs.append(torch.empty_like(srcs[-1]))
+        seeds.append(confusion_seeds(ticks + warm, 8000 + i))
+    b = B.Batch()
+    items = lambda t: [(k, s, o, sc[t:t + 1]) for k, s, o, sc in zip(keys, srcs, outs, seeds)]
+    shape = b.autotune(items(0))
+    b.run(items(0))
+    b.sync()
+    # oracle check of a sample (every 8th stream) on the first tick
+    sample = list(range(0, 64, 8))
+    mism = 0
+    for i in sample:
+        h, w, c, n = specs[i]
+        want = oracle.PlcmKey(h, w, c, n, R, pms[i]).encrypt(
+            srcs[i].cpu().numpy().reshape(1, h, w, c), seeds[i][:1])
+        mism += int(np.count_nonzero(outs[i].cpu().numpy().reshape(want.shape) != want))
+    for t in range(1, warm):
+        b.run(items(t))
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(ticks + 1)]
+    t0 = time.perf_counter()
+    ev[0].record()
+    for t in range(warm, warm + ticks):
+        b.run(items(t))
+        ev[t - warm + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tick_ms = [ev[t].elapsed_time(ev[t + 1]) for t in range(ticks)]
+    info = b.info()
+    # the plain path on the same streams: one call per stream and frame
+    plain_keys = [B.Key(h, w, c, n, R, pm) for (h, w, c, n), pm in zip(specs, pms)]
+    for k, s_, o in zip(plain_keys, srcs, outs):
+        k.encrypt(s_, o, [1])
+    torch.cuda.synchronize()
+    reps = 2
+    t1 = time.perf_counter()
+    for rep in range(reps):
+        for k, s_, o, sc in zip(plain_keys, srcs, outs, seeds):
+            k.encrypt(s_, o, sc[rep:rep + 1])
+    torch.cuda.synchronize()
+    plain_wall = time.perf_counter() - t1
+    frames = 64 * ticks
+    return {
+        "workload": "64 streams, {480^2, 576^2, 768^2, 1920x1080}x3, n in {8,16,32}, one frame "
+                    "per stream per tick",
+        "frames_per_s": frames / wall, "ticks": ticks, "tick_ms_p50": pct(tick_ms, 50),
+        "tick_ms_p99": pct(tick_ms, 99), "deadline_ms": DEADLINE_MS,
+        "plain_frames_per_s": 64 * reps / plain_wall,
+        "speedup_vs_plain": (frames / wall) / (64 * reps / plain_wall),
+        "mb_per_s": sum(h * w * c for h, w, c, _ in specs) * ticks / wall / 1e6,
+        "shape": shape, "graph_replays": info["graph_replays"],
+        "oracle_sample_streams": len(sample), "oracle_mismatched_bytes": mism,
+    }
+
+
+def bench_served(B, torch, np, args):
+    """256 live streams with Poisson arrivals through the serving loop."""
+    import oracle
+    from paper_2302_07411_amd.inputs import (CorrelatedVideo, SERVED_SIZES, confusion_seeds,
+                                             plcm_key, poisson_arrivals, served_streams)
+    dev = torch.device("cuda:0")
+    N, RATE, Q = 256, 24.0, 8
+    secs = args.serve_seconds
+    specs = served_streams(N, 5005)
+    # one plaintext frame per resolution, and its cipher for the decrypting streams
+    plain, cipher = {}, {}
+    for j, (h, w) in enumerate(SERVED_SIZES):
+        n = next(s[3] for s in specs if s[:2] == (h, w))
+        plain[(h, w)] = CorrelatedVideo(h, w, 3, 9000 + j).frames_torch(0, 1, dev).reshape(-1)
+        cipher[(h, w)] = torch.empty_like(plain[(h, w)])
+        B.Key(h, w, 3, n, R, plcm_key(n, 9100 + j)).encrypt(plain[(h, w)], cipher[(h, w)], [1])
+    srv = B.Server(ring_frames=args.serve_ring, queue_frames=Q, split_cus=not args.serve_shared_cus)
+    streams, outs, pms, first_out = [], [], [], []
+    for i, (h, w, c, n, dec) in enumerate(specs):
+        pm = plcm_key(n, 9500 + i)
+        pms.append(pm)
+        streams.append(srv.open(h, w, c, n, R, pm, decrypt=dec))
+        outs.append([torch.empty(h * w * c, dtype=torch.uint8, device=dev) for _ in range(Q)])
+    sample = list(range(0, N, 20))  # about 5% of the streams: their first frame vs the oracle
+    first = {i: torch.empty(specs[i][0] * specs[i][1] * 3, dtype=torch.uint8, device=dev)
+             for i in sample}
+    seeds = [confusion_seeds(int(RATE * secs * 3) + 64, 9700 + i) for i in range(N)]
+    arrivals = poisson_arrivals(N, RATE, secs, 5006)
+    torch.cuda.synchronize()
+    time.sleep(0.5)  # let the keystream rings fill
+    nxt = [0] * N
+    tickets = []  # (stream, ticket, arrival, submit delay)
+    backlog = []
+    t0 = time.perf_counter()
+    k = 0
+    deferred = 0
+    while k < len(arrivals) or backlog:
+        now = time.perf_counter() - t0
+        while k < len(arrivals) and arrivals[k][0] <= now:
+            backlog.append(arrivals[k])
+            k += 1
+        keep = []
+        for (ta, i) in backlog:
+            t = nxt[i]
+            h, w, c, n, dec = specs[i]
+            src = cipher[(h, w)] if dec else plain[(h, w)]
+            out = first[i] if (t == 0 and i in first) else outs[i][t % Q]
+            tk = streams[i].try_submit(src, out, int(seeds[i][t]))
+            if tk is None:
+                keep.append((ta, i))
+                deferred += 1
+                continue
+            tickets.append((i, tk, ta, (time.perf_counter() - t0) - ta))
+            nxt[i] += 1
+        backlog = keep
+        if k < len(arrivals):
+            time.sleep(max(0.0, min(0.0005, arrivals[k][0] - (time.perf_counter() - t0))))
+        elif backlog:
+            time.sleep(0.0002)
+    srv.drain()
+    wall = time.perf_counter() - t0
+    lat = []
+    for i, tk, ta, delay in tickets:
+        done, l = streams[i].poll(tk)
+        lat.append(l + delay * 1e3)
+    stats = srv.stats()
+    mism = 0
+    for i in sample:
+        h, w, c, n, dec = specs[i]
+        src = (cipher if dec else plain)[(h, w)].cpu().numpy().reshape(1, h, w, c)
+        ref = oracle.PlcmKey(h, w, c, n, R, pms[i])
+        want = (ref.decrypt if dec else ref.encrypt)(src, seeds[i][:1])
+        mism += int(np.count_nonzero(first[i].cpu().numpy().reshape(want.shape) != want))
+    srv.close()
+    lat_np = np.asarray(lat)
+    return {
+        "workload": f"{N} streams, Poisson {RATE:g} frames/s each, "
+                    "{480^2, 576^2, 768^2, 1280x720, 1920x1080, 3840x2160}x3, n = smallest of "
+                    "8/16/32/64 with bands <= 800 KB, 20% decrypting",
+        "seconds": secs, "frames": len(tickets), "frames_per_s": len(tickets) / wall,
+        "offered_frames_per_s": len(arrivals) / secs,
+        "latency_ms_p50": pct(lat, 50), "latency_ms_p99": pct(lat, 99),
+        "latency_ms_max": float(lat_np.max()) if len(lat) else None,
+        "over_deadline": float(np.mean(lat_np > DEADLINE_MS)) if len(lat) else None,
+        "deadline_ms": DEADLINE_MS, "deferred_submits": deferred,
+        "rounds_ticks": stats["rounds_ticks"], "keystream_launches": stats["keystream_launches"],
+        "keystream_launch_ms_avg": stats["keystream_ms"] / max(1, stats["keystream_launches"]),
+        "rounds_tick_ms_avg": stats["rounds_ms"] / max(1, stats["rounds_ticks"]),
+        "frames_waiting_for_keystream": stats["starved_frames"],
+        "keystream_ring_gb": stats["hbm_used"] / 1e9,
+        "decrypt_streams": sum(1 for s in specs if s[4]),
+        "split_cus": bool(stats["split_cus"]), "ring_frames": args.serve_ring, "queue_frames": Q,
+        "oracle_sample_streams": len(sample), "oracle_mismatched_bytes": mism,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +262,14 @@ def main():
     ap.add_argument("--batch", type=int, default=48, help="frames per step (2 s of 24 FPS video)")
     ap.add_argument("--cpu-frames", type=int, default=120)
     ap.add_argument("--latency-frames", type=int, default=48)
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-stream batched workload")
+    ap.add_argument("--no-served", action="store_true", help="skip the 256-stream served workload")
+    ap.add_argument("--batched-ticks", type=int, default=20)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-ring", type=int, default=8,
+                    help="keystream frames generated ahead per served stream")
+    ap.add_argument("--serve-shared-cus", action="store_true",
+                    help="serve without splitting the CUs between keystream and rounds")
     ap.add_argument("--path", choices=["plain", "fused"], default="fused",
                     help="round implementation: one launch per round, or all rounds fused")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -220,8 +405,17 @@ def main():
         "roofline_prbg": roof_prbg,
         "cpu_baseline": cpu,
     }
+    bad = cpu is not None and cpu["parity_mismatched_bytes"]
+    if not args.no_batched:
+        print("[bench] batched workload", file=sys.stderr, flush=True)
+        out["batched"] = bench_batched(B, torch, np, args)
+        bad = bad or out["batched"]["oracle_mismatched_bytes"]
+    if not args.no_served:
+        print("[bench] served workload", file=sys.stderr, flush=True)
+        out["served"] = bench_served(B, torch, np, args)
+        bad = bad or out["served"]["oracle_mismatched_bytes"]
     print(json.dumps(out), flush=True)
-    if cpu is not None and cpu["parity_mismatched_bytes"]:
+    if bad:
         sys.exit(1)
 
 

@@ -324,8 +324,12 @@ cv_status cv_server_create(int device, size_t hbm_budget, cv_server **out);
 
 /* Ring depth (keystream frames generated ahead, >= 1) and queue depth
  * (frames a stream may have submitted and not finished, >= 1) for streams
- * opened after the call.  CV_E_INVAL if 0 or above 64. */
-cv_status cv_server_tune(cv_server *server, uint32_t ring_frames, uint32_t queue_frames);
+ * opened after the call; split_cus = 1 (the default) runs keystream
+ * generation on a quarter of the compute units of every XCD and the rounds
+ * on the rest, 0 lets both use every CU.  CV_E_INVAL if a depth is 0 or
+ * above 64; CV_E_STATE if split_cus changes while streams are open. */
+cv_status cv_server_tune(cv_server *server, uint32_t ring_frames, uint32_t queue_frames,
+                         int split_cus);
 
 /* Stop the worker after the submitted frames are done, close every stream
  * and release the server.  NULL is ignored. */
@@ -341,8 +345,11 @@ typedef struct {
   uint64_t keystream_launches;  /* keystream generation launches */
   uint64_t keystream_frames;    /* stream-frames of keystream generated */
   uint32_t open_streams;
-  uint32_t pad;
+  uint32_t split_cus;           /* 1 if keystream and rounds run on disjoint CUs */
   uint64_t hbm_used, hbm_budget; /* keystream ring bytes in use / allowed */
+  double keystream_ms;          /* summed launch-to-completion time of keystream launches */
+  double rounds_ms;             /* summed launch-to-completion time of rounds ticks */
+  uint64_t starved_frames;      /* frames that waited in the queue for their keystream */
 } cv_server_stats;
 
 cv_status cv_server_get_stats(cv_server *server, cv_server_stats *stats);

@@ -72,8 +72,10 @@ class CvBatchInfo(ct.Structure):
 class CvServerStats(ct.Structure):
     _fields_ = [("frames_done", ct.c_uint64), ("rounds_ticks", ct.c_uint64),
                 ("keystream_launches", ct.c_uint64), ("keystream_frames", ct.c_uint64),
-                ("open_streams", ct.c_uint32), ("pad", ct.c_uint32),
-                ("hbm_used", ct.c_uint64), ("hbm_budget", ct.c_uint64)]
+                ("open_streams", ct.c_uint32), ("split_cus", ct.c_uint32),
+                ("hbm_used", ct.c_uint64), ("hbm_budget", ct.c_uint64),
+                ("keystream_ms", ct.c_double), ("rounds_ms", ct.c_double),
+                ("starved_frames", ct.c_uint64)]
 
 
 class CvError(RuntimeError):
@@ -149,7 +151,7 @@ def load() -> ct.CDLL:
     L.cv_server_create.restype = ct.c_int
     L.cv_server_create.argtypes = [ct.c_int, sz, ct.POINTER(vp)]
     L.cv_server_tune.restype = ct.c_int
-    L.cv_server_tune.argtypes = [vp, ct.c_uint32, ct.c_uint32]
+    L.cv_server_tune.argtypes = [vp, ct.c_uint32, ct.c_uint32, ct.c_int]
     L.cv_server_free.restype = None
     L.cv_server_free.argtypes = [vp]
     L.cv_server_drain.restype = ct.c_int
@@ -372,13 +374,13 @@ class Server:
     rounds ticks by a worker thread, keystream generated ahead."""
 
     def __init__(self, device: int = 0, hbm_budget: int = 0, ring_frames: int = None,
-                 queue_frames: int = None):
+                 queue_frames: int = None, split_cus: bool = True):
         h = ct.c_void_p()
         _check(load().cv_server_create(device, hbm_budget, ct.byref(h)))
         self._h = h
         self._streams = []
-        if ring_frames is not None or queue_frames is not None:
-            _check(load().cv_server_tune(self._h, ring_frames or 3, queue_frames or 8))
+        _check(load().cv_server_tune(self._h, ring_frames or 3, queue_frames or 8,
+                                     int(bool(split_cus))))
 
     def open(self, H, W, C, n, r, pm, decrypt: bool = False) -> "ServerStream":
         pm = np.ascontiguousarray(np.asarray(pm, np.float64).reshape(-1))
@@ -397,7 +399,7 @@ class Server:
     def stats(self) -> dict:
         st = CvServerStats()
         _check(load().cv_server_get_stats(self._h, ct.byref(st)))
-        return {f: getattr(st, f) for f, _ in CvServerStats._fields_ if f != "pad"}
+        return {f: getattr(st, f) for f, _ in CvServerStats._fields_}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -400,6 +401,28 @@ cv_status crypt_frames(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
 
 bool finite_in(double v, double lo, double hi) { return isfinite(v) && v > lo && v < hi; }
 
+// Blocking host<->device copy on a private non-blocking stream of the current
+// device, so that it waits for no other stream (the legacy null stream would
+// wait for every blocking stream, compute-unit-masked ones included).
+hipError_t copy_sync(void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+  static std::mutex mu;
+  static std::vector<hipStream_t> streams;  // per device
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  hipStream_t st = nullptr;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
+    if (!streams[dev] && (e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking)) != hipSuccess)
+      return e;
+    st = streams[dev];
+  }
+  e = hipMemcpyAsync(dst, src, bytes, kind, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e;
+}
+
 }  // namespace rt
 }  // namespace cv
 
@@ -489,10 +512,10 @@ cv_status cv_keysetup(const cv_geom* geom, cv_map map, const double* p_m, size_t
     c.frame_stride = (uint64_t)g.r * k->F;
     c.nbytes = (uint64_t)g.r * (hi - lo) * row;
   }
-  hipError_t e = hipMemcpy(k->d_state, state.data(), state.size() * sizeof(double),
+  hipError_t e = copy_sync(k->d_state, state.data(), state.size() * sizeof(double),
                            hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = hipMemcpy(k->d_chains, chains.data(), chains.size() * sizeof(cv::PlcmChain),
+    e = copy_sync(k->d_chains, chains.data(), chains.size() * sizeof(cv::PlcmChain),
                   hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&k->gm_done, hipEventDisableTiming);
   k->h_chains = chains;

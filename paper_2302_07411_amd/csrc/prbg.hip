@@ -234,6 +234,9 @@ __global__ __launch_bounds__(128) void prbg_plcm_kernel(const PlcmChain* __restr
   const ChainPlan cp = plan(ch, n_frames);
   const uint32_t total_max = wave_max(has ? cp.total : 0u);  // same in both wavefronts
   const uint32_t nblk = (total_max + kBlock - 1) / kBlock;
+  // Both wavefronts run a latency-bound chain: ask the SIMD arbiter to issue
+  // them ahead of throughput work (a rounds kernel) sharing the compute unit.
+  __builtin_amdgcn_s_setprio(3);
 
   if (wave == 0) {
     const uint32_t m = (lane / (kLanes / 2)) & 1u;

@@ -106,6 +106,7 @@ struct Part {
 
 struct Tick {
   hipEvent_t ev = nullptr;
+  Clock::time_point t_launch;
   bool batched = false;
   std::vector<Part> parts;
 };
@@ -132,12 +133,14 @@ struct cv_stream {
   std::vector<double> lat;    // latency (ms) of ticket t at t % kLatencyLog
   bool closing = false;
   bool in_ks_launch = false;
+  uint64_t starved_mark = 0;  // tickets below this were counted as starved
 };
 
 struct cv_server {
   int device = 0;
   size_t lds_max = 0;
   uint32_t ring_frames = 3, queue_frames = 8;
+  bool split = false;      // keystream and rounds on disjoint compute units
   uint8_t* arena_mem = nullptr;
   Arena arena;
   cv_batch* rb = nullptr;  // rounds ticks
@@ -154,6 +157,7 @@ struct cv_server {
   std::vector<cv_stream*> streams;
   std::vector<std::pair<cv_stream*, uint32_t>> ks_launch;  // in flight
   bool ks_busy = false;
+  Clock::time_point ks_launch_t;
   std::deque<Tick> ticks;
   cv_server_stats stats{};
 };
@@ -203,6 +207,11 @@ void plan_keystream(cv_server* S, std::vector<ChainJob>& cj) {
 void plan_rounds(cv_server* S, std::vector<FrameJob>& fj, std::vector<Pending>& solo,
                  std::vector<cv_stream*>& solo_st, Tick& t) {
   for (cv_stream* st : S->streams) {
+    for (const Pending& p : st->queue) {
+      if (p.ticket < st->ks_ready || p.ticket < st->starved_mark) continue;
+      st->starved_mark = p.ticket + 1;  // counted once
+      S->stats.starved_frames++;
+    }
     while (!st->queue.empty() && st->queue.front().ticket < st->ks_ready) {
       const Pending p = st->queue.front();
       st->queue.pop_front();
@@ -238,6 +247,46 @@ cv_status run_solo(cv_server* S, const std::vector<Pending>& solo,
 
 // Release a stream's ring (mutex held) and then, with the mutex released,
 // its key.
+// The server's two HIP streams.  With `split`, the keystream stream may use a
+// quarter of the compute units of every XCD (mask bits i with (i/8) % 4 == 0:
+// eight CUs per XCD whether consecutive mask bits walk the CUs of one XCD or
+// alternate between XCDs) and the rounds stream the rest, so that neither
+// kernel slows the other's wavefronts; the rounds launch is then sized for
+// the CUs it has.
+hipError_t make_streams(cv_server* S, bool split) {
+  if (S->s_rounds) (void)hipStreamDestroy(S->s_rounds);
+  if (S->s_ks) (void)hipStreamDestroy(S->s_ks);
+  S->s_rounds = S->s_ks = nullptr;
+  int cus = 0;
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->device);
+  if (e != hipSuccess) return e;
+  cv_batch_shape shape{kThreads, 8, 0, 0};
+  S->split = split && cus >= 64 && cus % 32 == 0;
+  if (S->split) {
+    std::vector<uint32_t> ks((cus + 31) / 32, 0), rd((cus + 31) / 32, 0);
+    for (int i = 0; i < cus; i++) ((i / 8) % 4 == 0 ? ks : rd)[i / 32] |= 1u << (i % 32);
+    e = hipExtStreamCreateWithCUMask(&S->s_ks, (uint32_t)ks.size(), ks.data());
+    if (e == hipSuccess) e = hipExtStreamCreateWithCUMask(&S->s_rounds, (uint32_t)rd.size(), rd.data());
+    if (e != hipSuccess) {  // masks not supported here: share the CUs
+      (void)hipGetLastError();
+      if (S->s_ks) (void)hipStreamDestroy(S->s_ks);
+      if (S->s_rounds) (void)hipStreamDestroy(S->s_rounds);
+      S->s_ks = S->s_rounds = nullptr;
+      S->split = false;
+    } else {
+      // one 1024-thread workgroup per CU: groups of 8 on the rounds CUs of each XCD
+      shape.max_groups = 8 * ((uint32_t)(cus * 3 / 4) / 8 / shape.group_wgs);
+    }
+  }
+  if (!S->split) {
+    e = hipStreamCreateWithFlags(&S->s_ks, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->s_rounds, hipStreamNonBlocking);
+  }
+  (void)cv_batch_set_shape(S->rb, &shape);
+  (void)cv_batch_set_shape(S->kb, &shape);
+  return e;
+}
+
 void free_stream(cv_server* S, cv_stream* st, std::unique_lock<std::mutex>* lk) {
   S->arena.release(st->ring_off, st->ring_bytes);
   if (lk) lk->unlock();
@@ -259,6 +308,8 @@ void worker_main(cv_server* S) {
       }
       S->ks_launch.clear();
       S->ks_busy = false;
+      S->stats.keystream_ms +=
+          std::chrono::duration<double, std::milli>(Clock::now() - S->ks_launch_t).count();
       progressed = true;
     }
     // rounds ticks done, in order
@@ -273,6 +324,7 @@ void worker_main(cv_server* S) {
         p.st->completed++;
       }
       S->stats.frames_done += t.parts.size();
+      S->stats.rounds_ms += std::chrono::duration<double, std::milli>(now - t.t_launch).count();
       S->ev_pool.push_back(t.ev);
       S->ticks.pop_front();
       progressed = true;
@@ -299,6 +351,7 @@ void worker_main(cv_server* S) {
       plan_rounds(S, fj, solo, solo_st, t);
       if (!t.parts.empty()) {
         t.ev = take_event(S);
+        t.t_launch = Clock::now();
         t.batched = !fj.empty();
         lk.unlock();
         cv_status s = run_solo(S, solo, solo_st);
@@ -321,6 +374,7 @@ void worker_main(cv_server* S) {
       if (!cj.empty()) {
         uint64_t frames = 0;
         for (auto& c : cj) frames += c.frames;
+        S->ks_launch_t = Clock::now();
         lk.unlock();
         cv_status s = batch_enqueue(S->kb, cj, {}, S->arena_mem, S->s_ks);
         std::string msg = s != CV_OK ? cv_last_error() : "";
@@ -411,13 +465,8 @@ cv_status cv_server_create(int device, size_t hbm_budget, cv_server** out) {
     destroy(S);
     return s;
   }
-  // ticks change shape every time: launch kernel by kernel; groups of 8
-  // workgroups leave room on every CU for the keystream launch alongside
-  cv_batch_shape shape{kThreads, 8, 0, 0};
-  (void)cv_batch_set_shape(S->rb, &shape);
-  (void)cv_batch_set_shape(S->kb, &shape);
-  hipError_t e = hipStreamCreateWithFlags(&S->s_rounds, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->s_ks, hipStreamNonBlocking);
+  // ticks change shape every time: launch kernel by kernel, groups of 8
+  hipError_t e = make_streams(S, true);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ks_ev, hipEventDisableTiming);
   if (e != hipSuccess) {
     destroy(S);
@@ -435,11 +484,25 @@ cv_status cv_server_create(int device, size_t hbm_budget, cv_server** out) {
   return CV_OK;
 }
 
-cv_status cv_server_tune(cv_server* S, uint32_t ring_frames, uint32_t queue_frames) {
+cv_status cv_server_tune(cv_server* S, uint32_t ring_frames, uint32_t queue_frames,
+                         int split_cus) {
   if (!S) return fail(CV_E_INVAL, "server is NULL");
   if (ring_frames < 1 || ring_frames > 64 || queue_frames < 1 || queue_frames > 64)
     return fail(CV_E_INVAL, "ring_frames and queue_frames must be in 1..64");
+  if (split_cus != 0 && split_cus != 1) return fail(CV_E_INVAL, "split_cus must be 0 or 1");
   std::lock_guard<std::mutex> g(S->mu);
+  if (split_cus != (int)S->split) {
+    if (!S->streams.empty() || S->ks_busy || !S->ticks.empty())
+      return fail(CV_E_STATE, "the compute-unit split can change only with no stream open");
+    DeviceGuard dg(S->device);
+    (void)hipStreamSynchronize(S->s_ks);
+    (void)hipStreamSynchronize(S->s_rounds);
+    hipError_t e = make_streams(S, split_cus != 0);
+    if (e != hipSuccess) {
+      set_error(S, CV_E_HIP, "stream creation failed");
+      return hip_fail(e, "cv_server_tune");
+    }
+  }
   S->ring_frames = ring_frames;
   S->queue_frames = queue_frames;
   return CV_OK;
@@ -468,6 +531,7 @@ cv_status cv_server_get_stats(cv_server* S, cv_server_stats* stats) {
   std::lock_guard<std::mutex> g(S->mu);
   *stats = S->stats;
   stats->open_streams = (uint32_t)S->streams.size();
+  stats->split_cus = S->split;
   stats->hbm_used = S->arena.used();
   return CV_OK;
 }

@@ -124,6 +124,50 @@ WORKLOADS = {
 }
 
 
+def batched_streams(count: int, seed: int):
+    """Multi-stream tick workload: per stream (H, W, C, n), resolution uniform
+    over 480^2, 576^2, 768^2 and 1920x1080 (3 channels), n uniform over
+    8/16/32."""
+    r = _rng(seed)
+    sizes = [(480, 480), (576, 576), (768, 768), (1080, 1920)]
+    out = []
+    for _ in range(count):
+        H, W = sizes[int(r.integers(0, len(sizes)))]
+        out.append((H, W, 3, int((8, 16, 32)[int(r.integers(0, 3))])))
+    return out
+
+
+SERVED_SIZES = [(480, 480), (576, 576), (768, 768), (720, 1280), (1080, 1920), (2160, 3840)]
+
+
+def served_streams(count: int, seed: int, decrypt_share: float = 0.2):
+    """Serving workload: per stream (H, W, C, n, decrypt), resolution uniform
+    over SERVED_SIZES (3 channels), n the smallest of 8/16/32/64 whose
+    tallest band holds at most 800 KB, and a decrypt_share of the streams
+    decrypting."""
+    r = _rng(seed)
+    out = []
+    for _ in range(count):
+        H, W = SERVED_SIZES[int(r.integers(0, len(SERVED_SIZES)))]
+        n = next(n for n in (8, 16, 32, 64) if -(-H // n) * W * 3 <= 800_000)
+        out.append((H, W, 3, n, bool(r.random() < decrypt_share)))
+    return out
+
+
+def poisson_arrivals(count: int, rate: float, seconds: float, seed: int):
+    """Arrival times of `count` independent Poisson streams of `rate` frames
+    per second over `seconds`: a list of (time, stream) sorted by time."""
+    r = _rng(seed)
+    ev = []
+    for s in range(count):
+        t = r.exponential(1.0 / rate)
+        while t < seconds:
+            ev.append((t, s))
+            t += r.exponential(1.0 / rate)
+    ev.sort()
+    return ev
+
+
 def adjacent_correlation(frame: np.ndarray, axis: int) -> float:
     """Pearson correlation of horizontally (axis=1) or vertically (axis=0)
     adjacent pixel values over all channels; used to validate the generator."""
