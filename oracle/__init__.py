@@ -8,7 +8,8 @@ generator).  Only the test suite, ``__graft_entry__.smoke()`` and the
 loads it, and the two share no code.
 
 Pins (tests/test_oracle_*.py): exact-rational PLCM orbits, the special
-orbits of Eq. (5), hand-traced confusion and diffusion fixtures
+orbits of Eq. (5), the 2DLASM sine against mpmath and the special orbits
+and reductions of Eq. (6), hand-traced confusion and diffusion fixtures
 (tests/golden/), the skew/row-rotation factorisation of Eq. (1), the
 prefix-XOR closed form of Eq. (3), high-precision g tables, round trips,
 bijection/histogram invariants, and the NPCR/UACI and error-propagation
@@ -36,7 +37,7 @@ def build(force: bool = True) -> str:
     """Compile oracle.c into liboracle.so with gcc and return its path."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lquadmath", "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -77,6 +78,20 @@ def lib() -> ct.CDLL:
             f.restype = ct.c_int
             f.argtypes = [u32, u32, u32, u32, u32, dp, dp, dp, dp, u8p, u8p,
                           ct.POINTER(ct.c_uint32), ct.c_uint64]
+        L.oracle_cr_sin_margin.restype = ct.c_int
+        L.oracle_cr_sin_margin.argtypes = [ct.c_double, dp, ct.c_int]
+        L.oracle_cr_sin.restype = ct.c_int
+        L.oracle_cr_sin.argtypes = [ct.c_double, dp]
+        L.oracle_lasm.restype = ct.c_int
+        L.oracle_lasm.argtypes = [dp, dp, ct.c_double]
+        L.oracle_lasm_bytes.restype = ct.c_int
+        L.oracle_lasm_bytes.argtypes = [dp, dp, ct.c_double, dp, dp, ct.c_double, ct.c_uint64, u8p]
+        L.oracle_lasm_keystream.restype = ct.c_int
+        L.oracle_lasm_keystream.argtypes = [u32, u32, u32, u32, u32, dp, dp, dp, dp, dp, dp,
+                                            ct.c_uint64, u8p]
+        L.oracle_rounds.restype = ct.c_int
+        L.oracle_rounds.argtypes = [u32, u32, u32, u32, u32, ct.c_int, u8p, u8p, u8p,
+                                    ct.POINTER(ct.c_uint32), ct.c_uint64]
         _lib = L
     return _lib
 
@@ -105,6 +120,37 @@ def plcm_bytes(x1: float, p1: float, x2: float, p2: float, nbytes: int):
     out = np.zeros(nbytes, np.uint8)
     lib().oracle_plcm_bytes(ct.byref(a), p1, ct.byref(b), p2, nbytes, _u8(out))
     return out, a.value, b.value
+
+
+class Undecided(ArithmeticError):
+    """A sine value too close to a binary64 rounding boundary to round."""
+
+
+def cr_sin(t: float) -> float:
+    """RN(sin(t)), binary128 evaluation rounded once (Sec. 3, Eq. (6)'s sine)."""
+    out = ct.c_double()
+    if lib().oracle_cr_sin(t, ct.byref(out)):
+        raise Undecided(t)
+    return out.value
+
+
+def lasm(x: float, y: float, mu: float):
+    """Eq. (6), one step of one map: returns (x', y')."""
+    a, b = ct.c_double(x), ct.c_double(y)
+    if lib().oracle_lasm(ct.byref(a), ct.byref(b), mu):
+        raise Undecided((x, y, mu))
+    return a.value, b.value
+
+
+def lasm_bytes(m1, m2, nbytes: int):
+    """2DLASM byte generator (Sec. 3) for maps m1, m2 = (x, y, mu).  Returns
+    (bytes, (x1', y1'), (x2', y2'))."""
+    x1, y1, x2, y2 = (ct.c_double(v) for v in (m1[0], m1[1], m2[0], m2[1]))
+    out = np.zeros(nbytes, np.uint8)
+    if lib().oracle_lasm_bytes(ct.byref(x1), ct.byref(y1), m1[2], ct.byref(x2), ct.byref(y2),
+                               m2[2], nbytes, _u8(out)):
+        raise Undecided((m1, m2))
+    return out, (x1.value, y1.value), (x2.value, y2.value)
 
 
 def band_lo(H: int, n: int, i: int) -> int:
@@ -202,3 +248,51 @@ class PlcmKey:
 
     def decrypt(self, frames, s_c) -> np.ndarray:
         return self._run(lib().oracle_decrypt, frames, s_c)
+
+
+class LasmKey:
+    """2DLASM key state of one stream: per band two maps (x, y, mu); the
+    states advance with every frame.  `pm` is (n, 6): x0_1, y0_1, mu_1,
+    x0_2, y0_2, mu_2."""
+
+    def __init__(self, H, W, C, n, r, pm):
+        pm = np.asarray(pm, np.float64).reshape(n, 6)
+        self.geom = (H, W, C, n, r)
+        self.x1 = np.ascontiguousarray(pm[:, 0].copy())
+        self.y1 = np.ascontiguousarray(pm[:, 1].copy())
+        self.mu1 = np.ascontiguousarray(pm[:, 2].copy())
+        self.x2 = np.ascontiguousarray(pm[:, 3].copy())
+        self.y2 = np.ascontiguousarray(pm[:, 4].copy())
+        self.mu2 = np.ascontiguousarray(pm[:, 5].copy())
+
+    def state(self) -> np.ndarray:
+        """(n, 4): x_1, y_1, x_2, y_2 per band."""
+        return np.stack([self.x1, self.y1, self.x2, self.y2], axis=1)
+
+    def keystream(self, T: int) -> np.ndarray:
+        H, W, C, n, r = self.geom
+        ks = np.zeros(T * r * H * W * C, np.uint8)
+        if lib().oracle_lasm_keystream(H, W, C, n, r, _f64(self.x1), _f64(self.y1),
+                                       _f64(self.mu1), _f64(self.x2), _f64(self.y2),
+                                       _f64(self.mu2), T, _u8(ks)):
+            raise Undecided("keystream")
+        return ks.reshape(T, r * H * W * C)
+
+    def _rounds(self, decrypt, frames, s_c):
+        H, W, C, n, r = self.geom
+        frames = np.ascontiguousarray(frames, np.uint8).reshape(-1, H, W, C)
+        T = frames.shape[0]
+        s_c = np.ascontiguousarray(np.asarray(s_c, np.uint32).reshape(-1))
+        assert s_c.size == T
+        ks = np.ascontiguousarray(self.keystream(T).reshape(-1))
+        out = np.zeros_like(frames)
+        if lib().oracle_rounds(H, W, C, n, r, int(decrypt), _u8(ks), _u8(frames), _u8(out),
+                               s_c.ctypes.data_as(ct.POINTER(ct.c_uint32)), T):
+            raise MemoryError("oracle allocation failed")
+        return out
+
+    def encrypt(self, frames, s_c) -> np.ndarray:
+        return self._rounds(False, frames, s_c)
+
+    def decrypt(self, frames, s_c) -> np.ndarray:
+        return self._rounds(True, frames, s_c)

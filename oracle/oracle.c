@@ -12,6 +12,9 @@
  *   - Sec. 3, Eq. (5): the piecewise linear chaotic map (PLCM);
  *   - Sec. 3, PLCM byte extraction (two PLCMs, 6 mantissa bytes of every
  *     iterate, the two byte sets XORed);
+ *   - Sec. 3, Eq. (6): the 2D logistic-adjusted-sine map (2DLASM) and its
+ *     byte extraction (two maps, 6 bytes of every x and every y iterate,
+ *     XORed between the maps);
  *   - Sec. 2, Eq. (1) and Algorithm 2: confusion (discretised Chirikov map);
  *   - Sec. 2, Eq. (2): inverse confusion;
  *   - Sec. 2, Eq. (3) and Algorithm 2: diffusion with the seed taken from
@@ -32,11 +35,18 @@
  *   bit pattern; the keystream of band i for one frame is the first r*S_i
  *   bytes of ceil(r*S_i/6) steps, round j consuming bytes [j*S_i,(j+1)*S_i).
  *
+ * For Eq. (6) the oracle reads the products left to right,
+ * (((pi*mu)*(y+3))*x)*(1-x) with pi = M_PI, and takes the sine correctly
+ * rounded (RN(sin(t))): the sine is evaluated in binary128 by libquadmath
+ * and rounded once to binary64; a value so close to a rounding boundary
+ * that binary128 cannot decide it is reported, never guessed.
+ *
  * Build: gcc -std=c11 -O2 -ffp-contract=off -fno-fast-math (SSE2 binary64,
- * no FMA contraction), so every floating-point operation below is a single
- * correctly rounded IEEE-754 operation.
+ * no FMA contraction) -lquadmath, so every binary64 operation below is a
+ * single correctly rounded IEEE-754 operation.
  */
 #include <math.h>
+#include <quadmath.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -81,6 +91,72 @@ void oracle_plcm_bytes(double *x1, double p1, double *x2, double p2,
         for (int k = 0; k < 6 && made < nbytes; k++)
             out[made++] = (uint8_t)(((u >> (8 * k)) & 0xFF) ^ ((v >> (8 * k)) & 0xFF));
     }
+}
+
+/* -------------------------------------------------------------- 2DLASM --- */
+
+/* RN(sin(t)): sinq is accurate to about one binary128 ulp (2^-112 relative),
+ * so rounding its value to binary64 gives the correctly rounded sine unless
+ * it lies within 2^-100 of a binary64 midpoint; then 1 is returned and the
+ * result must not be trusted.  (The margin is a parameter of the first
+ * function only so that the test suite can exercise the check.) */
+int oracle_cr_sin_margin(double t, double *out, int log2_margin)
+{
+    __float128 s = sinq((__float128)t);
+    double d = (double)s;
+    *out = d;
+    if (s == 0)
+        return 0;
+    __float128 up = (__float128)nextafter(d, INFINITY);
+    __float128 dn = (__float128)nextafter(d, -INFINITY);
+    __float128 m_up = ((__float128)d + up) / 2, m_dn = ((__float128)d + dn) / 2;
+    __float128 tol = fabsq(s) * ldexpq(1.0Q, log2_margin);
+    return (fabsq(s - m_up) <= tol || fabsq(s - m_dn) <= tol) ? 1 : 0;
+}
+
+int oracle_cr_sin(double t, double *out)
+{
+    return oracle_cr_sin_margin(t, out, -100);
+}
+
+/* Sec. 3, Eq. (6): x' = sin(pi*mu*(y+3)*x*(1-x)), then
+ * y' = sin(pi*mu*(x'+3)*y*(1-y)) -- the new x enters the y update.
+ * Returns 1 (state unchanged) if a sine could not be rounded with certainty. */
+int oracle_lasm(double *x, double *y, double mu)
+{
+    double nx, ny;
+    double ax = (((M_PI * mu) * (*y + 3.0)) * *x) * (1.0 - *x);
+    if (oracle_cr_sin(ax, &nx))
+        return 1;
+    double ay = (((M_PI * mu) * (nx + 3.0)) * *y) * (1.0 - *y);
+    if (oracle_cr_sin(ay, &ny))
+        return 1;
+    *x = nx;
+    *y = ny;
+    return 0;
+}
+
+/* Sec. 3, 2DLASM byte generator: per step both maps advance once; the
+ * iterates are taken in the order x_1, y_1, x_2, y_2, ..., 6 bytes of each
+ * (bytes 0..5 of the binary64 pattern), the bytes of map 1 XORed with those
+ * of map 2: 12 bytes per step.  Writes exactly nbytes (the rest of the last
+ * step is dropped); advances both maps by ceil(nbytes/12) steps.  Returns 1
+ * if a sine could not be rounded with certainty. */
+int oracle_lasm_bytes(double *x1, double *y1, double mu1, double *x2, double *y2,
+                      double mu2, uint64_t nbytes, uint8_t *out)
+{
+    uint64_t k = 0;
+    while (k < nbytes) {
+        if (oracle_lasm(x1, y1, mu1) || oracle_lasm(x2, y2, mu2))
+            return 1;
+        uint64_t bx = bits_of(*x1) ^ bits_of(*x2);
+        uint64_t by = bits_of(*y1) ^ bits_of(*y2);
+        for (int b = 0; b < 6 && k < nbytes; b++)
+            out[k++] = (uint8_t)(bx >> (8 * b));
+        for (int b = 0; b < 6 && k < nbytes; b++)
+            out[k++] = (uint8_t)(by >> (8 * b));
+    }
+    return 0;
 }
 
 /* ------------------------------------------------------------ geometry --- */
@@ -212,6 +288,61 @@ void oracle_plcm_keystream(uint32_t H, uint32_t W, uint32_t C, uint32_t n,
             oracle_plcm_bytes(&x1[i], p1[i], &x2[i], p2[i], (uint64_t)r * S,
                               ks + t * (uint64_t)r * F + (uint64_t)r * lo);
         }
+}
+
+/* The 2DLASM keystream of T frames in the layout of oracle_plcm_keystream;
+ * each band's records (x1,y1,mu1,x2,y2,mu2) advance.  Returns 1 if a sine
+ * could not be rounded with certainty. */
+int oracle_lasm_keystream(uint32_t H, uint32_t W, uint32_t C, uint32_t n, uint32_t r,
+                          double *x1, double *y1, const double *mu1, double *x2,
+                          double *y2, const double *mu2, uint64_t T, uint8_t *ks)
+{
+    uint64_t row = (uint64_t)W * C, F = (uint64_t)H * row;
+    for (uint64_t t = 0; t < T; t++)
+        for (uint32_t i = 0; i < n; i++) {
+            uint64_t lo = oracle_band_lo(H, n, i) * row;
+            uint64_t S = oracle_band_lo(H, n, i + 1) * row - lo;
+            if (oracle_lasm_bytes(&x1[i], &y1[i], mu1[i], &x2[i], &y2[i], mu2[i],
+                                  (uint64_t)r * S, ks + t * (uint64_t)r * F + (uint64_t)r * lo))
+                return 1;
+        }
+    return 0;
+}
+
+/* The rounds of Algorithm 2 for T frames whose keystream is given (r*F
+ * bytes per frame): encryption confuses (Eq. 1) then diffuses (Eq. 3) r
+ * times; decryption undoes diffusion (Eq. 4) then confusion (Eq. 2) in
+ * reverse round order. */
+int oracle_rounds(uint32_t H, uint32_t W, uint32_t C, uint32_t n, uint32_t r, int decrypt,
+                  const uint8_t *ks, const uint8_t *in, uint8_t *out, const uint32_t *s_c,
+                  uint64_t T)
+{
+    uint64_t F = (uint64_t)H * W * C;
+    uint8_t *A = malloc(F), *Y = malloc(F);
+    int64_t *g = malloc(sizeof(int64_t) * H);
+    if (!A || !Y || !g) {
+        free(A); free(Y); free(g);
+        return -1;
+    }
+    for (uint64_t t = 0; t < T; t++) {
+        const uint8_t *k = ks + t * (uint64_t)r * F;
+        oracle_gtable(H, s_c[t], g);
+        memcpy(A, in + t * F, F);
+        if (!decrypt) {
+            for (uint32_t j = 0; j < r; j++) {
+                oracle_confuse(A, Y, H, W, C, g);
+                oracle_diffuse(Y, A, H, W, C, n, r, j, k);
+            }
+        } else {
+            for (uint32_t jj = r; jj-- > 0;) {
+                oracle_undiffuse(A, Y, H, W, C, n, r, jj, k);
+                oracle_unconfuse(Y, A, H, W, C, g);
+            }
+        }
+        memcpy(out + t * F, A, F);
+    }
+    free(A); free(Y); free(g);
+    return 0;
 }
 
 /* Algorithms 1 and 2: for every frame, generate the keystream, then r times

@@ -111,6 +111,25 @@ def plcm_key(n: int, seed: int) -> np.ndarray:
     return pm
 
 
+# Admissible control parameters of the 2DLASM (Sec. 3, Eq. (6)).
+LASM_MU_RANGES = [(0.37, 0.38), (0.4, 0.42), (0.44, 0.93)]
+
+
+def lasm_key(n: int, seed: int) -> np.ndarray:
+    """n 2DLASM key records (x0_1, y0_1, mu_1, x0_2, y0_2, mu_2) as an (n, 6)
+    float64 array: initial values in (0,1), mu uniform over the admissible
+    intervals (weighted by length)."""
+    r = _rng(seed)
+    pm = np.empty((n, 6), np.float64)
+    lens = np.array([b - a for a, b in LASM_MU_RANGES])
+    for m in range(2):
+        pm[:, 3 * m] = _open_uniform(r, 0.0, 1.0, n)
+        pm[:, 3 * m + 1] = _open_uniform(r, 0.0, 1.0, n)
+        k = r.choice(len(LASM_MU_RANGES), size=n, p=lens / lens.sum())
+        pm[:, 3 * m + 2] = [r.uniform(*LASM_MU_RANGES[i]) for i in k]
+    return pm
+
+
 def confusion_seeds(T: int, seed: int) -> np.ndarray:
     """One confusion seed per frame, uniform on 1..65535."""
     return _rng(seed + 7919).integers(1, 65536, size=T, dtype=np.uint32)
