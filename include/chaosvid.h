@@ -27,7 +27,12 @@
  *    binary64 iterate, XORed between the two maps; the first iterate x_1 is
  *    the first one used; per frame band i takes the first r*S_i bytes of
  *    ceil(r*S_i/6) steps (S_i = bytes of band i), round j using bytes
- *    [j*S_i, (j+1)*S_i).
+ *    [j*S_i, (j+1)*S_i);
+ *  - a 2DLASM step computes x' = sin(((pi*mu)*(y+3))*x*(1-x)) and then
+ *    y' = sin(((pi*mu)*(x'+3))*y*(1-y)) in binary64 from left to right
+ *    (pi = M_PI) with the sine correctly rounded, and emits bytes 0..5 of
+ *    x'(map 1) XOR x'(map 2), then bytes 0..5 of y'(map 1) XOR y'(map 2):
+ *    12 bytes per step, ceil(r*S_i/12) steps per band and frame.
  *
  * Conventions.  All functions return cv_status; no C++ exception crosses the
  * ABI.  On error the key state is unchanged and cv_last_error() (thread
@@ -59,7 +64,8 @@ typedef enum {
 } cv_status;
 
 typedef enum {
-  CV_MAP_PLCM = 0 /* two piecewise linear chaotic maps per band (Sec. 3, Eq. 5) */
+  CV_MAP_PLCM = 0,  /* two piecewise linear chaotic maps per band (Sec. 3, Eq. 5) */
+  CV_MAP_2DLASM = 1 /* two 2D logistic-adjusted-sine maps per band (Sec. 3, Eq. 6) */
 } cv_map;
 
 /* Round implementation used by cv_encrypt_frames / cv_decrypt_frames.
@@ -113,24 +119,37 @@ const char *cv_last_error(void);
  * "Initialize PRBG_a^i with p_m^i"; Sec. 3, Eq. 5).
  *  geom      frame geometry; requires H,W,C,n,r >= 1, n <= H, every band at
  *            least 2 bytes, H*W*C < 2^32 per row block limits of uint32.
- *  map       CV_MAP_PLCM.
- *  p_m       host array of n records {x0_1, p_1, x0_2, p_2} (map 1, map 2);
- *            x0 in (0,1), p in (0,1/2), all finite.
- *  n_doubles 4*n.
+ *  map       CV_MAP_PLCM or CV_MAP_2DLASM.
+ *  p_m       host array of n records: PLCM {x0_1, p_1, x0_2, p_2} with x0 in
+ *            (0,1), p in (0,1/2); 2DLASM {x0_1, y0_1, mu_1, x0_2, y0_2, mu_2}
+ *            with x0, y0 in (0,1) and mu in [0.37,0.38], [0.4,0.42],
+ *            [0.44,0.93] or {1} (Sec. 3, Eq. 6); all finite.
+ *  n_doubles 4*n (PLCM) or 6*n (2DLASM).
  *  device    HIP device ordinal the key lives on.
  *  out       receives the key (owned by the caller, release with cv_key_free).
  * Errors: CV_E_INVAL for any violated requirement, CV_E_NOMEM, CV_E_HIP. */
 cv_status cv_keysetup(const cv_geom *geom, cv_map map, const double *p_m, size_t n_doubles,
                       int device, cv_key **out);
 
+/* The correctly rounded binary64 sine of the 2DLASM generator, RN(sin(t)),
+ * exported so that it can be checked against an independent reference.
+ * t, out: device arrays of n doubles, each t in [0, RN(pi)] (the range of
+ * Eq. 6's arguments).  force_exact = 1 evaluates every argument >= 2^-30 on
+ * the 256-bit exact path instead of the double-double fast path.
+ * *undecided (a device word the caller zeroes) is set to 1 if a value could
+ * not be rounded with certainty.  Errors: CV_E_INVAL (NULL), CV_E_HIP. */
+cv_status cv_cr_sin(const double *t, double *out, size_t n, int force_exact, uint32_t *undecided,
+                    void *stream);
+
 /* Release a key and its device memory (synchronises the device first).
  * NULL is ignored. */
 void cv_key_free(cv_key *key);
 
 /* Current generator state (Algorithm 2: the PRBG state persists from frame
- * to frame) for checkpointing: x holds n records {x_1, x_2} (2*n doubles),
- * *frame_index the number of frames processed so far.  Synchronises the
- * key's device.  CV_E_INVAL if n_doubles != 2*n or a pointer is NULL. */
+ * to frame) for checkpointing: x holds n records, {x_1, x_2} for PLCM (2*n
+ * doubles) or {x_1, y_1, x_2, y_2} for 2DLASM (4*n doubles), *frame_index
+ * the number of frames processed so far.  Synchronises the key's device.
+ * CV_E_INVAL if n_doubles is not that size or a pointer is NULL. */
 cv_status cv_key_get_state(const cv_key *key, double *x, size_t n_doubles, uint64_t *frame_index);
 
 /* Restore a state obtained from cv_key_get_state (same geometry and p_m).

@@ -80,6 +80,8 @@ def lib() -> ct.CDLL:
                           ct.POINTER(ct.c_uint32), ct.c_uint64]
         L.oracle_cr_sin_margin.restype = ct.c_int
         L.oracle_cr_sin_margin.argtypes = [ct.c_double, dp, ct.c_int]
+        L.oracle_cr_sin_array.restype = ct.c_uint64
+        L.oracle_cr_sin_array.argtypes = [dp, dp, ct.c_uint64]
         L.oracle_cr_sin.restype = ct.c_int
         L.oracle_cr_sin.argtypes = [ct.c_double, dp]
         L.oracle_lasm.restype = ct.c_int
@@ -132,6 +134,15 @@ def cr_sin(t: float) -> float:
     if lib().oracle_cr_sin(t, ct.byref(out)):
         raise Undecided(t)
     return out.value
+
+
+def cr_sin_array(t: np.ndarray) -> np.ndarray:
+    """cr_sin over a float64 array."""
+    t = np.ascontiguousarray(t, np.float64)
+    out = np.empty_like(t)
+    if lib().oracle_cr_sin_array(_f64(t), _f64(out), t.size):
+        raise Undecided("array")
+    return out
 
 
 def lasm(x: float, y: float, mu: float):

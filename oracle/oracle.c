@@ -119,6 +119,15 @@ int oracle_cr_sin(double t, double *out)
     return oracle_cr_sin_margin(t, out, -100);
 }
 
+/* oracle_cr_sin over an array; returns the number of undecided values. */
+uint64_t oracle_cr_sin_array(const double *t, double *out, uint64_t n)
+{
+    uint64_t bad = 0;
+    for (uint64_t i = 0; i < n; i++)
+        bad += (uint64_t)oracle_cr_sin(t[i], &out[i]);
+    return bad;
+}
+
 /* Sec. 3, Eq. (6): x' = sin(pi*mu*(y+3)*x*(1-x)), then
  * y' = sin(pi*mu*(x'+3)*y*(1-y)) -- the new x enters the y update.
  * Returns 1 (state unchanged) if a sine could not be rounded with certainty. */

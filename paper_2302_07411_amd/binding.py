@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(PKG, "libchaosvid.so")
 
 CV_OK, CV_E_INVAL, CV_E_NOMEM, CV_E_HIP, CV_E_AGAIN, CV_E_STATE = range(6)
 CV_MAP_PLCM = 0
+CV_MAP_2DLASM = 1
 CV_PATH_PLAIN = 0
 CV_PATH_FUSED = 1
 
@@ -29,7 +30,7 @@ EXPORTS = (
     "cv_batch_get_info", "cv_batch_autotune", "cv_batch_set_profiling", "cv_batch_get_profile",
     "cv_server_create", "cv_server_tune", "cv_server_free", "cv_server_drain",
     "cv_server_get_stats", "cv_stream_open", "cv_stream_submit", "cv_stream_poll",
-    "cv_stream_close",
+    "cv_stream_close", "cv_cr_sin",
 )
 
 
@@ -148,6 +149,8 @@ def load() -> ct.CDLL:
     L.cv_batch_set_profiling.argtypes = [vp, ct.c_int]
     L.cv_batch_get_profile.restype = ct.c_int
     L.cv_batch_get_profile.argtypes = [vp, ct.POINTER(CvProfile)]
+    L.cv_cr_sin.restype = ct.c_int
+    L.cv_cr_sin.argtypes = [vp, vp, sz, ct.c_int, vp, vp]
     L.cv_server_create.restype = ct.c_int
     L.cv_server_create.argtypes = [ct.c_int, sz, ct.POINTER(vp)]
     L.cv_server_tune.restype = ct.c_int
@@ -201,17 +204,20 @@ def _seeds(s_c, n: int):
 
 
 class Key:
-    """One stream's key: per-band PLCM generators on the device
-    (cv_keysetup).  `pm` is an (n, 4) array of (x0_1, p_1, x0_2, p_2)."""
+    """One stream's key: per-band chaotic generators on the device
+    (cv_keysetup).  `pm` is an (n, 4) array of (x0_1, p_1, x0_2, p_2) for
+    PLCM or an (n, 6) array of (x0_1, y0_1, mu_1, x0_2, y0_2, mu_2) for
+    2DLASM."""
 
-    def __init__(self, H, W, C, n, r, pm, device: int = 0):
+    def __init__(self, H, W, C, n, r, pm, device: int = 0, map: int = CV_MAP_PLCM):
         L = load()
         self.geom = (H, W, C, n, r)
+        self.map = map
         self.frame_bytes = H * W * C
         pm = np.ascontiguousarray(np.asarray(pm, np.float64).reshape(-1))
         g = CvGeom(H, W, C, n, r)
         h = ct.c_void_p()
-        _check(L.cv_keysetup(ct.byref(g), CV_MAP_PLCM, pm.ctypes.data_as(ct.POINTER(ct.c_double)),
+        _check(L.cv_keysetup(ct.byref(g), map, pm.ctypes.data_as(ct.POINTER(ct.c_double)),
                              pm.size, device, ct.byref(h)))
         self._h = h
 
@@ -261,12 +267,15 @@ class Key:
                                       p, n, _stream(stream)))
 
     def get_state(self):
+        """(state, frame_index): state is (n, 2) {x_1, x_2} for PLCM, (n, 4)
+        {x_1, y_1, x_2, y_2} for 2DLASM."""
         n = self.geom[3]
-        x = np.zeros(2 * n, np.float64)
+        per = 2 if self.map == CV_MAP_PLCM else 4
+        x = np.zeros(per * n, np.float64)
         fi = ct.c_uint64()
         _check(load().cv_key_get_state(self._h, x.ctypes.data_as(ct.POINTER(ct.c_double)), x.size,
                                        ct.byref(fi)))
-        return x.reshape(n, 2), fi.value
+        return x.reshape(n, per), fi.value
 
     def set_state(self, x, frame_index: int):
         x = np.ascontiguousarray(np.asarray(x, np.float64).reshape(-1))
@@ -382,11 +391,12 @@ class Server:
         _check(load().cv_server_tune(self._h, ring_frames or 3, queue_frames or 8,
                                      int(bool(split_cus))))
 
-    def open(self, H, W, C, n, r, pm, decrypt: bool = False) -> "ServerStream":
+    def open(self, H, W, C, n, r, pm, decrypt: bool = False,
+             map: int = CV_MAP_PLCM) -> "ServerStream":
         pm = np.ascontiguousarray(np.asarray(pm, np.float64).reshape(-1))
         g = CvGeom(H, W, C, n, r)
         h = ct.c_void_p()
-        _check(load().cv_stream_open(self._h, ct.byref(g), CV_MAP_PLCM,
+        _check(load().cv_stream_open(self._h, ct.byref(g), map,
                                      pm.ctypes.data_as(ct.POINTER(ct.c_double)), pm.size,
                                      int(bool(decrypt)), ct.byref(h)))
         st = ServerStream(self, h, H * W * C)
@@ -451,3 +461,20 @@ class ServerStream:
                 self.server._streams.remove(self)
             except ValueError:
                 pass
+
+
+def cr_sin(t, out, force_exact: bool = False, stream=None) -> bool:
+    """RN(sin(t)) on the device for a float64 CUDA tensor t with values in
+    [0, RN(pi)] into `out`; returns True if every value was rounded with
+    certainty (cv_cr_sin)."""
+    import torch
+    for x in (t, out):
+        if not isinstance(x, torch.Tensor) or x.dtype != torch.float64 or not x.is_cuda \
+                or not x.is_contiguous():
+            raise TypeError("expected contiguous float64 tensors on a HIP device")
+    if out.numel() != t.numel():
+        raise ValueError("out size differs from t")
+    flag = torch.zeros(1, dtype=torch.int32, device=t.device)
+    _check(load().cv_cr_sin(t.data_ptr(), out.data_ptr(), t.numel(), int(bool(force_exact)),
+                            flag.data_ptr(), _stream(stream)))
+    return int(flag.item()) == 0

@@ -23,6 +23,8 @@ namespace rt {
 
 thread_local std::string g_last_error;
 
+hipError_t copy_sync(void* dst, const void* src, size_t bytes, hipMemcpyKind kind);
+
 cv_status fail(cv_status s, const std::string& msg) {
   g_last_error = msg;
   return s;
@@ -109,11 +111,26 @@ int prbg_variant(const cv_key* k) {
 uint64_t prbg_steps(const cv_key* k, uint64_t frames) {
   uint64_t steps = 0;
   const uint64_t row = (uint64_t)k->g.W * k->g.C;
+  const uint64_t per_step = k->map == CV_MAP_2DLASM ? 12 : 6;  // keystream bytes per step
   for (uint32_t i = 0; i < k->g.n; i++) {
     const uint64_t S = (cv::band_lo(k->g.H, k->g.n, i + 1) - cv::band_lo(k->g.H, k->g.n, i)) * row;
-    steps += (k->g.r * S + 5) / 6;
+    steps += (k->g.r * S + per_step - 1) / per_step;
   }
   return steps * frames;
+}
+
+// Keystream of T frames into ks (layout of cv_keystream_frames) on st,
+// advancing the key's generators.
+cv_status launch_keystream(cv_key* k, uint8_t* ks, uint32_t T, hipStream_t st) {
+  Timed tm(k, st);
+  if (k->map == CV_MAP_2DLASM) {
+    CV_HIP(cv::launch_prbg_lasm(k->d_lchains, k->g.n, ks, T, 0, k->d_err, st));
+    tm.end(0, prbg_steps(k, T));
+    return queue_err_readback(k, st);
+  }
+  CV_HIP(cv::launch_prbg_plcm(k->d_chains, k->g.n, ks, T, prbg_variant(k), st));
+  tm.end(0, prbg_steps(k, T));
+  return CV_OK;
 }
 
 // Largest pixel-word tile (rows) not above `want` that the kernels accept
@@ -223,7 +240,11 @@ cv_status check_async_errors(cv_key* k, bool wait) {
   }
   k->err_pending = false;
   if (*k->h_err) {
+    const uint32_t v = *k->h_err;
     *k->h_err = 0;
+    if (v == 2)
+      return fail(CV_E_HIP,
+                  "a 2DLASM sine could not be rounded with certainty; the keystream is invalid");
     return fail(CV_E_HIP,
                 "a fused launch timed out at a group barrier or found a group spread over "
                 "XCDs; its output is invalid");
@@ -242,6 +263,31 @@ void set_fused_groups(cv_key* k, uint32_t want) {
   k->fused_groups = (w == 0 || w > k->fused_cap) ? k->fused_cap : w;
 }
 
+// The key's asynchronous error word (a fused launch's barrier timeout, a
+// 2DLASM sine that could not be rounded) and its pinned read-back.
+cv_status ensure_err_flag(cv_key* k) {
+  if (k->d_err) return CV_OK;
+  if (hipMalloc(&k->d_err, sizeof(uint32_t)) != hipSuccess ||
+      hipHostMalloc(&k->h_err, sizeof(uint32_t)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(CV_E_NOMEM, "error-flag allocation failed");
+  }
+  *k->h_err = 0;
+  const uint32_t zero = 0;
+  CV_HIP(copy_sync(k->d_err, &zero, sizeof(zero), hipMemcpyHostToDevice));
+  CV_HIP(hipEventCreateWithFlags(&k->err_copied, hipEventDisableTiming));
+  return CV_OK;
+}
+
+// Bring the error word back to the host behind the work just enqueued on st;
+// the next call on the key reports it.
+cv_status queue_err_readback(cv_key* k, hipStream_t st) {
+  CV_HIP(hipMemcpyAsync(k->h_err, k->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  CV_HIP(hipEventRecord(k->err_copied, st));
+  k->err_pending = true;
+  return CV_OK;
+}
+
 cv_status ensure_fused(cv_key* k) {
   if (k->d_fscratch) return CV_OK;
   const Geom& g = k->g;
@@ -252,17 +298,7 @@ cv_status ensure_fused(cv_key* k) {
     k->d_fscratch = nullptr;
     return fail(CV_E_NOMEM, "fused-path workspace allocation failed");
   }
-  if (!k->d_err) {
-    if (hipMalloc(&k->d_err, sizeof(uint32_t)) != hipSuccess ||
-        hipHostMalloc(&k->h_err, sizeof(uint32_t)) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(CV_E_NOMEM, "fused-path workspace allocation failed");
-    }
-    *k->h_err = 0;
-    CV_HIP(hipMemset(k->d_err, 0, sizeof(uint32_t)));
-    CV_HIP(hipEventCreateWithFlags(&k->err_copied, hipEventDisableTiming));
-  }
-  return CV_OK;
+  return ensure_err_flag(k);
 }
 
 cv_status run_rounds_fused(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
@@ -286,10 +322,7 @@ cv_status run_rounds_fused(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* 
   Timed tm(k, st);
   CV_HIP(cv::launch_rounds_fused(a, k->threads, st));
   tm.end(1, (uint64_t)T * k->g.r);
-  CV_HIP(hipMemcpyAsync(k->h_err, k->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-  CV_HIP(hipEventRecord(k->err_copied, st));
-  k->err_pending = true;
-  return CV_OK;
+  return queue_err_readback(k, st);
 }
 
 bool pw_eligible(const cv_key* k, const uint8_t* in, const uint8_t* out, uint32_t threads,
@@ -389,9 +422,7 @@ cv_status crypt_frames(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
   for (size_t f0 = 0; f0 < n; f0 += B) {
     const uint32_t T = (uint32_t)std::min(B, n - f0);
     if ((s = upload_shift_tables(k, s_c + f0, T, st)) != CV_OK) return s;
-    Timed tm(k, st);
-    CV_HIP(cv::launch_prbg_plcm(k->d_chains, k->g.n, k->d_ks, T, prbg_variant(k), st));
-    tm.end(0, prbg_steps(k, T));
+    if ((s = launch_keystream(k, k->d_ks, T, st)) != CV_OK) return s;
     if ((s = run_rounds(k, decrypt, in + f0 * k->F, out + f0 * k->F, k->d_ks, T, st)) != CV_OK)
       return s;
     k->frame_index += T;
@@ -400,6 +431,54 @@ cv_status crypt_frames(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
 }
 
 bool finite_in(double v, double lo, double hi) { return isfinite(v) && v > lo && v < hi; }
+
+size_t state_doubles(const cv_key* k) { return (k->map == CV_MAP_2DLASM ? 4ull : 2ull) * k->g.n; }
+
+// Sec. 3, Eq. (6): the control parameter's admissible set.
+bool lasm_mu_ok(double mu) {
+  return (mu >= 0.37 && mu <= 0.38) || (mu >= 0.4 && mu <= 0.42) || (mu >= 0.44 && mu <= 0.93) ||
+         mu == 1.0;
+}
+
+cv_status ensure_err_flag(cv_key* k);
+hipError_t copy_sync(void* dst, const void* src, size_t bytes, hipMemcpyKind kind);
+
+// Generators of a 2DLASM key: per band two maps (x0, y0, mu) of Eq. (6).
+cv_status setup_lasm(cv_key* k, const double* p_m) {
+  const Geom& g = k->g;
+  const uint64_t row = (uint64_t)g.W * g.C;
+  std::vector<double> state(4 * g.n);
+  std::vector<cv::LasmChain> chains(g.n);
+  if (hipMalloc(&k->d_state, state.size() * sizeof(double)) != hipSuccess ||
+      hipMalloc(&k->d_lchains, chains.size() * sizeof(cv::LasmChain)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(CV_E_NOMEM, "key allocation failed");
+  }
+  k->fast = false;
+  for (uint32_t i = 0; i < g.n; i++) {
+    const double* q = p_m + 6 * i;
+    cv::LasmChain& c = chains[i];
+    c.state = k->d_state + 4 * i;
+    for (int m = 0; m < 2; m++) {
+      state[4 * i + 2 * m] = q[3 * m];
+      state[4 * i + 2 * m + 1] = q[3 * m + 1];
+      c.mu[m] = q[3 * m + 2];
+    }
+    const uint64_t lo = cv::band_lo(g.H, g.n, i), hi = cv::band_lo(g.H, g.n, i + 1);
+    c.out_off = (uint64_t)g.r * lo * row;
+    c.frame_stride = (uint64_t)g.r * k->F;
+    c.nbytes = (uint64_t)g.r * (hi - lo) * row;
+  }
+  hipError_t e = copy_sync(k->d_state, state.data(), state.size() * sizeof(double),
+                           hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = copy_sync(k->d_lchains, chains.data(), chains.size() * sizeof(cv::LasmChain),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&k->gm_done, hipEventDisableTiming);
+  if (e != hipSuccess) return hip_fail(e, "cv_keysetup");
+  k->h_lchains = chains;
+  return ensure_err_flag(k);
+}
 
 // Blocking host<->device copy on a private non-blocking stream of the current
 // device, so that it waits for no other stream (the legacy null stream would
@@ -439,20 +518,34 @@ cv_status cv_keysetup(const cv_geom* geom, cv_map map, const double* p_m, size_t
   if (!geom || !p_m || !out) return fail(CV_E_INVAL, "NULL argument");
   *out = nullptr;
   const Geom g{geom->height, geom->width, geom->channels, geom->n_sub, geom->rounds};
-  if (map != CV_MAP_PLCM) return fail(CV_E_INVAL, "unknown map");
+  if (map != CV_MAP_PLCM && map != CV_MAP_2DLASM) return fail(CV_E_INVAL, "unknown map");
+  const uint32_t rec = map == CV_MAP_PLCM ? 4 : 6;  // doubles per subframe record
   if (!g.H || !g.W || !g.C || !g.n || !g.r) return fail(CV_E_INVAL, "zero in geometry");
   if (g.n > g.H) return fail(CV_E_INVAL, "more subframes than rows");
   const uint64_t row = (uint64_t)g.W * g.C;
   if ((uint64_t)g.H * row > 0xFFFFFFFFull / 8) return fail(CV_E_INVAL, "frame too large");
-  if (n_doubles != 4ull * g.n) return fail(CV_E_INVAL, "p_m must hold 4 doubles per subframe");
+  if (n_doubles != (uint64_t)rec * g.n)
+    return fail(CV_E_INVAL, map == CV_MAP_PLCM ? "p_m must hold 4 doubles per subframe"
+                                               : "p_m must hold 6 doubles per subframe");
   for (uint32_t i = 0; i < g.n; i++) {
     const uint64_t S = (cv::band_lo(g.H, g.n, i + 1) - cv::band_lo(g.H, g.n, i)) * row;
     if (S < 2) return fail(CV_E_INVAL, "every subframe needs at least 2 bytes");
-    const double* q = p_m + 4 * i;
-    if (!finite_in(q[0], 0.0, 1.0) || !finite_in(q[2], 0.0, 1.0))
-      return fail(CV_E_INVAL, "PLCM x0 must lie in (0,1)");
-    if (!finite_in(q[1], 0.0, 0.5) || !finite_in(q[3], 0.0, 0.5))
-      return fail(CV_E_INVAL, "PLCM p must lie in (0,1/2)");
+    const double* q = p_m + (uint64_t)rec * i;
+    if (map == CV_MAP_PLCM) {
+      if (!finite_in(q[0], 0.0, 1.0) || !finite_in(q[2], 0.0, 1.0))
+        return fail(CV_E_INVAL, "PLCM x0 must lie in (0,1)");
+      if (!finite_in(q[1], 0.0, 0.5) || !finite_in(q[3], 0.0, 0.5))
+        return fail(CV_E_INVAL, "PLCM p must lie in (0,1/2)");
+    } else {
+      for (int m = 0; m < 2; m++) {
+        if (!finite_in(q[3 * m], 0.0, 1.0) || !finite_in(q[3 * m + 1], 0.0, 1.0))
+          return fail(CV_E_INVAL, "2DLASM x0 and y0 must lie in (0,1)");
+        if (!lasm_mu_ok(q[3 * m + 2]))
+          return fail(CV_E_INVAL, "2DLASM mu must lie in [0.37,0.38], [0.4,0.42], [0.44,0.93] or be 1");
+      }
+      // one launch covers a batch of frames: a chain's steps must fit 31 bits
+      if ((uint64_t)g.r * S > (1ull << 31)) return fail(CV_E_INVAL, "subframe too large");
+    }
   }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
@@ -485,6 +578,15 @@ cv_status cv_keysetup(const cv_geom* geom, cv_map map, const double* p_m, size_t
   const uint64_t per_frame = (uint64_t)(g.r + 1) * k->F;
   k->batch_frames = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(256, (1ull << 30) / per_frame));
 
+  if (map == CV_MAP_2DLASM) {
+    cv_status st = setup_lasm(k, p_m);
+    if (st != CV_OK) {
+      cv_key_free(k);
+      return st;
+    }
+    *out = k;
+    return CV_OK;
+  }
   std::vector<double> state(2 * g.n);
   std::vector<cv::PlcmChain> chains(g.n);
   if (hipMalloc(&k->d_state, state.size() * sizeof(double)) != hipSuccess ||
@@ -541,13 +643,15 @@ void cv_key_free(cv_key* k) {
   if (k->err_copied) (void)hipEventDestroy(k->err_copied);
   if (k->d_state) (void)hipFree(k->d_state);
   if (k->d_chains) (void)hipFree(k->d_chains);
+  if (k->d_lchains) (void)hipFree(k->d_lchains);
   if (k->gm_done) (void)hipEventDestroy(k->gm_done);
   delete k;
 }
 
 cv_status cv_key_get_state(const cv_key* k, double* x, size_t n_doubles, uint64_t* frame_index) {
   if (!k || !x || !frame_index) return fail(CV_E_INVAL, "NULL argument");
-  if (n_doubles != 2ull * k->g.n) return fail(CV_E_INVAL, "state holds 2 doubles per subframe");
+  if (n_doubles != state_doubles(k))
+    return fail(CV_E_INVAL, "state holds 2 (PLCM) or 4 (2DLASM) doubles per subframe");
   DeviceGuard dg(k->device);
   CV_HIP(hipDeviceSynchronize());
   cv_status s = check_async_errors(const_cast<cv_key*>(k), true);
@@ -559,17 +663,20 @@ cv_status cv_key_get_state(const cv_key* k, double* x, size_t n_doubles, uint64_
 
 cv_status cv_key_set_state(cv_key* k, const double* x, size_t n_doubles, uint64_t frame_index) {
   if (!k || !x) return fail(CV_E_INVAL, "NULL argument");
-  if (n_doubles != 2ull * k->g.n) return fail(CV_E_INVAL, "state holds 2 doubles per subframe");
+  if (n_doubles != state_doubles(k))
+    return fail(CV_E_INVAL, "state holds 2 (PLCM) or 4 (2DLASM) doubles per subframe");
   for (size_t i = 0; i < n_doubles; i++)
     if (!(x[i] >= 0.0 && x[i] <= 1.0)) return fail(CV_E_INVAL, "state outside [0,1]");
   DeviceGuard dg(k->device);
   CV_HIP(hipDeviceSynchronize());
   CV_HIP(hipMemcpy(k->d_state, x, n_doubles * sizeof(double), hipMemcpyHostToDevice));
   k->frame_index = frame_index;
-  bool fast = true;
-  for (uint32_t i = 0; i < k->g.n; i++)
-    for (int m = 0; m < 2; m++) fast = fast && cv::plcm_fast_ok(x[2 * i + m], k->pm[4 * i + 2 * m + 1]);
-  k->fast = fast;
+  if (k->map == CV_MAP_PLCM) {
+    bool fast = true;
+    for (uint32_t i = 0; i < k->g.n; i++)
+      for (int m = 0; m < 2; m++) fast = fast && cv::plcm_fast_ok(x[2 * i + m], k->pm[4 * i + 2 * m + 1]);
+    k->fast = fast;
+  }
   return CV_OK;
 }
 
@@ -660,16 +767,23 @@ cv_status cv_decrypt_frames(cv_key* k, const uint8_t* in, uint8_t* out, const ui
   return crypt_frames(k, true, in, out, s_c, n, stream);
 }
 
+cv_status cv_cr_sin(const double* t, double* out, size_t n, int force_exact, uint32_t* undecided,
+                    void* stream) {
+  if (n == 0) return CV_OK;
+  if (!t || !out || !undecided) return fail(CV_E_INVAL, "NULL argument");
+  CV_HIP(cv::launch_cr_sin(t, out, n, force_exact != 0, undecided, (hipStream_t)stream));
+  return CV_OK;
+}
+
 cv_status cv_keystream_frames(cv_key* k, uint8_t* ks, size_t n, void* stream) {
   if (!k) return fail(CV_E_INVAL, "key is NULL");
   if (n == 0) return CV_OK;
   if (!ks) return fail(CV_E_INVAL, "NULL buffer");
   if (n > 0xFFFFFFFFull) return fail(CV_E_INVAL, "too many frames in one call");
+  cv_status s = check_async_errors(k, false);
+  if (s != CV_OK) return s;
   DeviceGuard dg(k->device);
-  Timed tm(k, (hipStream_t)stream);
-  CV_HIP(cv::launch_prbg_plcm(k->d_chains, k->g.n, ks, (uint32_t)n, prbg_variant(k),
-                              (hipStream_t)stream));
-  tm.end(0, prbg_steps(k, n));
+  if ((s = launch_keystream(k, ks, (uint32_t)n, (hipStream_t)stream)) != CV_OK) return s;
   k->frame_index += n;
   return CV_OK;
 }

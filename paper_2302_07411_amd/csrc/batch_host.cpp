@@ -536,8 +536,10 @@ cv_status launch_graph(cv_batch* b, const Plan& P, const Layout& L, Slot& sl, ui
 }
 
 // Items outside the pixel-word conditions run on their key's own path.
+// (2DLASM keys too: the batched keystream launch runs PLCM generators only.)
 bool item_eligible(const cv_batch* b, const cv_batch_item& it) {
-  return pw_eligible(it.key, it.in, it.out, b->shape.threads, b->lds_max);
+  return it.key->map == CV_MAP_PLCM &&
+         pw_eligible(it.key, it.in, it.out, b->shape.threads, b->lds_max);
 }
 
 // Chains and frame jobs of the items that take the batched kernels, with

@@ -37,6 +37,26 @@ struct PlcmChain {
   uint32_t pad;
 };
 
+// One band of a 2DLASM stream (Sec. 3, Eq. (6)): two maps, 12 bytes per step.
+struct LasmChain {
+  double* state;          // [4]: x, y of map 1, x, y of map 2 (device, updated)
+  double mu[2];           // control parameters of map 1, map 2
+  uint64_t out_off;       // offset of this band's bytes in a frame's keystream
+  uint64_t frame_stride;  // bytes from one frame's keystream to the next
+  uint64_t nbytes;        // r * S_i bytes per frame
+  uint32_t frames;        // frames of this chain when the launch passes n_frames = 0
+  uint32_t pad;
+};
+
+// 2DLASM keystream of n_frames frames (0: every chain its own `frames`); a
+// sine whose rounding could not be decided stores 2 into *err.
+// force_exact sends every sine to the exact path (for testing it).
+hipError_t launch_prbg_lasm(const LasmChain* d_chains, uint32_t n_chains, uint8_t* ks_base,
+                            uint32_t n_frames, uint32_t force_exact, uint32_t* err, hipStream_t s);
+// The generator's correctly rounded sine on n device doubles in [0, RN(pi)].
+hipError_t launch_cr_sin(const double* t, double* out, uint64_t n, uint32_t force_exact,
+                         uint32_t* undecided, hipStream_t s);
+
 // Generator variants (identical bytes): IEEE division; reciprocal division
 // (valid only for chains that satisfy plcm_fast_ok); reciprocal division with
 // one lane per piece of Eq. (5).

@@ -37,6 +37,8 @@ struct cv_key {
   bool err_pending = false;
   cv::PlcmChain* d_chains = nullptr;
   std::vector<cv::PlcmChain> h_chains;  // host copy (tables of multi-stream batches)
+  cv::LasmChain* d_lchains = nullptr;   // 2DLASM keys: generators of the bands
+  std::vector<cv::LasmChain> h_lchains;
   // workspace, grown on demand
   uint32_t batch_frames = 0;
   uint8_t* d_ks = nullptr;
@@ -109,6 +111,9 @@ uint32_t pw_tile_rows(const Geom& g, uint32_t threads, size_t lds_max);
 cv_status crypt_frames(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
                        const uint32_t* s_c, size_t n, void* stream);
 
+// Keystream of T frames of one key into ks on st (either map), advancing it.
+cv_status launch_keystream(cv_key* k, uint8_t* ks, uint32_t T, hipStream_t st);
+cv_status queue_err_readback(cv_key* k, hipStream_t st);
 // Pixel-word kernels apply to this key and buffers with `threads` threads.
 bool pw_eligible(const cv_key* k, const uint8_t* in, const uint8_t* out, uint32_t threads,
                  size_t lds_max);

@@ -183,8 +183,15 @@ hipEvent_t take_event(cv_server* S) {
   return hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess ? e : nullptr;
 }
 
+// A 2DLASM stream's share of a keystream launch (its own generator launch).
+struct LasmJob {
+  cv_key* k;
+  uint64_t ks_off;
+  uint32_t frames;
+};
+
 // Frames of keystream to generate for each stream in the next launch (mutex held).
-void plan_keystream(cv_server* S, std::vector<ChainJob>& cj) {
+void plan_keystream(cv_server* S, std::vector<ChainJob>& cj, std::vector<LasmJob>& lj) {
   uint64_t longest = 0;
   for (cv_stream* st : S->streams)
     if (!st->closing && st->ks_issued - st->completed < st->D)
@@ -196,7 +203,11 @@ void plan_keystream(cv_server* S, std::vector<ChainJob>& cj) {
     const uint64_t contiguous = st->D - st->ks_issued % st->D;  // no wrap within a launch
     const uint64_t share = std::max<uint64_t>(1, longest / std::max<uint64_t>(1, st->steps_per_frame));
     const uint32_t k = (uint32_t)std::min({free, contiguous, share});
-    cj.push_back({st->key, st->ring_off + (st->ks_issued % st->D) * st->rF, 0, k});
+    const uint64_t off = st->ring_off + (st->ks_issued % st->D) * st->rF;
+    if (st->key->map == CV_MAP_PLCM)
+      cj.push_back({st->key, off, 0, k});
+    else
+      lj.push_back({st->key, off, k});
     S->ks_launch.push_back({st, k});
     st->ks_issued += k;
     st->in_ks_launch = true;
@@ -305,6 +316,8 @@ void worker_main(cv_server* S) {
       for (auto& [st, k] : S->ks_launch) {
         st->ks_ready += k;
         st->in_ks_launch = false;
+        if (st->key->map != CV_MAP_PLCM && *st->key->h_err)
+          set_error(S, CV_E_HIP, "a 2DLASM sine could not be rounded with certainty");
       }
       S->ks_launch.clear();
       S->ks_busy = false;
@@ -370,13 +383,23 @@ void worker_main(cv_server* S) {
     }
     if (S->err == CV_OK && !S->ks_busy && !S->stop) {
       std::vector<ChainJob> cj;
-      plan_keystream(S, cj);
-      if (!cj.empty()) {
+      std::vector<LasmJob> lj;
+      plan_keystream(S, cj, lj);
+      if (!cj.empty() || !lj.empty()) {
         uint64_t frames = 0;
         for (auto& c : cj) frames += c.frames;
+        for (auto& l : lj) frames += l.frames;
         S->ks_launch_t = Clock::now();
         lk.unlock();
-        cv_status s = batch_enqueue(S->kb, cj, {}, S->arena_mem, S->s_ks);
+        cv_status s = cj.empty() ? CV_OK : batch_enqueue(S->kb, cj, {}, S->arena_mem, S->s_ks);
+        for (const LasmJob& l : lj) {
+          if (s != CV_OK) break;
+          if (cv::launch_prbg_lasm(l.k->d_lchains, l.k->g.n, S->arena_mem + l.ks_off, l.frames, 0,
+                                   l.k->d_err, S->s_ks) != hipSuccess ||
+              hipMemcpyAsync(l.k->h_err, l.k->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                             S->s_ks) != hipSuccess)
+            s = fail(CV_E_HIP, "2DLASM keystream launch failed");
+        }
         std::string msg = s != CV_OK ? cv_last_error() : "";
         hipError_t e = hipEventRecord(S->ks_ev, S->s_ks);
         lk.lock();
