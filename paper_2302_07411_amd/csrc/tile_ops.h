@@ -9,6 +9,29 @@ namespace tile {
 
 
 constexpr uint32_t kMaxThreads = 1024;
+
+// Global-memory views.  Frame, keystream and scratch pointers reach the
+// kernels through argument structs, where the compiler cannot see that they
+// point to global memory; without these casts it emits flat accesses, which
+// also count against the LDS wait counter and serialise the gathers.
+typedef __attribute__((address_space(1))) const uint32_t gcu32;
+typedef __attribute__((address_space(1))) uint32_t gu32;
+typedef __attribute__((address_space(1))) const uint8_t gcu8;
+typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) v4u32 gv4;
+__device__ __forceinline__ const gcu32* g32(const void* p) { return (const gcu32*)p; }
+__device__ __forceinline__ uint4 gload4(const void* p) {
+  const v4u32 x = *(const gv4*)p;
+  return make_uint4(x.x, x.y, x.z, x.w);
+}
+__device__ __forceinline__ void gstore4(void* p, uint4 v) {
+  v4u32 x;
+  x.x = v.x;
+  x.y = v.y;
+  x.z = v.z;
+  x.w = v.w;
+  *(gv4*)p = x;
+}
 constexpr uint32_t kUnroll = 8;  // gather loads in flight per thread
 constexpr uint32_t kPix = 16;    // pixels per thread in the diffusion pass (tile <= kPix*threads)
 
@@ -31,21 +54,21 @@ __host__ __device__ constexpr uint32_t pixel_mask() {
 // keeps it inside the buffer otherwise.
 template <uint32_t C>
 __device__ __forceinline__ uint32_t load_packed(const uint8_t* base, uint64_t p, const uint8_t* last) {
-  if constexpr (C == 4) return reinterpret_cast<const uint32_t*>(base)[p];
+  if constexpr (C == 4) return g32(base)[p];
   const uint8_t* a = base + p * 3;
   const uint8_t* al = reinterpret_cast<const uint8_t*>((uintptr_t)a & ~(uintptr_t)3);
   const uint32_t sh = (uint32_t)((uintptr_t)a & 3);
   const uint8_t* a1 = al + 4 <= last ? al + 4 : last;
-  const uint32_t w0 = *reinterpret_cast<const uint32_t*>(al);
-  const uint32_t w1 = *reinterpret_cast<const uint32_t*>(a1);
+  const uint32_t w0 = *g32(al);
+  const uint32_t w1 = *g32(a1);
   return __builtin_amdgcn_alignbyte(w1, w0, sh) & 0x00FFFFFFu;
 }
 
 // Four packed pixels starting at a 16-byte-aligned group (12 or 16 bytes).
 template <uint32_t C>
 __device__ __forceinline__ uint4 load4_packed(const uint8_t* p) {
-  if constexpr (C == 4) return *reinterpret_cast<const uint4*>(p);
-  const uint32_t* w = reinterpret_cast<const uint32_t*>(p);
+  if constexpr (C == 4) return gload4(p);
+  const gcu32* w = g32(p);
   const uint32_t k0 = w[0], k1 = w[1], k2 = w[2];
   return make_uint4(k0 & 0xFFFFFFu, (k0 >> 24) | ((k1 & 0xFFFFu) << 8),
                     (k1 >> 16) | ((k2 & 0xFFu) << 16), k2 >> 8);
@@ -54,9 +77,9 @@ __device__ __forceinline__ uint4 load4_packed(const uint8_t* p) {
 template <uint32_t C>
 __device__ __forceinline__ void store4_packed(uint8_t* p, uint4 v) {
   if constexpr (C == 4) {
-    *reinterpret_cast<uint4*>(p) = v;
+    gstore4(p, v);
   } else {
-    uint32_t* w = reinterpret_cast<uint32_t*>(p);
+    gu32* w = (gu32*)p;
     w[0] = (v.x & 0xFFFFFFu) | (v.y << 24);
     w[1] = ((v.y >> 8) & 0xFFFFu) | (v.z << 16);
     w[2] = ((v.z >> 16) & 0xFFu) | (v.w << 8);
@@ -99,17 +122,20 @@ struct View {
 template <uint32_t C, bool kSrcPacked>
 __device__ __forceinline__ uint32_t src_pixel(const View& v, uint64_t p) {
   if constexpr (kSrcPacked) return load_packed<C>(v.src, p, v.src_last);
-  return reinterpret_cast<const uint32_t*>(v.src)[p];
+  return g32(v.src)[p];
 }
 
 // Gather of Eq. (1) for destination rows [t0, t0+R): tile[k*W + beta] =
 // source pixel (a, o) with alpha = t0+k = (a+o) mod H, beta = (o+g) mod W.
 // Thread = (k, slot): consecutive lanes take consecutive k, i.e. consecutive
 // pixels of one source row's run; each thread walks source rows a = slot,
-// slot+ns, ... with incremental index arithmetic, kUnroll loads in flight.
+// slot+ns, ... with incremental index arithmetic.  Loads go out kUnroll at a
+// time and the next batch is issued before the current one is stored; the
+// stores are unconditional (a lane past the frame writes to `sink`).
 template <uint32_t C, bool kSrcPacked>
 __device__ __forceinline__ void gather_rows(const View& v, const Geom& g, uint32_t t0, uint32_t R,
                                             uint32_t* tile) {
+  __shared__ uint32_t sink;
   const uint32_t tid = threadIdx.x, T = blockDim.x;
   const uint32_t W = g.W, H = g.H;
   const uint32_t M = (W + H - 1) / H;   // runs per source row
@@ -124,24 +150,36 @@ __device__ __forceinline__ void gather_rows(const View& v, const Geom& g, uint32
   uint32_t a = slot / M;
   uint32_t ob = alpha + H - a % H;      // (alpha - a) mod H
   if (ob >= H) ob -= H;
-  while (a < H) {
-    uint32_t val[kUnroll], beta[kUnroll];
-    bool ok[kUnroll];
+  uint32_t val[kUnroll];
+  uint32_t* dst[kUnroll];
+  auto issue = [&](uint32_t* vv, uint32_t** dd) {
 #pragma unroll
     for (uint32_t u = 0; u < kUnroll; u++) {
       const uint32_t o = ob + m * H;
-      ok[u] = a < H && o < W;
-      const uint32_t oc = ok[u] ? o : 0;
+      const bool ok = a < H && o < W;
+      const uint32_t oc = ok ? o : 0;
       const uint32_t bs = oc + shift;
-      beta[u] = bs >= W ? bs - W : bs;
-      val[u] = src_pixel<C, kSrcPacked>(v, ok[u] ? a * W + oc : 0u);
+      dd[u] = ok ? drow + (bs >= W ? bs - W : bs) : &sink;
+      vv[u] = src_pixel<C, kSrcPacked>(v, ok ? a * W + oc : 0u);
       a += astep;
       ob = ob >= dstep ? ob - dstep : ob + H - dstep;
     }
+  };
+  issue(val, dst);
+  while (a < H) {
+    uint32_t val2[kUnroll];
+    uint32_t* dst2[kUnroll];
+    issue(val2, dst2);
 #pragma unroll
-    for (uint32_t u = 0; u < kUnroll; u++)
-      if (ok[u]) drow[beta[u]] = val[u];
+    for (uint32_t u = 0; u < kUnroll; u++) *dst[u] = val[u];
+#pragma unroll
+    for (uint32_t u = 0; u < kUnroll; u++) {
+      val[u] = val2[u];
+      dst[u] = dst2[u];
+    }
   }
+#pragma unroll
+  for (uint32_t u = 0; u < kUnroll; u++) *dst[u] = val[u];
 }
 
 // Encryption of rows [t0, t0+R) of band [lo, hi), round j: gather (Eq. 1)
@@ -200,10 +238,10 @@ __device__ uint32_t enc_tile(const View& v, const Geom& g, uint32_t j, uint32_t 
       for (uint32_t i = 0; i < kPix / 4; i++)
         store4_packed<C>(o + 4 * i * C, make_uint4(d[4 * i], d[4 * i + 1], d[4 * i + 2], d[4 * i + 3]));
     } else {
-      uint4* o = reinterpret_cast<uint4*>(v.dst + ((uint64_t)t0 * W + p0) * 4);
+      uint8_t* o = v.dst + ((uint64_t)t0 * W + p0) * 4;
 #pragma unroll
       for (uint32_t i = 0; i < kPix / 4; i++)
-        o[i] = make_uint4(d[4 * i], d[4 * i + 1], d[4 * i + 2], d[4 * i + 3]);
+        gstore4(o + 16 * i, make_uint4(d[4 * i], d[4 * i + 1], d[4 * i + 2], d[4 * i + 3]));
     }
   }
   return (carry ^ total) & 0xFFu;
@@ -229,6 +267,7 @@ __device__ uint32_t enc_seed(const View& v, const Geom& g, uint32_t band) {
 template <uint32_t C, bool kSrcPacked, bool kDstPacked>
 __device__ void dec_tile(const View& v, const Geom& g, uint32_t j, uint32_t t0, uint32_t R,
                          uint32_t* tile, const uint32_t* blo, const uint32_t* seed) {
+  __shared__ uint32_t sink;  // target of the stores of lanes past the frame
   const uint32_t tid = threadIdx.x, T = blockDim.x;
   const uint32_t W = g.W, H = g.H;
   constexpr uint32_t msk = pixel_mask<C>();
@@ -271,11 +310,10 @@ __device__ void dec_tile(const View& v, const Geom& g, uint32_t j, uint32_t t0, 
         }
 #pragma unroll
         for (uint32_t u = 0; u < kU; u++) {
-          if (!ok[u]) continue;
           const uint32_t prev = first[u] ? sv[u] : (pv[u] >> (8 * (C - 1))) & 0xFFu;
           const uint32_t b = bv[u] & msk, z = zv[u];
           const uint32_t zp = ((z << 8) | prev) & msk;
-          drow[ov[u]] = sub_bytes(b ^ z ^ zp, b) & msk;
+          *(ok[u] ? drow + ov[u] : &sink) = sub_bytes(b ^ z ^ zp, b) & msk;
         }
       }
     }
@@ -287,8 +325,8 @@ __device__ void dec_tile(const View& v, const Geom& g, uint32_t j, uint32_t t0, 
     for (uint32_t q = tid; q < npix / 4; q += T)
       store4_packed<C>(d + (uint64_t)q * 4 * C, reinterpret_cast<const uint4*>(tile)[q]);
   } else {
-    uint4* d = reinterpret_cast<uint4*>(v.dst + (uint64_t)t0 * W * 4);
-    for (uint32_t q = tid; q < npix / 4; q += T) d[q] = reinterpret_cast<const uint4*>(tile)[q];
+    uint8_t* d = v.dst + (uint64_t)t0 * W * 4;
+    for (uint32_t q = tid; q < npix / 4; q += T) gstore4(d + 16 * (uint64_t)q, reinterpret_cast<const uint4*>(tile)[q]);
   }
   __syncthreads();
 }
@@ -304,7 +342,7 @@ __device__ void dec_seeds(const View& v, const Geom& g, uint32_t j, uint32_t* bl
     const uint32_t ip = i + 1 == g.n ? 0 : i + 1;
     const uint64_t first = (uint64_t)blo[ip] * g.W, end = (uint64_t)blo[ip + 1] * g.W;
     const uint64_t Sp = (end - first) * C;
-    const uint8_t bp = v.ks[(uint64_t)g.r * first * C + (uint64_t)j * Sp + Sp - 1];
+    const uint8_t bp = ((const gcu8*)v.ks)[(uint64_t)g.r * first * C + (uint64_t)j * Sp + Sp - 1];
     const uint32_t zl = src_pixel<C, kSrcPacked>(v, end - 1);  // last pixel of band ip
     const uint8_t z1 = (uint8_t)(zl >> (8 * (C - 1))), z0 = (uint8_t)(zl >> (8 * (C - 2)));
     seed[i] = (uint8_t)((bp ^ z1 ^ z0) - bp);
