@@ -15,7 +15,9 @@ launch stream; `roofline_rounds` is the same for the round kernel.
 `cpu_baseline` times the plain CPU oracle on the first frames of the same
 video and checks the GPU output of those frames against it byte for byte.
 
-Two more workloads are reported beside it:
+Three more workloads are reported beside it:
+  `lasm`: the same 768^2 stream with the 2DLASM generator (Sec. 3, Eq. (6),
+  correctly rounded sine); frames/s and ns per generator step.
   `batched`: 64 streams of mixed resolution (480^2, 576^2, 768^2,
   1920x1080) and subframe count (8/16/32), one frame per stream per tick,
   each tick one keystream launch and one persistent rounds launch (shape
@@ -158,6 +160,40 @@ def bench_batched(B, torch, np, args):
     }
 
 
+def bench_lasm(B, torch, np, args):
+    """One 768x768x3 stream with the 2DLASM generator (Sec. 3, Eq. (6)):
+    frames/s of the whole path, ns per generator step, first frame checked
+    against the oracle."""
+    import oracle
+    from paper_2302_07411_amd.inputs import CorrelatedVideo, confusion_seeds, lasm_key
+    dev = torch.device("cuda:0")
+    T = args.lasm_frames
+    pm = lasm_key(N_SUB, 2002)
+    s_c = confusion_seeds(T, 2003)
+    src = CorrelatedVideo(H, W, C, 1002).frames_torch(0, T, dev).reshape(T, F)
+    dst = torch.empty_like(src)
+    key = B.Key(H, W, C, N_SUB, R, pm, map=B.CV_MAP_2DLASM)
+    key.set_launch(batch_frames=T)
+    key.encrypt(src[:1], dst[:1], s_c[:1])  # warm-up frame
+    torch.cuda.synchronize()
+    key.set_profiling(True)
+    t0 = time.perf_counter()
+    key.encrypt(src[1:], dst[1:], s_c[1:])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = key.get_profile()
+    key.get_state()  # raises if a sine could not be rounded
+    want = oracle.LasmKey(H, W, C, N_SUB, R, pm).encrypt(
+        src[:1].cpu().numpy().reshape(1, H, W, C), s_c[:1])
+    mism = int(np.count_nonzero(dst[:1].cpu().numpy().reshape(want.shape) != want))
+    steps_per_chain = prof["prbg_steps"] / N_SUB
+    return {"workload": f"one {H}x{W}x{C} stream, {N_SUB} subframes, {R} rounds, 2DLASM key",
+            "frames_per_s": (T - 1) / wall, "frames": T - 1,
+            "ns_per_step": prof["prbg_ms"] * 1e6 / max(1, steps_per_chain),
+            "prbg_share": prof["prbg_ms"] / max(1e-9, prof["prbg_ms"] + prof["round_ms"]),
+            "oracle_frames": 1, "oracle_mismatched_bytes": mism}
+
+
 def bench_served(B, torch, np, args):
     """256 live streams with Poisson arrivals through the serving loop."""
     import oracle
@@ -265,6 +301,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-stream batched workload")
     ap.add_argument("--no-served", action="store_true", help="skip the 256-stream served workload")
     ap.add_argument("--batched-ticks", type=int, default=20)
+    ap.add_argument("--no-lasm", action="store_true", help="skip the 2DLASM stream")
+    ap.add_argument("--lasm-frames", type=int, default=13)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-ring", type=int, default=8,
                     help="keystream frames generated ahead per served stream")
@@ -410,6 +448,10 @@ def main():
         print("[bench] batched workload", file=sys.stderr, flush=True)
         out["batched"] = bench_batched(B, torch, np, args)
         bad = bad or out["batched"]["oracle_mismatched_bytes"]
+    if not args.no_lasm:
+        print("[bench] 2DLASM stream", file=sys.stderr, flush=True)
+        out["lasm"] = bench_lasm(B, torch, np, args)
+        bad = bad or out["lasm"]["oracle_mismatched_bytes"]
     if not args.no_served:
         print("[bench] served workload", file=sys.stderr, flush=True)
         out["served"] = bench_served(B, torch, np, args)

@@ -71,8 +71,26 @@ __device__ __forceinline__ DD reduce(double t) {
   return fast_two_sum(s.hi, s.lo);
 }
 
+// The fast path's table, staged in LDS by the calling kernel: per point j
+// {sin hi, sin lo, cos hi, cos lo}.  A sine's table read is on the critical
+// path of a generator step, so it must not wait for global memory.
+struct LdsTable {
+  double v[kTab][4];
+};
+
+// Copy the double-double table into LDS (all threads of the workgroup take
+// part; the caller synchronises before use).
+__device__ __forceinline__ void stage_table(LdsTable* t) {
+  for (uint32_t i = threadIdx.x; i < (uint32_t)kTab; i += blockDim.x) {
+    t->v[i][0] = kSinDD[i][0];
+    t->v[i][1] = kSinDD[i][1];
+    t->v[i][2] = kCosDD[i][0];
+    t->v[i][3] = kCosDD[i][1];
+  }
+}
+
 // Fast path; returns false when the rounding cannot be decided.
-__device__ __forceinline__ bool sin_fast(double t, double* out) {
+__device__ __forceinline__ bool sin_fast(double t, const LdsTable* tab, double* out) {
   const DD u = reduce(t);
   int j = (int)(u.hi * 64.0 + 0.5);
   j = j > kTab - 1 ? kTab - 1 : j;
@@ -92,7 +110,7 @@ __device__ __forceinline__ bool sin_fast(double t, double* out) {
   v = dd_add(DD{-kInv6Hi, -kInv6Lo}, dd_mul(z, v));
   v = dd_add_d(dd_mul(z, v), 1.0);
   const DD sh = dd_mul(h, v);
-  const DD S{kSinDD[j][0], kSinDD[j][1]}, C{kCosDD[j][0], kCosDD[j][1]};
+  const DD S{tab->v[j][0], tab->v[j][1]}, C{tab->v[j][2], tab->v[j][3]};
   const DD r = dd_add(S, dd_add(dd_mul(S, cm1), dd_mul(C, sh)));
   // Ziv's rounding test with a 2^-95 relative error bound
   const double e = fabs(r.hi) * 0x1p-95;
@@ -229,9 +247,10 @@ __device__ double sin_exact(double t, bool* undecided) {
 // RN(sin(t)) for t in [0, RN(pi)].  `force_exact` sends every argument at
 // least 2^-30 to the exact path (for testing it); smaller arguments are
 // always decided by the fast path.
-__device__ __forceinline__ double cr_sin(double t, bool force_exact, bool* undecided) {
+__device__ __forceinline__ double cr_sin(double t, const LdsTable* tab, bool force_exact,
+                                         bool* undecided) {
   double r;
-  const bool ok = sin_fast(t, &r);
+  const bool ok = sin_fast(t, tab, &r);
   if (ok && !(force_exact && t >= 0x1p-30)) return r;
   if (t < 0x1p-30) {  // the fast path cannot fail here; keep its result but report
     *undecided = true;

@@ -38,6 +38,9 @@ __global__ __launch_bounds__(128) void prbg_lasm_kernel(const LasmChain* __restr
                                                         uint32_t n_frames, uint32_t force_exact,
                                                         uint32_t* err) {
   __shared__ double2 ring[2][kB][64];
+  __shared__ crsin::LdsTable tab;
+  crsin::stage_table(&tab);
+  __syncthreads();
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   const uint32_t c0 = blockIdx.x * 32;
   const uint32_t nch = min(32u, n_chains - c0);
@@ -60,9 +63,9 @@ __global__ __launch_bounds__(128) void prbg_lasm_kernel(const LasmChain* __restr
     for (uint32_t b = 0; b < nblk; b++) {
       for (uint32_t s = 0; s < kB; s++) {
         const double ax = ((pm * (y + 3.0)) * x) * (1.0 - x);
-        const double nx = crsin::cr_sin(ax, force_exact != 0, &undecided);
+        const double nx = crsin::cr_sin(ax, &tab, force_exact != 0, &undecided);
         const double ay = ((pm * (nx + 3.0)) * y) * (1.0 - y);
-        y = crsin::cr_sin(ay, force_exact != 0, &undecided);
+        y = crsin::cr_sin(ay, &tab, force_exact != 0, &undecided);
         x = nx;
         ring[b & 1u][s][lane] = make_double2(x, y);
       }
@@ -104,10 +107,13 @@ __global__ __launch_bounds__(128) void prbg_lasm_kernel(const LasmChain* __restr
 
 __global__ void cr_sin_kernel(const double* __restrict__ t, double* __restrict__ out, uint64_t n,
                               uint32_t force_exact, uint32_t* undecided) {
+  __shared__ crsin::LdsTable tab;
+  crsin::stage_table(&tab);
+  __syncthreads();
   bool und = false;
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x)
-    out[i] = crsin::cr_sin(t[i], force_exact != 0, &und);
+    out[i] = crsin::cr_sin(t[i], &tab, force_exact != 0, &und);
   if (und) __hip_atomic_store(undecided, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
