@@ -116,11 +116,13 @@ def bench_batched(B, torch, np, args):
     # oracle check of a sample (every 8th stream) on the first tick
     sample = list(range(0, 64, 8))
     mism = 0
+    t_or = time.perf_counter()
     for i in sample:
         h, w, c, n = specs[i]
         want = oracle.PlcmKey(h, w, c, n, R, pms[i]).encrypt(
             srcs[i].cpu().numpy().reshape(1, h, w, c), seeds[i][:1])
         mism += int(np.count_nonzero(outs[i].cpu().numpy().reshape(want.shape) != want))
+    oracle_s = time.perf_counter() - t_or
     for t in range(1, warm):
         b.run(items(t))
     torch.cuda.synchronize()
@@ -157,6 +159,7 @@ def bench_batched(B, torch, np, args):
         "mb_per_s": sum(h * w * c for h, w, c, _ in specs) * ticks / wall / 1e6,
         "shape": shape, "graph_replays": info["graph_replays"],
         "oracle_sample_streams": len(sample), "oracle_mismatched_bytes": mism,
+        "oracle_sample_s": oracle_s,
     }
 
 
@@ -261,6 +264,7 @@ def bench_served(B, torch, np, args):
         lat.append(l + delay * 1e3)
     stats = srv.stats()
     mism = 0
+    t_or = time.perf_counter()
     for i in sample:
         h, w, c, n, dec = specs[i]
         src = (cipher if dec else plain)[(h, w)].cpu().numpy().reshape(1, h, w, c)
@@ -287,7 +291,46 @@ def bench_served(B, torch, np, args):
         "decrypt_streams": sum(1 for s in specs if s[4]),
         "split_cus": bool(stats["split_cus"]), "ring_frames": args.serve_ring, "queue_frames": Q,
         "oracle_sample_streams": len(sample), "oracle_mismatched_bytes": mism,
+        "oracle_sample_s": time.perf_counter() - t_or,
     }
+
+
+def _oracle_worker(args):
+    """One independent stream on one host core: `frames` frames of a seeded
+    768x768x3 video under its own key, timed."""
+    seed, frames = args
+    import oracle
+    from paper_2302_07411_amd.inputs import confusion_seeds, plcm_key, uniform_frames
+    f = uniform_frames(H, W, C, frames, 11000 + seed)
+    key = oracle.PlcmKey(H, W, C, N_SUB, R, plcm_key(N_SUB, 12000 + seed))
+    t0 = time.perf_counter()
+    key.encrypt(f, confusion_seeds(frames, 13000 + seed))
+    return time.perf_counter() - t0
+
+
+def cpu_all_cores(frames_per_core: int):
+    """The oracle on every host core at once, one independent stream per
+    process (aggregate throughput; not the paper's multithreaded design)."""
+    import multiprocessing as mp
+    import platform
+    cores = min(os.cpu_count() or 1, 16)
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        times = pool.map(_oracle_worker, [(i, frames_per_core) for i in range(cores)])
+    wall = time.perf_counter() - t0
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        model = platform.processor()
+    return {"value": cores * frames_per_core / max(times), "unit": "frames/s", "cores": cores,
+            "kind": "oracle", "cpu": model,
+            "sample": f"{cores} processes x {frames_per_core} frames of 768x768x3, one key each "
+                      f"(slowest process {max(times):.1f} s, wall {wall:.1f} s)"}
 
 
 def main():
@@ -297,6 +340,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=48, help="frames per step (2 s of 24 FPS video)")
     ap.add_argument("--cpu-frames", type=int, default=120)
+    ap.add_argument("--cpu-all-frames", type=int, default=8,
+                    help="frames per host core for the all-cores oracle line (0 = skip)")
     ap.add_argument("--latency-frames", type=int, default=48)
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-stream batched workload")
     ap.add_argument("--no-served", action="store_true", help="skip the 256-stream served workload")
@@ -443,6 +488,9 @@ def main():
         "roofline_prbg": roof_prbg,
         "cpu_baseline": cpu,
     }
+    if args.cpu_all_frames > 0:
+        print("[bench] oracle on all host cores", file=sys.stderr, flush=True)
+        out["cpu_all_cores"] = cpu_all_cores(args.cpu_all_frames)
     bad = cpu is not None and cpu["parity_mismatched_bytes"]
     if not args.no_batched:
         print("[bench] batched workload", file=sys.stderr, flush=True)
