@@ -80,6 +80,9 @@ def lib() -> ct.CDLL:
                           ct.POINTER(ct.c_uint32), ct.c_uint64]
         L.oracle_cr_sin_margin.restype = ct.c_int
         L.oracle_cr_sin_margin.argtypes = [ct.c_double, dp, ct.c_int]
+        L.oracle_key_schedule.restype = ct.c_int
+        L.oracle_key_schedule.argtypes = [ct.c_int, dp, u32, dp, ct.c_uint64,
+                                          ct.POINTER(ct.c_uint32), ct.c_uint64]
         L.oracle_cr_sin_array.restype = ct.c_uint64
         L.oracle_cr_sin_array.argtypes = [dp, dp, ct.c_uint64]
         L.oracle_cr_sin.restype = ct.c_int
@@ -162,6 +165,21 @@ def lasm_bytes(m1, m2, nbytes: int):
                                m2[2], nbytes, _u8(out)):
         raise Undecided((m1, m2))
     return out, (x1.value, y1.value), (x2.value, y2.value)
+
+
+def key_schedule(is_lasm: bool, K, n: int, first_frame: int, T: int):
+    """Algorithm 1's key schedule (reading 1): returns (P_m as (n, 4) or (n, 6),
+    s_c for frames first_frame .. first_frame+T-1)."""
+    K = np.ascontiguousarray(np.asarray(K, np.float64))
+    pm = np.zeros(n * (6 if is_lasm else 4), np.float64)
+    sc = np.zeros(max(T, 1), np.uint32)
+    rc = lib().oracle_key_schedule(int(is_lasm), _f64(K), n, _f64(pm), first_frame,
+                                   sc.ctypes.data_as(ct.POINTER(ct.c_uint32)), T)
+    if rc == 1:
+        raise Undecided("key schedule")
+    if rc:
+        raise ValueError("degenerate master key")
+    return pm.reshape(n, -1), sc[:T]
 
 
 def band_lo(H: int, n: int, i: int) -> int:

@@ -168,6 +168,76 @@ int oracle_lasm_bytes(double *x1, double *y1, double mu1, double *x2, double *y2
     return 0;
 }
 
+/* ------------------------------------------------------ key schedule --- */
+
+/* Algorithm 1: the main thread's PRBG_m, initialised with K, gives P_m and
+ * then one s_c per frame.  The conversion is not given by the paper; this is
+ * reading 1 (see the library's header): a draw is one step of the master
+ * (PLCM master: both maps, (u, v) = (x_1, x_2); 2DLASM master: one map,
+ * (u, v) = (x, y)); parameters come from draws with u and v in (0,1), band
+ * after band -- PLCM (x0, p) = (u, v/2) per map; 2DLASM (x0, y0) = (u, v)
+ * then mu = 0.44 + 0.49 u per map -- and after P_m every draw gives one
+ * seed s_c = 1 + ((bits(u) XOR bits(v)) mod 2^16).
+ * is_lasm = 0: K = {x0_1, p_1, x0_2, p_2}; 1: K = {x0, y0, mu}.
+ * Returns 0, 1 (a sine undecided) or 2 (1000 unusable draws in a row). */
+static int master_draw(int is_lasm, double *s, double *u, double *v)
+{
+    if (!is_lasm) {
+        s[0] = oracle_plcm(s[0], s[1]);
+        s[2] = oracle_plcm(s[2], s[3]);
+        *u = s[0];
+        *v = s[2];
+        return 0;
+    }
+    if (oracle_lasm(&s[0], &s[1], s[2]))
+        return 1;
+    *u = s[0];
+    *v = s[1];
+    return 0;
+}
+
+static int master_usable(int is_lasm, double *s, double *u, double *v)
+{
+    for (int tries = 0; tries < 1000; tries++) {
+        if (master_draw(is_lasm, s, u, v))
+            return 1;
+        if (*u > 0.0 && *u < 1.0 && *v > 0.0 && *v < 1.0)
+            return 0;
+    }
+    return 2;
+}
+
+int oracle_key_schedule(int is_lasm, const double *K, uint32_t n, double *pm,
+                        uint64_t first_frame, uint32_t *s_c, uint64_t T)
+{
+    double s[4] = {K[0], K[1], K[2], is_lasm ? 0.0 : K[3]};
+    double u, v;
+    int rc;
+    for (uint32_t i = 0; i < n; i++) {
+        for (int m = 0; m < 2; m++) {
+            if ((rc = master_usable(is_lasm, s, &u, &v)))
+                return rc;
+            if (!is_lasm) {
+                pm[4 * i + 2 * m] = u;
+                pm[4 * i + 2 * m + 1] = v / 2.0;
+            } else {
+                pm[6 * i + 3 * m] = u;
+                pm[6 * i + 3 * m + 1] = v;
+                if ((rc = master_usable(is_lasm, s, &u, &v)))
+                    return rc;
+                pm[6 * i + 3 * m + 2] = 0.44 + 0.49 * u;
+            }
+        }
+    }
+    for (uint64_t t = 0; t < first_frame + T; t++) {
+        if (master_draw(is_lasm, s, &u, &v))
+            return 1;
+        if (t >= first_frame)
+            s_c[t - first_frame] = 1u + (uint32_t)((bits_of(u) ^ bits_of(v)) & 0xFFFFu);
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------ geometry --- */
 
 /* Algorithm 2 (startRow/endRow), generalised so that every row is covered
