@@ -141,6 +141,35 @@ cv_status cv_keysetup(const cv_geom *geom, cv_map map, const double *p_m, size_t
 cv_status cv_cr_sin(const double *t, double *out, size_t n, int force_exact, uint32_t *undecided,
                     void *stream);
 
+/* Key schedule of the main thread (Algorithm 1): PRBG_m, initialised with the
+ * key K, yields the parameters P_m of the n subframe generators and then one
+ * confusion seed s_c per frame.  The paper leaves the conversion of iterates
+ * into parameters open; reading CV_KEY_SCHEDULE_VERSION 1:
+ *  - PLCM master: K = {x0_1, p_1, x0_2, p_2} (ranges as a PLCM record), two
+ *    PLCMs (Eq. 5); a draw advances both and gives (u, v) = their iterates.
+ *    2DLASM master: K = {x0, y0, mu} (the paper's three doubles), one 2DLASM
+ *    (Eq. 6, correctly rounded sine); a draw is one step, (u, v) = (x, y).
+ *  - P_m, band after band, from usable draws (u and v both in (0,1); other
+ *    draws are skipped): PLCM records {x0_1, p_1, x0_2, p_2} take two draws,
+ *    (x0, p) = (u, v/2) each; 2DLASM records {x0_1, y0_1, mu_1, x0_2, y0_2,
+ *    mu_2} take two draws per map, (x0, y0) = (u, v), then
+ *    mu = 0.44 + 0.49*u (inside the admissible [0.44, 0.93]).
+ *  - Then one draw per frame, usable or not: s_c = 1 + ((bits(u) XOR
+ *    bits(v)) mod 2^16), bits() the binary64 pattern.
+ *  p_m       host array of 4*n_sub (PLCM) or 6*n_sub (2DLASM) doubles.
+ *  s_c       host array of n_frames seeds for frames first_frame ...
+ *            first_frame + n_frames - 1 (the earlier draws are generated and
+ *            dropped), so a stream can be resumed at any frame.
+ * Host computation; no device is used, and nothing is written on error
+ * beyond the output arrays.  Errors: CV_E_INVAL (NULL, ranges, sizes, a
+ * degenerate master orbit: 0 is a fixed point of both maps, so after 1000
+ * consecutive unusable draws the key is rejected); CV_E_HIP if a 2DLASM sine
+ * could not be rounded with certainty (the status the device generator
+ * reports for the same event). */
+#define CV_KEY_SCHEDULE_VERSION 1
+cv_status cv_key_schedule(cv_map map, const double *K, size_t n_k, uint32_t n_sub, double *p_m,
+                          size_t n_pm, uint64_t first_frame, uint32_t *s_c, size_t n_frames);
+
 /* Release a key and its device memory (synchronises the device first).
  * NULL is ignored. */
 void cv_key_free(cv_key *key);

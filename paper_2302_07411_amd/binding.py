@@ -30,7 +30,7 @@ EXPORTS = (
     "cv_batch_get_info", "cv_batch_autotune", "cv_batch_set_profiling", "cv_batch_get_profile",
     "cv_server_create", "cv_server_tune", "cv_server_free", "cv_server_drain",
     "cv_server_get_stats", "cv_stream_open", "cv_stream_submit", "cv_stream_poll",
-    "cv_stream_close", "cv_cr_sin",
+    "cv_stream_close", "cv_cr_sin", "cv_key_schedule",
 )
 
 
@@ -149,6 +149,10 @@ def load() -> ct.CDLL:
     L.cv_batch_set_profiling.argtypes = [vp, ct.c_int]
     L.cv_batch_get_profile.restype = ct.c_int
     L.cv_batch_get_profile.argtypes = [vp, ct.POINTER(CvProfile)]
+    L.cv_key_schedule.restype = ct.c_int
+    L.cv_key_schedule.argtypes = [ct.c_int, ct.POINTER(ct.c_double), sz, ct.c_uint32,
+                                  ct.POINTER(ct.c_double), sz, ct.c_uint64,
+                                  ct.POINTER(ct.c_uint32), sz]
     L.cv_cr_sin.restype = ct.c_int
     L.cv_cr_sin.argtypes = [vp, vp, sz, ct.c_int, vp, vp]
     L.cv_server_create.restype = ct.c_int
@@ -478,3 +482,19 @@ def cr_sin(t, out, force_exact: bool = False, stream=None) -> bool:
     _check(load().cv_cr_sin(t.data_ptr(), out.data_ptr(), t.numel(), int(bool(force_exact)),
                             flag.data_ptr(), _stream(stream)))
     return int(flag.item()) == 0
+
+
+def key_schedule(K, n_sub: int, first_frame: int = 0, n_frames: int = 0,
+                 map: int = CV_MAP_PLCM):
+    """Algorithm 1's key schedule (cv_key_schedule): the subframe parameters
+    P_m ((n_sub, 4) for PLCM, (n_sub, 6) for 2DLASM) and the confusion seeds
+    of frames first_frame .. first_frame + n_frames - 1, from the key K."""
+    K = np.ascontiguousarray(np.asarray(K, np.float64).reshape(-1))
+    per = 4 if map == CV_MAP_PLCM else 6
+    pm = np.zeros(per * n_sub, np.float64)
+    sc = np.zeros(max(1, n_frames), np.uint32)
+    _check(load().cv_key_schedule(map, K.ctypes.data_as(ct.POINTER(ct.c_double)), K.size, n_sub,
+                                  pm.ctypes.data_as(ct.POINTER(ct.c_double)), pm.size,
+                                  first_frame, sc.ctypes.data_as(ct.POINTER(ct.c_uint32)),
+                                  n_frames))
+    return pm.reshape(n_sub, per), sc[:n_frames]

@@ -22,6 +22,10 @@
 
 #include "sin_tables.h"
 
+// Host and device: the library's host code uses the same functions for the
+// key schedule of 2DLASM master keys.
+#define CRSIN_HD __host__ __device__ __forceinline__
+
 namespace cv {
 namespace crsin {
 
@@ -29,19 +33,19 @@ struct DD {
   double hi, lo;
 };
 
-__device__ __forceinline__ DD two_sum(double a, double b) {
+CRSIN_HD DD two_sum(double a, double b) {
   const double s = a + b, bb = s - a;
   return {s, (a - (s - bb)) + (b - bb)};
 }
-__device__ __forceinline__ DD fast_two_sum(double a, double b) {  // |a| >= |b| or a == 0
+CRSIN_HD DD fast_two_sum(double a, double b) {  // |a| >= |b| or a == 0
   const double s = a + b;
   return {s, b - (s - a)};
 }
-__device__ __forceinline__ DD two_prod(double a, double b) {
+CRSIN_HD DD two_prod(double a, double b) {
   const double p = a * b;
   return {p, __builtin_fma(a, b, -p)};
 }
-__device__ __forceinline__ DD dd_add(DD a, DD b) {
+CRSIN_HD DD dd_add(DD a, DD b) {
   DD s = two_sum(a.hi, b.hi);
   const DD t = two_sum(a.lo, b.lo);
   s.lo += t.hi;
@@ -49,12 +53,12 @@ __device__ __forceinline__ DD dd_add(DD a, DD b) {
   s.lo += t.lo;
   return fast_two_sum(s.hi, s.lo);
 }
-__device__ __forceinline__ DD dd_add_d(DD a, double b) {
+CRSIN_HD DD dd_add_d(DD a, double b) {
   DD s = two_sum(a.hi, b);
   s.lo += a.lo;
   return fast_two_sum(s.hi, s.lo);
 }
-__device__ __forceinline__ DD dd_mul(DD a, DD b) {
+CRSIN_HD DD dd_mul(DD a, DD b) {
   DD p = two_prod(a.hi, b.hi);
   p.lo += a.hi * b.lo + a.lo * b.hi;
   return fast_two_sum(p.hi, p.lo);
@@ -63,7 +67,7 @@ __device__ __forceinline__ DD dd_mul(DD a, DD b) {
 constexpr double kHalfPi = 0x1.921fb54442d18p+0;  // RN(pi)/2, exactly half of kPiHi
 
 // u = t, or pi - t for t above pi/2, as a normalised double-double.
-__device__ __forceinline__ DD reduce(double t) {
+CRSIN_HD DD reduce(double t) {
   if (t <= kHalfPi) return {t, 0.0};
   const double d = kPiHi - t;  // exact (Sterbenz: t in [kPiHi/2, kPiHi])
   DD s = two_sum(d, kPiMid);
@@ -71,26 +75,40 @@ __device__ __forceinline__ DD reduce(double t) {
   return fast_two_sum(s.hi, s.lo);
 }
 
-// The fast path's table, staged in LDS by the calling kernel: per point j
-// {sin hi, sin lo, cos hi, cos lo}.  A sine's table read is on the critical
-// path of a generator step, so it must not wait for global memory.
+// The fast path's table per point j: {sin hi, sin lo, cos hi, cos lo}.
+// Kernels stage it in LDS (a sine's table read is on the critical path of a
+// generator step and must not wait for global memory); host code fills one
+// copy.
 struct LdsTable {
   double v[kTab][4];
 };
 
-// Copy the double-double table into LDS (all threads of the workgroup take
-// part; the caller synchronises before use).
+CRSIN_HD void fill_entry(LdsTable* t, uint32_t i) {
+  t->v[i][0] = kSinDD[i][0];
+  t->v[i][1] = kSinDD[i][1];
+  t->v[i][2] = kCosDD[i][0];
+  t->v[i][3] = kCosDD[i][1];
+}
+
+// Copy the table into LDS (all threads of the workgroup take part; the
+// caller synchronises before use).
 __device__ __forceinline__ void stage_table(LdsTable* t) {
-  for (uint32_t i = threadIdx.x; i < (uint32_t)kTab; i += blockDim.x) {
-    t->v[i][0] = kSinDD[i][0];
-    t->v[i][1] = kSinDD[i][1];
-    t->v[i][2] = kCosDD[i][0];
-    t->v[i][3] = kCosDD[i][1];
-  }
+  for (uint32_t i = threadIdx.x; i < (uint32_t)kTab; i += blockDim.x) fill_entry(t, i);
+}
+
+CRSIN_HD uint64_t bits_of(double x) { return __builtin_bit_cast(uint64_t, x); }
+
+// High 64 bits of a 64x64-bit product.
+CRSIN_HD uint64_t mulhi64(uint64_t a, uint64_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __umul64hi(a, b);
+#else
+  return (uint64_t)(((unsigned __int128)a * b) >> 64);
+#endif
 }
 
 // Fast path; returns false when the rounding cannot be decided.
-__device__ __forceinline__ bool sin_fast(double t, const LdsTable* tab, double* out) {
+CRSIN_HD bool sin_fast(double t, const LdsTable* tab, double* out) {
   const DD u = reduce(t);
   int j = (int)(u.hi * 64.0 + 0.5);
   j = j > kTab - 1 ? kTab - 1 : j;
@@ -125,9 +143,9 @@ struct F256 {
   uint64_t w[4];
 };
 
-__device__ __forceinline__ F256 fx_load(const uint64_t* p) { return {{p[0], p[1], p[2], p[3]}}; }
+CRSIN_HD F256 fx_load(const uint64_t* p) { return {{p[0], p[1], p[2], p[3]}}; }
 
-__device__ __forceinline__ F256 fx_add(const F256& a, const F256& b) {
+CRSIN_HD F256 fx_add(const F256& a, const F256& b) {
   F256 r;
   uint64_t carry = 0;
 #pragma unroll
@@ -139,7 +157,7 @@ __device__ __forceinline__ F256 fx_add(const F256& a, const F256& b) {
   }
   return r;
 }
-__device__ __forceinline__ F256 fx_neg(const F256& a) {
+CRSIN_HD F256 fx_neg(const F256& a) {
   F256 r;
   uint64_t carry = 1;
 #pragma unroll
@@ -149,11 +167,11 @@ __device__ __forceinline__ F256 fx_neg(const F256& a) {
   }
   return r;
 }
-__device__ __forceinline__ F256 fx_sub(const F256& a, const F256& b) { return fx_add(a, fx_neg(b)); }
-__device__ __forceinline__ bool fx_neg_p(const F256& a) { return (a.w[3] >> 63) != 0; }
+CRSIN_HD F256 fx_sub(const F256& a, const F256& b) { return fx_add(a, fx_neg(b)); }
+CRSIN_HD bool fx_neg_p(const F256& a) { return (a.w[3] >> 63) != 0; }
 
 // Signed product, truncated to the 2^-252 grid.
-__device__ F256 fx_mul(F256 a, F256 b) {
+CRSIN_HD F256 fx_mul(F256 a, F256 b) {
   const bool na = fx_neg_p(a), nb = fx_neg_p(b);
   if (na) a = fx_neg(a);
   if (nb) b = fx_neg(b);
@@ -161,7 +179,7 @@ __device__ F256 fx_mul(F256 a, F256 b) {
   for (int i = 0; i < 4; i++) {
     uint64_t carry = 0;
     for (int k = 0; k < 4; k++) {
-      const uint64_t lo = a.w[i] * b.w[k], hi = __umul64hi(a.w[i], b.w[k]);
+      const uint64_t lo = a.w[i] * b.w[k], hi = mulhi64(a.w[i], b.w[k]);
       uint64_t s = P[i + k] + lo;
       uint64_t c = s < lo;
       s += carry;
@@ -178,8 +196,8 @@ __device__ F256 fx_mul(F256 a, F256 b) {
 }
 
 // Exact conversion of a double in [2^-200, 8) to fixed point.
-__device__ __forceinline__ F256 fx_from_double(double t) {
-  const uint64_t bits = (uint64_t)__double_as_longlong(t);
+CRSIN_HD F256 fx_from_double(double t) {
+  const uint64_t bits = bits_of(t);
   const int e = (int)((bits >> 52) & 0x7FF) - 1023;
   const uint64_t m = (bits & ((1ull << 52) - 1)) | (1ull << 52);
   const int sh = e - 52 + 252;  // position of the mantissa's lowest bit
@@ -190,11 +208,11 @@ __device__ __forceinline__ F256 fx_from_double(double t) {
   return r;
 }
 
-__device__ __forceinline__ int fx_bit(const F256& a, int i) { return (int)((a.w[i >> 6] >> (i & 63)) & 1u); }
+CRSIN_HD int fx_bit(const F256& a, int i) { return (int)((a.w[i >> 6] >> (i & 63)) & 1u); }
 
 // Round a positive fixed-point value to binary64, nearest-even; `undecided`
 // when it lies within 2^10 units of a rounding boundary.
-__device__ double fx_to_double(const F256& R, bool* undecided) {
+CRSIN_HD double fx_to_double(const F256& R, bool* undecided) {
   int p = 255;
   while (p >= 0 && !fx_bit(R, p)) p--;
   if (p < 53) {  // not reached for the arguments of the exact path
@@ -217,7 +235,7 @@ __device__ double fx_to_double(const F256& R, bool* undecided) {
   return ldexp((double)m, low - 252);  // m may be 2^53: still exact
 }
 
-__device__ double sin_exact(double t, bool* undecided) {
+CRSIN_HD double sin_exact(double t, bool* undecided) {
   const F256 tf = fx_from_double(t);
   const F256 u = t <= kHalfPi ? tf : fx_sub(fx_load(kPiFX), tf);
   // j = round(u * 64); 1/64 is 2^246 in fixed point
@@ -247,7 +265,7 @@ __device__ double sin_exact(double t, bool* undecided) {
 // RN(sin(t)) for t in [0, RN(pi)].  `force_exact` sends every argument at
 // least 2^-30 to the exact path (for testing it); smaller arguments are
 // always decided by the fast path.
-__device__ __forceinline__ double cr_sin(double t, const LdsTable* tab, bool force_exact,
+CRSIN_HD double cr_sin(double t, const LdsTable* tab, bool force_exact,
                                          bool* undecided) {
   double r;
   const bool ok = sin_fast(t, tab, &r);

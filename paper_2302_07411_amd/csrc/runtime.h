@@ -114,6 +114,8 @@ cv_status crypt_frames(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
 // Keystream of T frames of one key into ks on st (either map), advancing it.
 cv_status launch_keystream(cv_key* k, uint8_t* ks, uint32_t T, hipStream_t st);
 cv_status queue_err_readback(cv_key* k, hipStream_t st);
+// Sec. 3, Eq. (6): the admissible set of the 2DLASM control parameter.
+bool lasm_mu_ok(double mu);
 // Pixel-word kernels apply to this key and buffers with `threads` threads.
 bool pw_eligible(const cv_key* k, const uint8_t* in, const uint8_t* out, uint32_t threads,
                  size_t lds_max);
