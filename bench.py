@@ -48,6 +48,11 @@ HBM_PEAK_GBS = 8000.0         # MI355X HBM3E
 DEADLINE_MS = 1000.0 / 24     # 24 FPS real-time bound
 # Eq. (5) per iterate: fold 1-x, subtract p, one division; two maps per step
 FLOPS_PER_STEP = 6
+# generator kernel by requested cv_launch.prbg_variant (0 = auto: the verified
+# two-operation quotient for keys in the reciprocal domain, as the bench keys are)
+PRBG_KERNEL = {0: "prbg_plcm_spec_kernel", 1: "prbg_plcm_kernel<exact>",
+               2: "prbg_plcm_kernel<recip>", 3: "prbg_plcm_kernel<recip pair>",
+               4: "prbg_plcm_spec_kernel", 5: "prbg_plcm_spec_kernel<planted errors>"}
 METRIC = "frames/s & GB/s, 5-round enc 768²×3; p50/p99 frame latency batched vs plain"
 
 
@@ -453,7 +458,7 @@ def main():
     dominant_prbg = prof["prbg_ms"] >= prof["round_ms"]
     roof_prbg = {"bound": "alu", "achieved": prbg_tflops, "peak": FP64_PEAK_TFLOPS,
                  "unit": "TFLOP/s", "frac": prbg_tflops / FP64_PEAK_TFLOPS, "traffic": None,
-                 "kernel": "prbg_plcm_kernel", "launch_ms": prbg_launch_ms,
+                 "kernel": PRBG_KERNEL[key.get_launch()["prbg_variant"]], "launch_ms": prbg_launch_ms,
                  "per_launch": f"{prof['prbg_steps'] // max(1, prof['prbg_launches'])} chain steps x "
                                f"{FLOPS_PER_STEP} FP64 ops",
                  "ns_per_step": prof["prbg_ms"] * 1e6 / max(1, prof["prbg_steps"] / N_SUB)}

@@ -96,11 +96,17 @@ typedef struct {
   uint32_t tile_rows_enc;  /* frame rows staged in LDS per step of an encryption round */
   uint32_t tile_rows_dec;  /* frame rows staged in LDS per step of a decryption round */
   uint32_t prbg_variant;   /* keystream generator, all giving the same bytes:
-                              0 auto (fastest valid), 1 IEEE division instruction sequence,
+                              0 auto (fastest valid: 4 where allowed, else 1),
+                              1 IEEE division instruction sequence,
                               2 reciprocal + two FMA corrections (provably correctly rounded
                                 for keys with p >= 2^-64 and states 0 or >= 2^-800),
-                              3 as 2 with one lane per piece of the map.
-                              2 and 3 fall back to 1 for keys outside that domain. */
+                              3 as 2 with one lane per piece of the map,
+                              4 two-operation quotient (multiply + FMA with a double-word
+                                reciprocal) on the chain, every step checked against 2 by
+                                other wavefronts and repaired from the first mismatch,
+                              5 as 4 with a one-bit error planted in every 29th step of
+                                every map (testing the repair; slower).
+                              2..5 fall back to 1 for keys outside 2's domain. */
   uint32_t round_variant;  /* round kernels, all giving the same bytes: 0 auto, 1 byte
                               kernels (any geometry), 2 pixel-word kernels (C in {3,4},
                               W a multiple of 16, 16-byte aligned buffers; otherwise 1) */

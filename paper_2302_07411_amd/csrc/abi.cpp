@@ -10,6 +10,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <cmath>
+
 #include <algorithm>
 #include <mutex>
 #include <string>
@@ -105,7 +107,9 @@ struct Timed {
 int prbg_variant(const cv_key* k) {
   if (!k->fast || k->prbg_variant == 1) return cv::PRBG_EXACT;
   if (k->prbg_variant == 2) return cv::PRBG_RECIP;
-  return cv::PRBG_RECIP_PAIR;
+  if (k->prbg_variant == 3) return cv::PRBG_RECIP_PAIR;
+  if (k->prbg_variant == 5) return cv::PRBG_SPEC_PLANT;
+  return cv::PRBG_SPEC;
 }
 
 uint64_t prbg_steps(const cv_key* k, uint64_t frames) {
@@ -607,6 +611,9 @@ cv_status cv_keysetup(const cv_geom* geom, cv_map map, const double* p_m, size_t
       c.h[m] = 0.5 - c.p[m];
       c.ip[m] = 1.0 / c.p[m];
       c.ih[m] = 1.0 / c.h[m];
+      // 1 - RN(1/d)*d is exact (one FMA), so dividing it by d gives RN(1/d - RN(1/d))
+      c.lp[m] = std::fma(-c.ip[m], c.p[m], 1.0) / c.p[m];
+      c.lh[m] = std::fma(-c.ih[m], c.h[m], 1.0) / c.h[m];
       k->fast = k->fast && cv::plcm_fast_ok(q[2 * m], c.p[m]);
     }
     const uint64_t lo = cv::band_lo(g.H, g.n, i), hi = cv::band_lo(g.H, g.n, i + 1);
@@ -703,7 +710,7 @@ cv_status cv_key_get_launch(const cv_key* k, cv_launch* l) {
 cv_status cv_key_set_launch(cv_key* k, const cv_launch* l) {
   if (!k || !l) return fail(CV_E_INVAL, "NULL argument");
   if (l->batch_frames == 0) return fail(CV_E_INVAL, "batch_frames must be >= 1");
-  if (l->prbg_variant > 3) return fail(CV_E_INVAL, "prbg_variant must be 0..3");
+  if (l->prbg_variant > 5) return fail(CV_E_INVAL, "prbg_variant must be 0..5");
   if (l->round_variant > 2) return fail(CV_E_INVAL, "round_variant must be 0..2");
   const uint32_t tp = pw_tile_limit(k->g, l->threads, l->tile_rows_pw);
   if (tp == 0 && (k->g.C == 3 || k->g.C == 4))

@@ -41,8 +41,8 @@ struct Signature {
   uint8_t* d_ks = nullptr;
   uint8_t* d_scratch = nullptr;
   uint32_t* d_counters = nullptr;
-  uint32_t n_chains[3] = {0, 0, 0};
-  size_t chain_off[3] = {0, 0, 0};
+  uint32_t n_chains[cv::kPrbgVariants] = {};
+  size_t chain_off[cv::kPrbgVariants] = {};
   uint32_t groups[2] = {0, 0};  // C = 3, C = 4
   uint32_t G = 0, threads = 0;
   size_t lds[2] = {0, 0};
@@ -52,7 +52,7 @@ struct Signature {
     bool eq = blob_bytes == o.blob_bytes && d_blob == o.d_blob && d_ks == o.d_ks &&
               d_scratch == o.d_scratch && d_counters == o.d_counters && G == o.G &&
               threads == o.threads && scratch_stride == o.scratch_stride;
-    for (int v = 0; v < 3; v++) eq = eq && n_chains[v] == o.n_chains[v] && chain_off[v] == o.chain_off[v];
+    for (int v = 0; v < cv::kPrbgVariants; v++) eq = eq && n_chains[v] == o.n_chains[v] && chain_off[v] == o.chain_off[v];
     for (int c = 0; c < 2; c++)
       eq = eq && groups[c] == o.groups[c] && lds[c] == o.lds[c] && job_off[c] == o.job_off[c] &&
            gj_off[c] == o.gj_off[c] && go_off[c] == o.go_off[c];
@@ -111,7 +111,7 @@ namespace {
 
 // ------------------------------------------------------------ the plan ---
 struct Plan {
-  std::vector<cv::PlcmChain> chains[3];  // by generator variant
+  std::vector<cv::PlcmChain> chains[cv::kPrbgVariants];  // by generator variant
   std::vector<cv::BatchJob> jobs[2];     // by C (3, 4); ks and gm hold offsets until fill_blob
   std::vector<uint32_t> group_jobs[2], group_off[2];
   std::vector<uint32_t> gm;              // shift tables of every frame job
@@ -274,13 +274,13 @@ void drop_graphs(cv_batch* b) {
 
 // Layout of the blob: chains (3 variants), jobs, group tables, shift tables.
 struct Layout {
-  size_t chain_off[3], job_off[2], gj_off[2], go_off[2], gm_off, bytes;
+  size_t chain_off[cv::kPrbgVariants], job_off[2], gj_off[2], go_off[2], gm_off, bytes;
 };
 
 Layout layout(const Plan& P) {
   Layout L{};
   size_t o = 0;
-  for (int v = 0; v < 3; v++) {
+  for (int v = 0; v < cv::kPrbgVariants; v++) {
     L.chain_off[v] = o;
     o = align_up(o + P.chains[v].size() * sizeof(cv::PlcmChain), 16);
   }
@@ -322,7 +322,7 @@ cv_status ensure_pinned(Slot& s, size_t bytes) {
 // Write the tables into the slot's staging buffer with device addresses.
 void fill_blob(const cv_batch* b, const Plan& P, const Layout& L, uint8_t* h,
                const uint8_t* ks_base) {
-  for (int v = 0; v < 3; v++)
+  for (int v = 0; v < cv::kPrbgVariants; v++)
     if (!P.chains[v].empty())
       memcpy(h + L.chain_off[v], P.chains[v].data(), P.chains[v].size() * sizeof(cv::PlcmChain));
   const uint8_t* d_gm = b->d_blob + L.gm_off;
@@ -348,7 +348,7 @@ Signature signature(const cv_batch* b, const Plan& P, const Layout& L, uint8_t* 
   s.d_ks = ks_base;
   s.d_scratch = b->d_scratch;
   s.d_counters = b->d_counters;
-  for (int v = 0; v < 3; v++) {
+  for (int v = 0; v < cv::kPrbgVariants; v++) {
     s.n_chains[v] = (uint32_t)P.chains[v].size();
     s.chain_off[v] = L.chain_off[v];
   }
@@ -401,11 +401,12 @@ cv_status drain(cv_batch* b) {
 cv_status enqueue_tick(cv_batch* b, const Plan& P, const Layout& L, const Slot& s, hipStream_t st,
                        bool timed, uint8_t* ks_base) {
   CV_HIP(hipMemcpyAsync(b->d_blob, s.h_blob, L.bytes, hipMemcpyHostToDevice, st));
-  const bool has_chains = !P.chains[0].empty() || !P.chains[1].empty() || !P.chains[2].empty();
+  bool has_chains = false;
+  for (const auto& cs : P.chains) has_chains = has_chains || !cs.empty();
   const bool has_jobs = !P.jobs[0].empty() || !P.jobs[1].empty();
   hipEvent_t ta = nullptr;
   if (timed && has_chains && (ta = pooled(b))) CV_HIP(hipEventRecord(ta, st));
-  for (int v = 0; v < 3; v++)
+  for (int v = 0; v < cv::kPrbgVariants; v++)
     if (!P.chains[v].empty())
       CV_HIP(cv::launch_prbg_plcm((const cv::PlcmChain*)(b->d_blob + L.chain_off[v]),
                                   (uint32_t)P.chains[v].size(), ks_base, 0, v, st));
@@ -601,7 +602,8 @@ cv_status batch_enqueue(cv_batch* b, const std::vector<ChainJob>& cj, const std:
   if (s != CV_OK) return s;
   b->info.last_jobs = (uint32_t)(P.jobs[0].size() + P.jobs[1].size());
   b->info.last_groups = P.groups[0] + P.groups[1];
-  b->info.last_chains = (uint32_t)(P.chains[0].size() + P.chains[1].size() + P.chains[2].size());
+  b->info.last_chains = 0;
+  for (const auto& cs : P.chains) b->info.last_chains += (uint32_t)cs.size();
   if (cj.empty() && fj.empty()) return CV_OK;
   Slot* sp = nullptr;
   if ((s = next_slot(b, L.bytes, &sp)) != CV_OK) return s;

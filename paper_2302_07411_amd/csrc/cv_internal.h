@@ -30,6 +30,7 @@ struct PlcmChain {
   double p[2];            // control parameters p of map 1, map 2
   double h[2];            // 1/2 - p, rounded once (bit-identical to forming it per step)
   double ip[2], ih[2];    // RN(1/p), RN(1/h) for the fast division path
+  double lp[2], lh[2];    // RN(1/p - RN(1/p)), RN(1/h - RN(1/h)): low parts of the reciprocals
   uint64_t out_off;       // offset of this band's bytes in a frame's keystream
   uint64_t frame_stride;  // bytes from one frame's keystream to the next
   uint64_t nbytes;        // r * S_i bytes per frame
@@ -60,7 +61,14 @@ hipError_t launch_cr_sin(const double* t, double* out, uint64_t n, uint32_t forc
 // Generator variants (identical bytes): IEEE division; reciprocal division
 // (valid only for chains that satisfy plcm_fast_ok); reciprocal division with
 // one lane per piece of Eq. (5).
-enum PrbgVariant : int { PRBG_EXACT = 0, PRBG_RECIP = 1, PRBG_RECIP_PAIR = 2 };
+enum PrbgVariant : int {
+  PRBG_EXACT = 0,
+  PRBG_RECIP = 1,
+  PRBG_RECIP_PAIR = 2,
+  PRBG_SPEC = 3,        // two-operation quotient, verified and repaired by other wavefronts
+  PRBG_SPEC_PLANT = 4,  // PRBG_SPEC with one-bit errors planted in the producer (testing)
+};
+constexpr int kPrbgVariants = 5;
 
 // Generate n_frames frames of keystream for n_chains chains into ks_base
 // (n_frames = 0: every chain generates its own `frames`).

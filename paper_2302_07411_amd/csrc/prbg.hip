@@ -41,6 +41,23 @@
 // so neither selects its operands; a DPP swap then lets both lanes take the
 // candidate of the piece y actually falls in.  This shortens the dependent
 // chain of a step; 16 chains fit a wavefront.
+//
+// The speculative variant shortens the chain further.  With zh = RN(1/d) and
+// zl = RN(1/d - zh) precomputed, q = RN(zh*y + RN(zl*y)) is one multiply and
+// one FMA; zh + zl carries 1/d to about 2^-106 relative, so q is within one
+// ulp of y/d and equals RN(y/d) unless y/d lies within about 2^-105 (relative)
+// of a rounding midpoint.  Such quotients exist but are extremely rare (none
+// in 2e8 orbit steps, none in 2e6 quotients constructed next to midpoints),
+// and correctness may not rest on rarity: the producer wavefront runs the
+// map with this quotient, two verifier wavefronts check every step against
+// its predecessor (the remainder by one FMA and one Markstein correction
+// must give the value back, see plcm_wrong), and an emitter wavefront turns
+// the block into bytes.  On a mismatch every wavefront takes a repair
+// branch: the producer recomputes the chain from the first wrong step with
+// the correctly rounded fast path above (the rest of that block and the
+// whole block it has produced since), and the emitter writes that chain's
+// bytes again.  The checks run on other SIMDs while the producer iterates,
+// so they cost no time on the chain.
 #include "cv_internal.h"
 
 namespace cv {
@@ -105,6 +122,37 @@ __device__ __forceinline__ double plcm_pair(double x, double p, double off, doub
   const double other = swap_pair(q);
   const bool first = y < p;  // y in [0,p): first piece
   return (first != lane_b) ? q : other;
+}
+
+// Eq. (5), one step, division by the two-operation quotient of the file
+// comment: both pieces are evaluated and the one y falls in is selected, so
+// the dependent chain is 1-x, min, y-p, multiply, FMA, select.
+__device__ __forceinline__ double plcm_two(double x, double p, double zp, double lp, double zh,
+                                           double lh) {
+  const double y = vmin(x, 1.0 - x);
+  const double g = y - p;
+  const double q1 = __builtin_fma(zp, y, lp * y);
+  const double q2 = __builtin_fma(zh, g, lh * g);
+  return y < p ? q1 : q2;
+}
+
+// Whether `cur` differs from the correctly rounded Eq. (5) step from `x`
+// (fast-path domain).  For each piece, the remainder num - cur*den by one FMA
+// and one Markstein correction cur + rem*RN(1/den): if cur is within one ulp
+// of num/den the remainder is exact and the correction is RN(num/den), so it
+// equals cur exactly when cur is right; if cur is further away, the
+// correction moves it by more than half an ulp.  Either way a wrong cur is
+// never accepted.  (The selected piece's comparison decides.)
+__device__ __forceinline__ bool plcm_wrong(double x, double cur, double p, double h, double ip,
+                                           double ih) {
+  const double y = vmin(x, 1.0 - x);
+  const double g = y - p;
+  const double r1 = __builtin_fma(-cur, p, y), r2 = __builtin_fma(-cur, h, g);
+  double c1 = __builtin_fma(r1, ip, cur), c2 = __builtin_fma(r2, ih, cur);
+  // both candidates in registers here: keeps the select branch-free, so the
+  // checks of a block overlap instead of running one masked branch at a time
+  asm volatile("" : "+v"(c1), "+v"(c2));
+  return (y < p ? c1 : c2) != cur;
 }
 
 // Division variants of the generator (identical bytes).
@@ -240,7 +288,8 @@ __global__ __launch_bounds__(128) void prbg_plcm_kernel(const PlcmChain* __restr
 
   if (wave == 0) {
     const uint32_t m = (lane / (kLanes / 2)) & 1u;
-    const double p = ch.p[m], h = ch.h[m], ip = ch.ip[m], ih = ch.ih[m];
+    const double p = m ? ch.p[1] : ch.p[0], h = m ? ch.h[1] : ch.h[0];
+    const double ip = m ? ch.ip[1] : ch.ip[0], ih = m ? ch.ih[1] : ch.ih[0];
     double x = has ? ch.state[m] : 0.0;
     const bool lane_b = lane & 1u;
     const double off = lane_b ? p : 0.0, den = lane_b ? h : p, rcp = lane_b ? ih : ip;
@@ -277,12 +326,156 @@ __global__ __launch_bounds__(128) void prbg_plcm_kernel(const PlcmChain* __restr
   }
 }
 
+// Speculative generator (see the file comment).  Workgroup of four
+// wavefronts: 0 producer, 1 emitter, 2 and 3 verifiers of steps [0,16) and
+// [16,32) of each block.  Lane 2c+m is map m of chain c in every wavefront.
+// Iteration b: the producer fills ring block b while the others take block
+// b-1; a barrier; then, if any verifier found a wrong step, the repair.
+constexpr uint32_t kNoFix = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t ring_index(uint32_t s, uint32_t lane) {
+  return ((s >> 1) * 64 + lane) * 2 + (s & 1u);  // as doubles: step s of a producer lane
+}
+
+template <bool kPlant>
+__global__ __launch_bounds__(256) void prbg_plcm_spec_kernel(const PlcmChain* __restrict__ chains,
+                                                              uint32_t n_chains, uint8_t* ks_base,
+                                                              uint32_t n_frames) {
+  __shared__ double2 ring[2][(kBlock / 2) * 64];
+  __shared__ double lastv[2][64];        // last verified value of blocks of parity 0 / 1
+  __shared__ uint32_t fix_step[2][64];   // per verifier: first wrong step of the lane, or kNoFix
+  __shared__ double fix_val[2][64];      // the verified value before it
+  __shared__ uint32_t fix_count;         // blocks that needed a repair so far
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const uint32_t c0 = blockIdx.x * 32;
+  const uint32_t nch = min(32u, n_chains - c0);
+  const uint32_t c = lane >> 1, m = lane & 1u;
+  const bool has = c < nch;
+  PlcmChain ch{};
+  if (has) ch = chains[c0 + c];
+  const ChainPlan cp = plan(ch, n_frames);
+  const uint32_t nblk = (wave_max(has ? cp.total : 0u) + kBlock - 1) / kBlock;
+  // per-lane map parameters, selected without indexing (which would put `ch` in scratch)
+  const double p = m ? ch.p[1] : ch.p[0], h = m ? ch.h[1] : ch.h[0];
+  const double ip = m ? ch.ip[1] : ch.ip[0], ih = m ? ch.ih[1] : ch.ih[0];
+  const double lp = m ? ch.lp[1] : ch.lp[0], lh = m ? ch.lh[1] : ch.lh[0];
+  double x = has ? ch.state[m] : 0.0;  // the producer's chain value
+  if (wave == 0) lastv[1][lane] = x;   // "block -1" ends with the launch's start state
+  if (threadIdx.x == 0) fix_count = 0;
+  uint8_t* base = ks_base + ch.out_off;
+  Cursor cu{0, 0};  // emitter lane 2c+q writes steps [16q, 16q+16) of each block
+  advance(cu, (lane & 1u) * (kBlock / 2), cp.spf ? cp.spf : 1);
+  uint32_t seen = 0;
+  __syncthreads();
+  __builtin_amdgcn_s_setprio(3);
+
+  for (uint32_t b = 0; b <= nblk; b++) {
+    const Cursor cu_before = cu;
+    if (wave == 0) {
+      if (b < nblk) {
+        double2* dst = &ring[b & 1u][lane];
+        double2 pend = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int s = 0; s < kBlock; s += 2) {
+          double x0 = plcm_two(x, p, ip, lp, ih, lh);
+          if constexpr (kPlant)  // testing: a one-bit error in some steps of every lane
+            if ((b * kBlock + s + 7 * lane) % 29 == 0)
+              x0 = __longlong_as_double(__double_as_longlong(x0) ^ 1);
+          // the previous pair is stored one pair late, so that the store does not
+          // hold up the next step's writes to the registers it reads
+          if (s > 0) dst[(s / 2 - 1) * 64] = pend;
+          x = plcm_two(x0, p, ip, lp, ih, lh);
+          pend = make_double2(x0, x);
+        }
+        dst[(kBlock / 2 - 1) * 64] = pend;
+      }
+    } else if (wave == 1) {
+      if (b > 0 && has)
+        emit_sub<2>(ring[(b - 1) & 1u], c, lane & 1u, b - 1, cp, base, ch.frame_stride, cu,
+                    ch.state);
+    } else if (b > 0) {
+      const uint32_t v = wave - 2;
+      const double* rb = reinterpret_cast<const double*>(ring[(b - 1) & 1u]);
+      constexpr uint32_t kV = kBlock / 2;  // steps per verifier
+      const uint32_t s0 = v * kV;
+      // the claimed values first (all loads in flight together), then every
+      // step recomputed from its claimed predecessor: independent chains
+      double val[kV + 1];
+      val[0] = v == 0 ? lastv[b & 1u][lane] : rb[ring_index(s0 - 1, lane)];
+#pragma unroll
+      for (uint32_t k = 0; k < kV; k++) val[k + 1] = rb[ring_index(s0 + k, lane)];
+      if (v == 1) lastv[(b - 1) & 1u][lane] = val[kV];
+      bool wrong[kV];
+#pragma unroll
+      for (uint32_t k = 0; k < kV; k++) wrong[k] = plcm_wrong(val[k], val[k + 1], p, h, ip, ih);
+      const uint32_t valid = has ? min(kV, cp.total - min(cp.total, (b - 1) * kBlock + s0)) : 0u;
+      uint32_t bad = kNoFix;
+      double want_bad = 0.0;  // the verified predecessor of the first wrong step
+#pragma unroll
+      for (int k = (int)kV - 1; k >= 0; k--)  // the earliest mismatch wins
+        if ((uint32_t)k < valid && wrong[k]) {
+          bad = s0 + (uint32_t)k;
+          want_bad = val[k];
+        }
+      fix_step[v][lane] = bad;
+      fix_val[v][lane] = want_bad;
+      if (__ballot(bad != kNoFix) != 0 && lane == 0) atomicAdd(&fix_count, 1u);
+    }
+    __syncthreads();
+    const uint32_t fc = __builtin_amdgcn_readfirstlane(fix_count);
+    if (fc != seen) {  // the same in every wavefront
+      seen = fc;
+      const uint32_t f0 = fix_step[0][lane], f1 = fix_step[1][lane];
+      if (wave == 0) {
+        const uint32_t s0 = f0 != kNoFix ? f0 : f1;
+        const bool fix = s0 != kNoFix;
+        double y = f0 != kNoFix ? fix_val[0][lane] : fix_val[1][lane];  // step s0 - 1
+        double* rp = reinterpret_cast<double*>(ring[(b - 1) & 1u]);
+        for (uint32_t s = 0; s < kBlock; s++)
+          if (fix && s >= s0) {
+            y = plcm_fast(y, p, h, ip, ih);
+            rp[ring_index(s, lane)] = y;
+          }
+        if (fix) lastv[(b - 1) & 1u][lane] = y;
+        if (b < nblk) {
+          double* rn = reinterpret_cast<double*>(ring[b & 1u]);
+          for (uint32_t s = 0; s < kBlock; s++)
+            if (fix) {
+              y = plcm_fast(y, p, h, ip, ih);
+              rn[ring_index(s, lane)] = y;
+            }
+          if (fix) x = y;
+        }
+      }
+      __syncthreads();
+      if (wave == 1 && has) {
+        const uint32_t g0 = fix_step[0][2 * c], g1 = fix_step[1][2 * c];
+        const uint32_t g2 = fix_step[0][2 * c + 1], g3 = fix_step[1][2 * c + 1];
+        if ((g0 & g1 & g2 & g3) != kNoFix) {  // some map of this chain was repaired
+          Cursor again = cu_before;
+          emit_sub<2>(ring[(b - 1) & 1u], c, lane & 1u, b - 1, cp, base, ch.frame_stride, again,
+                      ch.state);
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_prbg_plcm(const PlcmChain* d_chains, uint32_t n_chains, uint8_t* ks_base,
                             uint32_t n_frames, int variant, hipStream_t s) {
   if (n_chains == 0) return hipSuccess;
   switch (variant) {
+    case PRBG_SPEC:
+      hipLaunchKernelGGL(prbg_plcm_spec_kernel<false>, dim3((n_chains + 31) / 32), dim3(256), 0, s,
+                         d_chains, n_chains, ks_base, n_frames);
+      break;
+    case PRBG_SPEC_PLANT:
+      hipLaunchKernelGGL(prbg_plcm_spec_kernel<true>, dim3((n_chains + 31) / 32), dim3(256), 0, s,
+                         d_chains, n_chains, ks_base, n_frames);
+      break;
     case PRBG_RECIP_PAIR:
       hipLaunchKernelGGL(prbg_plcm_kernel<kRecipPair>, dim3((n_chains + 15) / 16), dim3(128), 0, s,
                          d_chains, n_chains, ks_base, n_frames);

@@ -146,6 +146,7 @@ def test_state_continuation_and_checkpoint(B):
                                                                   tile_rows_dec=1),
     dict(threads=512, tile_rows_enc=3, tile_rows_dec=5, prbg_variant=2), dict(threads=128, tile_rows_enc=7,
                                                               tile_rows_dec=64),
+    dict(prbg_variant=3), dict(prbg_variant=4), dict(batch_frames=2, prbg_variant=5),
 ])
 def test_launch_shapes_give_identical_bytes(B, launch):
     H, W, C, n, r, T = 50, 44, 3, 6, 5, 5
@@ -203,7 +204,7 @@ def test_exact_division_path_and_tiny_keys(B):
     assert np.array_equal(_host(enc, frames.shape), want)
     pm2 = plcm_key(n, 32)
     ref = oracle.PlcmKey(H, W, C, n, r, pm2).keystream(T)
-    for variant in (0, 1, 2, 3):
+    for variant in (0, 1, 2, 3, 4, 5):
         k = B.Key(H, W, C, n, r, pm2)
         k.set_launch(prbg_variant=variant)
         ks = torch.empty(T * r * H * W * C, dtype=torch.uint8, device="cuda:0")
@@ -211,11 +212,15 @@ def test_exact_division_path_and_tiny_keys(B):
         assert np.array_equal(_host(ks, ref.shape), ref)
 
 
-@pytest.mark.parametrize("variant", [2, 3])
+@pytest.mark.parametrize("variant", [2, 3, 4, 5])
 def test_long_keystream(B, variant):
     """About 26 million chain steps (52 million divisions) against the
     oracle: the reciprocal division over long chaotic orbits, 32 chains (two
-    wavefronts in the per-piece variant), frames straddling ring blocks."""
+    wavefronts in the per-piece variant), frames straddling ring blocks.
+    Variant 4 is the verified two-operation quotient; variant 5 plants a
+    one-bit error in every 29th producer step of every lane, so the bytes
+    are right only if the verifiers catch every planted error and the
+    repair recomputes the orbit."""
     H, W, C, n, r, T = 1024, 1024, 3, 32, 5, 10
     pm = plcm_key(n, 4242)
     print(f"[case] long keystream H={H} W={W} C={C} n={n} T={T} variant={variant}", flush=True)
