@@ -448,7 +448,8 @@ def main():
         # one launch runs all rounds: plaintext + cipher + r keystream slices per frame
         round_bytes = (2 + R) * F * prof["round_frames"] / R / max(1, prof["round_launches"])
         per_launch = f"{batch} frames x (2+r)F bytes (plaintext, cipher, keystream)"
-        round_kernel = "rounds_fused_kernel"
+        # encryption on the fused path: the row-run kernel (round_variant auto)
+        round_kernel = "rounds_skew_kernel"
     else:
         # one launch per round: its input, output and keystream slice
         round_bytes = 3 * F * prof["round_frames"] / max(1, prof["round_launches"])

@@ -107,9 +107,11 @@ typedef struct {
                               5 as 4 with a one-bit error planted in every 29th step of
                                 every map (testing the repair; slower).
                               2..5 fall back to 1 for keys outside 2's domain. */
-  uint32_t round_variant;  /* round kernels, all giving the same bytes: 0 auto, 1 byte
-                              kernels (any geometry), 2 pixel-word kernels (C in {3,4},
-                              W a multiple of 16, 16-byte aligned buffers; otherwise 1) */
+  uint32_t round_variant;  /* round kernels, all giving the same bytes: 0 auto (3 where it
+                              applies), 1 byte kernels (any geometry), 2 pixel-word kernels
+                              (C in {3,4}, W a multiple of 16, 16-byte aligned buffers;
+                              otherwise 1), 3 as 2, with CV_PATH_FUSED encryption by whole
+                              source-row runs and packed-byte diffusion */
   uint32_t tile_rows_pw;   /* frame rows per LDS tile of the pixel-word kernels */
   uint32_t fused_groups;   /* CV_PATH_FUSED: frame groups in flight (multiple of 8); 0 = as
                               many as can be resident (reading back gives the value used) */

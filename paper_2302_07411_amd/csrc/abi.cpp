@@ -263,6 +263,8 @@ void set_fused_groups(cv_key* k, uint32_t want) {
   k->fused_cap = 0;
   if (k->tile_pw > 0 && (g.C == 3 || g.C == 4) && g.W % 16 == 0)
     k->fused_cap = cv::rounds_fused_resident_groups(g, k->tile_pw, k->threads, k->device);
+  k->tile_skew = cv::rounds_skew_tile_rows(g, k->lds_max);
+  k->fused_cap_skew = cv::rounds_skew_resident_groups(g, k->tile_skew, k->device);
   const uint32_t w = want / 8 * 8;
   k->fused_groups = (w == 0 || w > k->fused_cap) ? k->fused_cap : w;
 }
@@ -320,11 +322,15 @@ cv_status run_rounds_fused(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* 
   a.g = k->g;
   a.tile_rows = k->tile_pw;
   a.n_frames = T;
-  a.groups = std::min<uint32_t>(k->fused_groups, ((T + 7) / 8) * 8);
+  // encryption by whole source-row runs unless the pixel-word kernels are asked for
+  const bool skew = !decrypt && k->round_variant != 2 && k->fused_cap_skew > 0;
+  const uint32_t cap = skew ? std::min(k->fused_groups, k->fused_cap_skew) : k->fused_groups;
+  a.groups = std::min<uint32_t>(cap, ((T + 7) / 8) * 8);
   a.spin_limit = 1u << 21;  // about two seconds of polling
   a.decrypt = decrypt;
   Timed tm(k, st);
-  CV_HIP(cv::launch_rounds_fused(a, k->threads, st));
+  if (skew) CV_HIP(cv::launch_rounds_skew(a, k->tile_skew, st));
+  else CV_HIP(cv::launch_rounds_fused(a, k->threads, st));
   tm.end(1, (uint64_t)T * k->g.r);
   return queue_err_readback(k, st);
 }
@@ -711,7 +717,7 @@ cv_status cv_key_set_launch(cv_key* k, const cv_launch* l) {
   if (!k || !l) return fail(CV_E_INVAL, "NULL argument");
   if (l->batch_frames == 0) return fail(CV_E_INVAL, "batch_frames must be >= 1");
   if (l->prbg_variant > 5) return fail(CV_E_INVAL, "prbg_variant must be 0..5");
-  if (l->round_variant > 2) return fail(CV_E_INVAL, "round_variant must be 0..2");
+  if (l->round_variant > 3) return fail(CV_E_INVAL, "round_variant must be 0..3");
   const uint32_t tp = pw_tile_limit(k->g, l->threads, l->tile_rows_pw);
   if (tp == 0 && (k->g.C == 3 || k->g.C == 4))
     return fail(CV_E_INVAL, "tile_rows_pw must be >= 1 (and the frame not too wide for threads)");

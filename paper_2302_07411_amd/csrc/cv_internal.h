@@ -137,6 +137,14 @@ hipError_t launch_rounds_fused(const RoundsFusedArgs& a, uint32_t threads, hipSt
 uint32_t rounds_fused_resident_groups(const Geom& g, uint32_t tile_rows, uint32_t threads,
                                       int device);
 
+// All r encryption rounds of a batch of frames by whole source-row runs
+// (rounds_skew.hip): the same arguments as launch_rounds_fused (decrypt must
+// be false), tile rows from rounds_skew_tile_rows, 1024 threads per workgroup.
+size_t rounds_skew_lds_bytes(const Geom& g, uint32_t tile_rows);
+uint32_t rounds_skew_tile_rows(const Geom& g, size_t lds_max);  // 0: not applicable
+uint32_t rounds_skew_resident_groups(const Geom& g, uint32_t tile_rows, int device);
+hipError_t launch_rounds_skew(const RoundsFusedArgs& a, uint32_t tile_rows, hipStream_t s);
+
 // ------------------------------------------------------------- batch ----
 // One (stream, frame) of a multi-stream tick.
 struct BatchJob {

@@ -29,6 +29,8 @@ struct cv_key {
   // and a timeout flag copied back to pinned memory after every launch
   uint32_t fused_groups = 0;   // groups in flight (<= resident capacity)
   uint32_t fused_cap = 0;      // resident capacity for the current launch shape
+  uint32_t tile_skew = 0;      // rows per LDS tile of the row-run encryption kernel (0 = n/a)
+  uint32_t fused_cap_skew = 0; // its resident capacity in groups
   uint8_t* d_fscratch = nullptr;
   uint32_t* d_counters = nullptr;
   uint32_t* d_err = nullptr;

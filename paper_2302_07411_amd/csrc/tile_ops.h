@@ -249,16 +249,21 @@ __device__ uint32_t enc_tile(const View& v, const Geom& g, uint32_t j, uint32_t 
 
 // Seed of band `band` for round j of encryption: the last byte of band
 // (band+1) mod n after confusion, before diffusion, read from the round
-// input through the inverse of Eq. (1).
-template <uint32_t C, bool kSrcPacked>
-__device__ uint32_t enc_seed(const View& v, const Geom& g, uint32_t band) {
+// input through the inverse of Eq. (1).  enc_seed_index gives the source
+// pixel index of that byte (it depends on the frame's shift table only).
+__device__ __forceinline__ uint64_t enc_seed_index(const View& v, const Geom& g, uint32_t band) {
   const uint32_t nb = band + 1 == g.n ? 0 : band + 1;
   const uint32_t alpha = (uint32_t)band_lo(g.H, g.n, nb + 1) - 1;
   uint32_t o = (g.W - 1) + g.W - v.gm[alpha];
   if (o >= g.W) o -= g.W;
   uint32_t a = alpha + g.H - (o % g.H);
   if (a >= g.H) a -= g.H;
-  return (src_pixel<C, kSrcPacked>(v, (uint64_t)a * g.W + o) >> (8 * (C - 1))) & 0xFFu;
+  return (uint64_t)a * g.W + o;
+}
+
+template <uint32_t C, bool kSrcPacked>
+__device__ uint32_t enc_seed(const View& v, const Geom& g, uint32_t band) {
+  return (src_pixel<C, kSrcPacked>(v, enc_seed_index(v, g, band)) >> (8 * (C - 1))) & 0xFFu;
 }
 
 // Decryption of rows [t0, t0+R) of the frame, round j: every output pixel

@@ -302,7 +302,7 @@ PW_GEOMS = [
 ]
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 @pytest.mark.parametrize("tile", [0, 1, 3])
 @pytest.mark.parametrize("geom", PW_GEOMS, ids=[g[0] for g in PW_GEOMS])
 def test_round_variants(B, geom, variant, tile):
@@ -328,21 +328,32 @@ def test_round_variants(B, geom, variant, tile):
     assert np.array_equal(_host(dec, frames.shape), frames)
 
 
+# wide frames: the row-run encryption kernel splits a band into several LDS
+# tiles (19 rows of 1920 pixels), with W a multiple of H and not
+FUSED_GEOMS = PW_GEOMS + [
+    ("wide1920-full", 64, 1920, 3, 2, 5, 2),
+    ("wide1920", 100, 1920, 3, 3, 5, 2),
+]
+
+
+@pytest.mark.parametrize("variant", [2, 3])
 @pytest.mark.parametrize("groups", [0, 8])
-@pytest.mark.parametrize("geom", PW_GEOMS, ids=[g[0] for g in PW_GEOMS])
-def test_fused_path(B, geom, groups):
+@pytest.mark.parametrize("geom", FUSED_GEOMS, ids=[g[0] for g in FUSED_GEOMS])
+def test_fused_path(B, geom, groups, variant):
     """All r rounds in one persistent launch (groups of n workgroups with a
     barrier per round): same bytes as the oracle.  With 8 groups and 20
-    frames every group walks several frames."""
+    frames every group walks several frames.  Variant 2 encrypts with the
+    pixel-word tiles, variant 3 by whole source-row runs."""
     name, H, W, C, n, r, _ = geom
-    T = 20
-    pm, frames, s_c = _case(f"{name} fused groups={groups}", H, W, C, n, r, T, seed=10)
+    T = 20 if W < 1000 else 4
+    pm, frames, s_c = _case(f"{name} fused groups={groups} variant={variant}", H, W, C, n, r, T,
+                            seed=10)
     want = oracle.PlcmKey(H, W, C, n, r, pm).encrypt(frames, s_c)
     src = _dev(frames)
     enc, dec = torch.empty_like(src), torch.empty_like(src)
     k = B.Key(H, W, C, n, r, pm)
     k.set_path(B.CV_PATH_FUSED)
-    k.set_launch(fused_groups=groups)
+    k.set_launch(fused_groups=groups, round_variant=variant)
     assert k.get_launch()["fused_groups"] > 0
     k.encrypt(src, enc, s_c)
     k.get_state()   # raises if a group barrier timed out or a group spanned XCDs
@@ -350,7 +361,7 @@ def test_fused_path(B, geom, groups):
     assert np.array_equal(got, want), f"{np.count_nonzero(got != want)} bytes differ"
     k2 = B.Key(H, W, C, n, r, pm)
     k2.set_path(B.CV_PATH_FUSED)
-    k2.set_launch(fused_groups=groups)
+    k2.set_launch(fused_groups=groups, round_variant=variant)
     k2.decrypt(enc, dec, s_c)
     k2.get_state()
     assert np.array_equal(_host(dec, frames.shape), frames)
