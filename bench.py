@@ -13,7 +13,10 @@ Prints one JSON line (see the keys below).  `roofline` is for the dominant
 kernel of the timed region, measured live with HIP events recorded on the
 launch stream; `roofline_rounds` is the same for the round kernel.
 `cpu_baseline` times the plain CPU oracle on the first frames of the same
-video and checks the GPU output of those frames against it byte for byte.
+video and checks the GPU output of those frames against it byte for byte;
+`cpu_paper_design` does the same with the paper's own multithreaded CPU
+design (one thread per subframe, two barriers per round), and
+`cpu_all_cores` runs one oracle stream per host core.
 
 Three more workloads are reported beside it:
   `lasm`: the same 768^2 stream with the 2DLASM generator (Sec. 3, Eq. (6),
@@ -313,6 +316,188 @@ def _oracle_worker(args):
     return time.perf_counter() - t0
 
 
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def bench_quality(B, torch, np, args, src, dst, s_c, pm):
+    """Sec. 4 and 5 measures of GPU ciphertexts (paper_2302_07411_amd.analysis):
+    uniformity, adjacent-pixel correlation, entropy and local entropy of a
+    768^2 cipher frame; NPCR/UACI of 100 one-pixel changes at 512^2 with the
+    same keystream; key sensitivity (delta = 1e-9); salt-and-pepper noise and
+    block loss before decryption."""
+    from paper_2302_07411_amd import analysis as A
+    from paper_2302_07411_amd.inputs import CorrelatedVideo, confusion_seeds, plcm_key
+    rng = np.random.default_rng(7001)
+    plain = src[0].cpu().numpy().reshape(H, W, C)
+    cipher = dst[0].cpu().numpy().reshape(H, W, C)
+    summ = A.frame_summary(plain, cipher, rng)
+    out = {"frame": "frame 0 of the 768x768x3 video, per channel",
+           "chi2": summ["chi2"], "chi2_critical": A.CHI2_CRITICAL_005,
+           "variance_plain": summ["variance_plain"], "variance_cipher": summ["variance_cipher"],
+           "entropy": summ["entropy"], "local_entropy_30_1936": summ["local_entropy"],
+           "corr_plain": summ["corr_plain"], "corr_cipher": summ["corr_cipher"]}
+    # differential attack: one changed plaintext byte, the same keystream
+    hs = ws = 512
+    fb = hs * ws * C
+    k512 = B.Key(hs, ws, C, N_SUB, R, plcm_key(N_SUB, 7002))
+    ks = torch.empty(R * fb, dtype=torch.uint8, device="cuda")
+    k512.keystream(ks, 1)
+    sc = confusion_seeds(1, 7003)
+    p0 = CorrelatedVideo(hs, ws, C, 7004).frame(0)
+    pd = torch.from_numpy(p0.reshape(-1)).cuda()
+    c1, c2 = torch.empty_like(pd), torch.empty_like(pd)
+    k512.apply_rounds(False, pd, c1, ks, sc)
+    a1 = c1.cpu().numpy().reshape(hs, ws, C)
+    npcr, uaci = [], []
+    for _ in range(100):
+        p2 = p0.copy()
+        i, j, c = int(rng.integers(hs)), int(rng.integers(ws)), int(rng.integers(C))
+        p2[i, j, c] = (int(p2[i, j, c]) + 1) % 256  # one step: the low bit always flips
+        k512.apply_rounds(False, torch.from_numpy(p2.reshape(-1)).cuda(), c2, ks, sc)
+        a2 = c2.cpu().numpy().reshape(hs, ws, C)
+        npcr.append(np.mean([A.npcr(a1[..., q], a2[..., q]) for q in range(C)]))
+        uaci.append(np.mean([A.uaci(a1[..., q], a2[..., q]) for q in range(C)]))
+    out["npcr_uaci_512"] = {
+        "repeats": 100, "npcr_mean": float(np.mean(npcr)), "npcr_min": float(np.min(npcr)),
+        "uaci_mean": float(np.mean(uaci)), "uaci_min": float(np.min(uaci)),
+        "uaci_max": float(np.max(uaci)), "npcr_expected_min": A.NPCR_MIN_512,
+        "uaci_expected": list(A.UACI_RANGE_512),
+        "share_passing": float(np.mean([(n > A.NPCR_MIN_512) and
+                                        (A.UACI_RANGE_512[0] <= u <= A.UACI_RANGE_512[1])
+                                        for n, u in zip(npcr, uaci)]))}
+    # key sensitivity: a master key K through the key schedule (P_m and s_c),
+    # frame 0 encrypted with it and decrypted with K's x0 or p moved by 1e-9
+    Km = [0.6180339887, 0.2718281828, 0.3141592653, 0.1414213562]
+
+    def crypt(decrypt_, K_, frame):
+        pm_, sc_ = B.key_schedule(K_, N_SUB, 0, 1)
+        k = B.Key(H, W, C, N_SUB, R, pm_)
+        x = torch.from_numpy(np.ascontiguousarray(frame).reshape(-1)).cuda()
+        y = torch.empty_like(x)
+        (k.decrypt if decrypt_ else k.encrypt)(x, y, sc_)
+        return y.cpu().numpy().reshape(H, W, C)
+
+    ck = crypt(False, Km, plain)
+    good = crypt(True, Km, ck)
+    sens = {"key": "master key K (PLCM x0_1, p_1, x0_2, p_2) through the key schedule",
+            "exact_with_key": bool(np.array_equal(good, plain))}
+    for name, q in (("x0+1e-9", 0), ("p+1e-9", 1)):
+        K2 = list(Km)
+        K2[q] += 1e-9
+        bad = crypt(True, K2, ck)
+        sens[name] = {"corr_with_correct": float(np.mean([A.correlation(good[..., c], bad[..., c])
+                                                          for c in range(C)])),
+                      "npcr_vs_plain": A.npcr(bad, plain)}
+    out["key_sensitivity"] = sens
+    # channel noise and data loss on the ciphertext, then decryption with the key
+    rob = {}
+    for frac in (0.01, 0.03, 0.05):
+        noisy = A.salt_and_pepper(cipher, frac, rng)
+        rec = decrypt_frame(B, torch, noisy, pm, s_c)
+        rob[f"salt_pepper_{frac:g}"] = {"psnr_db": A.psnr(plain, rec),
+                                        "bytes_exact": float(np.mean(rec == plain))}
+    for size in (64, 128, 384):
+        lost = A.block_loss(cipher, size, 255, rng)
+        rec = decrypt_frame(B, torch, lost, pm, s_c)
+        rob[f"block_{size}"] = {"psnr_db": A.psnr(plain, rec), "bytes_exact": float(np.mean(rec == plain))}
+    out["robustness"] = rob
+    return out
+
+
+def decrypt_frame(B, torch, cipher_np, pm, s_c):
+    k = B.Key(H, W, C, N_SUB, R, pm)
+    c = torch.from_numpy(np_contig(cipher_np)).cuda()
+    d = torch.empty_like(c)
+    k.decrypt(c, d, s_c[:1])
+    return d.cpu().numpy().reshape(H, W, C)
+
+
+def np_contig(a):
+    import numpy as np
+    return np.ascontiguousarray(a).reshape(-1)
+
+
+def bench_sweeps(B, torch, np, args):
+    """Sec. 6 parameter curves on the GPU path: frames/s of one stream against
+    the number of subframes n (576^2 video, as in the paper's thread sweep),
+    and frames/s, NPCR/UACI (10 one-pixel changes, same keystream, 512^2) and
+    the plain/cipher correlation against the number of rounds r = 1..10."""
+    from paper_2302_07411_amd import analysis as A
+    from paper_2302_07411_amd.inputs import CorrelatedVideo, confusion_seeds, plcm_key
+    rng = np.random.default_rng(7101)
+    T = 4
+
+    def fps(h, w, n, r, seed):
+        k = B.Key(h, w, C, n, r, plcm_key(n, seed))
+        k.set_launch(batch_frames=T)
+        fr = torch.from_numpy(CorrelatedVideo(h, w, C, seed).frames(0, T).reshape(-1)).cuda()
+        out = torch.empty_like(fr)
+        sc = confusion_seeds(T, seed)
+        k.encrypt(fr, out, sc)  # warm-up (workspace, first launch)
+        e0, e1 = _events(torch)
+        e0.record()
+        k.encrypt(fr, out, sc)
+        e1.record()
+        torch.cuda.synchronize()
+        return T / (e0.elapsed_time(e1) * 1e-3), fr, out
+
+    subframes = []
+    for n in (1, 2, 4, 8, 16, 32, 64):
+        v, _, _ = fps(576, 576, n, R, 7200 + n)
+        subframes.append({"n": n, "frames_per_s": v})
+    rounds = []
+    hs = ws = 512
+    fb = hs * ws * C
+    p0 = CorrelatedVideo(hs, ws, C, 7300).frame(0)
+    pd = torch.from_numpy(p0.reshape(-1)).cuda()
+    for r in range(1, 11):
+        v, fr, out = fps(H, W, N_SUB, r, 7400 + r)
+        pl = fr[:H * W * C].cpu().numpy().reshape(H, W, C)
+        ci = out[:H * W * C].cpu().numpy().reshape(H, W, C)
+        corr = float(np.mean([A.correlation(pl[..., c], ci[..., c]) for c in range(C)]))
+        k = B.Key(hs, ws, C, N_SUB, r, plcm_key(N_SUB, 7500 + r))
+        ks = torch.empty(r * fb, dtype=torch.uint8, device="cuda")
+        k.keystream(ks, 1)
+        sc = confusion_seeds(1, 7600 + r)
+        c1, c2 = torch.empty_like(pd), torch.empty_like(pd)
+        k.apply_rounds(False, pd, c1, ks, sc)
+        a1 = c1.cpu().numpy()
+        npcr, uaci = [], []
+        for _ in range(10):
+            p2 = p0.copy().reshape(-1)
+            q = int(rng.integers(p2.size))
+            p2[q] = (int(p2[q]) + 1) % 256
+            k.apply_rounds(False, torch.from_numpy(p2).cuda(), c2, ks, sc)
+            a2 = c2.cpu().numpy()
+            npcr.append(A.npcr(a1, a2))
+            uaci.append(A.uaci(a1, a2))
+        rounds.append({"r": r, "frames_per_s_768": v, "npcr_512": float(np.mean(npcr)),
+                       "uaci_512": float(np.mean(uaci)), "corr_plain_cipher_768": corr})
+    return {"subframes_576": subframes, "rounds": rounds,
+            "note": "rounds are full confusion+diffusion rounds; T=4 frames per point"}
+
+
+def cpu_paper_design(src, dst, s_c, n_frames, pm):
+    """The paper's own multithreaded CPU design (oracle/paper_mt.c: one
+    thread per subframe, 2r barriers per frame) on the first n_frames frames
+    of the video; its bytes must equal the GPU output of the same frames."""
+    import numpy as np
+    import oracle
+    frames = src[:n_frames].cpu().numpy().reshape(n_frames, H, W, C)
+    gpu = dst[:n_frames].cpu().numpy().reshape(n_frames, H, W, C)
+    state = np.ascontiguousarray(pm[:, [0, 2]])
+    oracle.lib()  # build/load outside the timed region
+    t0 = time.perf_counter()
+    got = oracle.paper_mt_encrypt(H, W, C, N_SUB, R, pm, state, frames, s_c[:n_frames])
+    dt = time.perf_counter() - t0
+    return {"value": n_frames / dt, "unit": "frames/s", "threads": N_SUB,
+            "host_cores": len(os.sched_getaffinity(0)), "kind": "paper multithreaded design",
+            "sample": f"first {n_frames} frames of the 768x768x3 video, same key and seeds, "
+                      f"{N_SUB} threads, one per subframe ({dt:.2f} s)",
+            "parity_mismatched_bytes": int(np.count_nonzero(got != gpu))}
+
+
 def cpu_all_cores(frames_per_core: int):
     """The oracle on every host core at once, one independent stream per
     process (aggregate throughput; not the paper's multithreaded design)."""
@@ -345,6 +530,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=48, help="frames per step (2 s of 24 FPS video)")
     ap.add_argument("--cpu-frames", type=int, default=120)
+    ap.add_argument("--paper-cpu-frames", type=int, default=240,
+                    help="frames for the paper's multithreaded CPU design (0 = skip)")
     ap.add_argument("--cpu-all-frames", type=int, default=8,
                     help="frames per host core for the all-cores oracle line (0 = skip)")
     ap.add_argument("--latency-frames", type=int, default=48)
@@ -352,6 +539,8 @@ def main():
     ap.add_argument("--no-served", action="store_true", help="skip the 256-stream served workload")
     ap.add_argument("--batched-ticks", type=int, default=20)
     ap.add_argument("--no-lasm", action="store_true", help="skip the 2DLASM stream")
+    ap.add_argument("--no-quality", action="store_true", help="skip the statistical measures")
+    ap.add_argument("--no-sweeps", action="store_true", help="skip the r and n sweeps")
     ap.add_argument("--lasm-frames", type=int, default=13)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-ring", type=int, default=8,
@@ -498,6 +687,10 @@ def main():
         print("[bench] oracle on all host cores", file=sys.stderr, flush=True)
         out["cpu_all_cores"] = cpu_all_cores(args.cpu_all_frames)
     bad = cpu is not None and cpu["parity_mismatched_bytes"]
+    if args.paper_cpu_frames > 0:
+        print("[bench] the paper's multithreaded CPU design", file=sys.stderr, flush=True)
+        out["cpu_paper_design"] = cpu_paper_design(src, dst, s_c, min(args.paper_cpu_frames, total), pm)
+        bad = bad or out["cpu_paper_design"]["parity_mismatched_bytes"]
     if not args.no_batched:
         print("[bench] batched workload", file=sys.stderr, flush=True)
         out["batched"] = bench_batched(B, torch, np, args)
@@ -506,6 +699,12 @@ def main():
         print("[bench] 2DLASM stream", file=sys.stderr, flush=True)
         out["lasm"] = bench_lasm(B, torch, np, args)
         bad = bad or out["lasm"]["oracle_mismatched_bytes"]
+    if not args.no_quality:
+        print("[bench] statistical and security measures", file=sys.stderr, flush=True)
+        out["quality"] = bench_quality(B, torch, np, args, src, dst, s_c, pm)
+    if not args.no_sweeps:
+        print("[bench] round and subframe sweeps", file=sys.stderr, flush=True)
+        out["sweeps"] = bench_sweeps(B, torch, np, args)
     if not args.no_served:
         print("[bench] served workload", file=sys.stderr, flush=True)
         out["served"] = bench_served(B, torch, np, args)

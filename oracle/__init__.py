@@ -14,6 +14,11 @@ and reductions of Eq. (6), hand-traced confusion and diffusion fixtures
 prefix-XOR closed form of Eq. (3), high-precision g tables, round trips,
 bijection/histogram invariants, and the NPCR/UACI and error-propagation
 bounds the construction implies.
+
+``paper_mt.c`` (same library) is the paper's multithreaded CPU design (one
+thread per subframe, two barriers per round), built on the oracle's
+primitives and checked against it; ``bench.py`` times it on the GPU
+machine's host as the paper-design CPU baseline.
 """
 from __future__ import annotations
 
@@ -25,6 +30,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRC_MT = os.path.join(_HERE, "paper_mt.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # binary64 throughout, one IEEE operation per C operator: no FMA contraction,
@@ -37,7 +43,8 @@ def build(force: bool = True) -> str:
     """Compile oracle.c into liboracle.so with gcc and return its path."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lquadmath", "-lm"])
+        subprocess.check_call(["gcc", *CFLAGS, "-pthread", "-o", tmp, _SRC, _SRC_MT,
+                               "-lquadmath", "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -48,7 +55,8 @@ _lib = None
 def lib() -> ct.CDLL:
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
+                os.path.getmtime(_SRC), os.path.getmtime(_SRC_MT)):
             build()
         L = ct.CDLL(_LIB)
         u8p = ct.POINTER(ct.c_uint8)
@@ -83,6 +91,9 @@ def lib() -> ct.CDLL:
         L.oracle_key_schedule.restype = ct.c_int
         L.oracle_key_schedule.argtypes = [ct.c_int, dp, u32, dp, ct.c_uint64,
                                           ct.POINTER(ct.c_uint32), ct.c_uint64]
+        L.paper_mt_encrypt.restype = ct.c_int
+        L.paper_mt_encrypt.argtypes = [u32, u32, u32, u32, u32, dp, dp, u8p, u8p,
+                                       ct.POINTER(ct.c_uint32), ct.c_uint64]
         L.oracle_cr_sin_array.restype = ct.c_uint64
         L.oracle_cr_sin_array.argtypes = [dp, dp, ct.c_uint64]
         L.oracle_cr_sin.restype = ct.c_int
@@ -325,3 +336,20 @@ class LasmKey:
 
     def decrypt(self, frames, s_c) -> np.ndarray:
         return self._rounds(True, frames, s_c)
+
+
+def paper_mt_encrypt(H, W, C, n, r, pm, state, frames, s_c) -> np.ndarray:
+    """The paper's multithreaded design (paper_mt.c): n threads, one per
+    subframe.  `state` is an (n, 2) float64 array of the current x of both
+    maps of every band (advanced in place); returns the cipher frames."""
+    frames = np.ascontiguousarray(frames, dtype=np.uint8)
+    T = frames.shape[0]
+    pm = np.ascontiguousarray(np.asarray(pm, np.float64).reshape(n, 4))
+    assert state.dtype == np.float64 and state.flags.c_contiguous and state.shape == (n, 2)
+    sc = np.ascontiguousarray(np.asarray(s_c, np.uint32).reshape(-1))
+    assert sc.size == T
+    out = np.empty_like(frames)
+    if lib().paper_mt_encrypt(H, W, C, n, r, _f64(pm), _f64(state), _u8(frames), _u8(out),
+                              sc.ctypes.data_as(ct.POINTER(ct.c_uint32)), T):
+        raise MemoryError("paper_mt_encrypt: buffers or threads")
+    return out
