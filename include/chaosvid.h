@@ -142,10 +142,19 @@ cv_status cv_keysetup(const cv_geom *geom, cv_map map, const double *p_m, size_t
 /* The correctly rounded binary64 sine of the 2DLASM generator, RN(sin(t)),
  * exported so that it can be checked against an independent reference.
  * t, out: device arrays of n doubles, each t in [0, RN(pi)] (the range of
- * Eq. 6's arguments).  force_exact = 1 evaluates every argument >= 2^-30 on
- * the 256-bit exact path instead of the double-double fast path.
+ * Eq. 6's arguments).  Three stages: a light evaluation (relative error
+ * below 2^-69.2) with a rounding test, then the double-double fast path
+ * (2^-100), then the 256-bit exact path.  force_exact = 1 skips the first
+ * stage and evaluates every argument >= 2^-30 on the exact path.
  * *undecided (a device word the caller zeroes) is set to 1 if a value could
  * not be rounded with certainty.  Errors: CV_E_INVAL (NULL), CV_E_HIP. */
+/* The first stage of cv_cr_sin on the host, for checking its error bound:
+ * for each t (host arrays of n values, t in [0, RN(pi)]), hi + lo is the
+ * stage's double-double approximation of sin(t) and decided[i] = 1 when its
+ * rounding test accepts hi as RN(sin t) (otherwise the later stages decide).
+ * No device is used.  Errors: CV_E_INVAL (NULL, t outside [0, RN(pi)]). */
+cv_status cv_sin_stage1(const double *t, double *hi, double *lo, int *decided, size_t n);
+
 cv_status cv_cr_sin(const double *t, double *out, size_t n, int force_exact, uint32_t *undecided,
                     void *stream);
 

@@ -30,7 +30,7 @@ EXPORTS = (
     "cv_batch_get_info", "cv_batch_autotune", "cv_batch_set_profiling", "cv_batch_get_profile",
     "cv_server_create", "cv_server_tune", "cv_server_free", "cv_server_drain",
     "cv_server_get_stats", "cv_stream_open", "cv_stream_submit", "cv_stream_poll",
-    "cv_stream_close", "cv_cr_sin", "cv_key_schedule",
+    "cv_stream_close", "cv_cr_sin", "cv_key_schedule", "cv_sin_stage1",
 )
 
 
@@ -149,6 +149,9 @@ def load() -> ct.CDLL:
     L.cv_batch_set_profiling.argtypes = [vp, ct.c_int]
     L.cv_batch_get_profile.restype = ct.c_int
     L.cv_batch_get_profile.argtypes = [vp, ct.POINTER(CvProfile)]
+    L.cv_sin_stage1.restype = ct.c_int
+    L.cv_sin_stage1.argtypes = [ct.POINTER(ct.c_double), ct.POINTER(ct.c_double),
+                                ct.POINTER(ct.c_double), ct.POINTER(ct.c_int), sz]
     L.cv_key_schedule.restype = ct.c_int
     L.cv_key_schedule.argtypes = [ct.c_int, ct.POINTER(ct.c_double), sz, ct.c_uint32,
                                   ct.POINTER(ct.c_double), sz, ct.c_uint64,
@@ -498,3 +501,14 @@ def key_schedule(K, n_sub: int, first_frame: int = 0, n_frames: int = 0,
                                   first_frame, sc.ctypes.data_as(ct.POINTER(ct.c_uint32)),
                                   n_frames))
     return pm.reshape(n_sub, per), sc[:n_frames]
+
+
+def sin_stage1(t):
+    """cv_sin_stage1 (host): (hi, lo, decided) of the sine's first stage."""
+    t = np.ascontiguousarray(np.asarray(t, np.float64).reshape(-1))
+    hi, lo = np.empty_like(t), np.empty_like(t)
+    dec = np.empty(t.size, np.int32)
+    dp = ct.POINTER(ct.c_double)
+    _check(load().cv_sin_stage1(t.ctypes.data_as(dp), hi.ctypes.data_as(dp), lo.ctypes.data_as(dp),
+                                dec.ctypes.data_as(ct.POINTER(ct.c_int)), t.size))
+    return hi, lo, dec.astype(bool)

@@ -3,7 +3,16 @@
 // that range.  Both ends of the cipher must compute the same bits, so the
 // sine is the exactly rounded one: RN(sin(t)).
 //
-// Fast path (every call): reduce t to u = t or pi - t in [0, pi/2 + 2^-53]
+// Stage 1 (every call): u = t or pi - t as above, split u = j/256 + h with
+// |h| <= 2^-9 and a table of sin, cos at j/256 as double-double.  Only
+// cos(j/256)*h is formed exactly (one FMA); the h^2 ... h^7 terms, each at
+// most 2^-19 of the result, are plain doubles.  The evaluation error is
+// below 2^-70 relative (every dropped or rounded term bounded in sin_quick),
+// and a rounding test at 2^-68 accepts the result; otherwise (about one call
+// in 2^15) the fast path decides.  Stage 1 has about a third of the fast
+// path's dependent operations, which set the speed of a 2DLASM chain.
+//
+// Fast path: reduce t to u = t or pi - t in [0, pi/2 + 2^-53]
 // (pi as three doubles, so u is exact to 2^-160), split u = j/64 + h with
 // |h| <= 1/128, and evaluate sin(j/64)cos(h) + cos(j/64)sin(h) in
 // double-double arithmetic (tables of sin, cos at j/64 as double-double,
@@ -75,25 +84,35 @@ CRSIN_HD DD reduce(double t) {
   return fast_two_sum(s.hi, s.lo);
 }
 
-// The fast path's table per point j: {sin hi, sin lo, cos hi, cos lo}.
-// Kernels stage it in LDS (a sine's table read is on the critical path of a
-// generator step and must not wait for global memory); host code fills one
-// copy.
+// The tables per point j: {sin hi, sin lo, cos hi, cos lo}, v1 for stage 1
+// (j/256) and v for the fast path (j/64).  Kernels stage them in LDS (a
+// sine's table read is on the critical path of a generator step and must not
+// wait for global memory); host code fills one copy.
 struct LdsTable {
+  double v1[kTab1][4];
   double v[kTab][4];
 };
 
 CRSIN_HD void fill_entry(LdsTable* t, uint32_t i) {
-  t->v[i][0] = kSinDD[i][0];
-  t->v[i][1] = kSinDD[i][1];
-  t->v[i][2] = kCosDD[i][0];
-  t->v[i][3] = kCosDD[i][1];
+  if (i < (uint32_t)kTab1) {
+    t->v1[i][0] = kSin1DD[i][0];
+    t->v1[i][1] = kSin1DD[i][1];
+    t->v1[i][2] = kCos1DD[i][0];
+    t->v1[i][3] = kCos1DD[i][1];
+  }
+  if (i < (uint32_t)kTab) {
+    t->v[i][0] = kSinDD[i][0];
+    t->v[i][1] = kSinDD[i][1];
+    t->v[i][2] = kCosDD[i][0];
+    t->v[i][3] = kCosDD[i][1];
+  }
 }
+constexpr uint32_t kTabEntries = kTab1 > kTab ? kTab1 : kTab;  // fill_entry indices
 
-// Copy the table into LDS (all threads of the workgroup take part; the
+// Copy the tables into LDS (all threads of the workgroup take part; the
 // caller synchronises before use).
 __device__ __forceinline__ void stage_table(LdsTable* t) {
-  for (uint32_t i = threadIdx.x; i < (uint32_t)kTab; i += blockDim.x) fill_entry(t, i);
+  for (uint32_t i = threadIdx.x; i < kTabEntries; i += blockDim.x) fill_entry(t, i);
 }
 
 CRSIN_HD uint64_t bits_of(double x) { return __builtin_bit_cast(uint64_t, x); }
@@ -105,6 +124,56 @@ CRSIN_HD uint64_t mulhi64(uint64_t a, uint64_t b) {
 #else
   return (uint64_t)(((unsigned __int128)a * b) >> 64);
 #endif
+}
+
+// Stage 1; *hi + *lo is the sine's approximation (relative error below
+// 2^-70), *hi its rounding to double.  Returns false when the rounding test
+// at 2^-68 cannot decide RN(sin t).
+//
+// With u = c + h (c = j/256 with j = rint(256 u.hi), h = a + b: a = u.hi - c
+// exact by Sterbenz' lemma, b = u.lo, |a| <= 2^-9, |b| <= 2^-53 u), and
+// S + s = sin c, C + k = cos c from the table:
+//   sin u = S + C a + [-S a^2/2] + [s + C b + k a - S a b - C a^2 b/2]
+//           + C a^3 (-1/6 + a^2/120 - a^4/5040) + S a^4 (1/24 - a^2/720) + e
+// where e (the h^8 and h^9 terms, the other products with b, table
+// errors) is below 2^-84 of the result R.  On [0, pi/2 + 2^-53],
+// |S| <= 2R and |C a| <= R (1 + 2^-8); C a is formed exactly (P1 + P2), so
+//   -S a^2/2 (at most 2^-18 R, two roundings) errs by at most 2^-70 R;
+//   C a^3/6 (at most 2^-20.5 R, about five roundings) by at most 2^-71.1 R;
+//   the bracket (each term at most 2^-52 R), the a^4 terms (at most
+//   2^-39 R) and the additions of the tail (at most 2^-20.4 R) by at most
+//   2^-72.4 R together.
+// The total, below 2^-69.2 R, is covered by the test bound 2^-68.
+CRSIN_HD bool sin_quick(double t, const LdsTable* tab, double* hi, double* lo) {
+  double uh, ul;
+  if (t <= kHalfPi) {
+    uh = t;
+    ul = 0.0;
+  } else {
+    const DD s = two_sum(kPiHi - t, kPiMid);  // kPiHi - t exact (Sterbenz)
+    uh = s.hi;
+    ul = s.lo + kPiLo;
+  }
+  const double jd = rint(uh * 256.0);  // no rounding error: |uh*256 - jd| <= 1/2
+  const int j = (int)jd;
+  const double c = jd * 0x1p-8;
+  const double a = uh - c;  // exact (Sterbenz for j >= 1)
+  const double b = ul;
+  const double S = tab->v1[j][0], s = tab->v1[j][1], C = tab->v1[j][2], k = tab->v1[j][3];
+  const double q = a * a;
+  const double P1 = C * a, P2 = __builtin_fma(C, a, -P1);  // C a = P1 + P2 exactly
+  const double T2 = -0.5 * (S * q);
+  const double pc = C * (a * q) * (-kInv6Hi + q * (kInv120Hi - q * kInv5040));
+  const double ps = S * (q * q) * (kInv24Hi - q * kInv720Hi);
+  const double small = ((s + C * b) + (k * a - S * (a * b) - 0.5 * (C * (q * b)))) + (ps + pc);
+  const DD s1 = two_sum(S, P1);
+  const DD s2 = two_sum(s1.hi, T2);
+  const double tail = ((s1.lo + s2.lo) + P2) + small;
+  const DD r = fast_two_sum(s2.hi, tail);
+  const double e = fabs(r.hi) * 0x1p-68;
+  *hi = r.hi;
+  *lo = r.lo;
+  return r.hi + (r.lo + e) == r.hi + (r.lo - e);
 }
 
 // Fast path; returns false when the rounding cannot be decided.
@@ -267,7 +336,8 @@ CRSIN_HD double sin_exact(double t, bool* undecided) {
 // always decided by the fast path.
 CRSIN_HD double cr_sin(double t, const LdsTable* tab, bool force_exact,
                                          bool* undecided) {
-  double r;
+  double r, rl;
+  if (!force_exact && sin_quick(t, tab, &r, &rl)) return r;
   const bool ok = sin_fast(t, tab, &r);
   if (ok && !(force_exact && t >= 0x1p-30)) return r;
   if (t < 0x1p-30) {  // the fast path cannot fail here; keep its result but report

@@ -15,6 +15,16 @@
 
 using namespace cv::rt;
 
+// The sine tables for host evaluation (key schedule, cv_sin_stage1).
+const cv::crsin::LdsTable& cv::rt::crsin_host_table() {
+  static const cv::crsin::LdsTable t = [] {
+    cv::crsin::LdsTable v;
+    for (uint32_t i = 0; i < cv::crsin::kTabEntries; i++) cv::crsin::fill_entry(&v, i);
+    return v;
+  }();
+  return t;
+}
+
 namespace {
 
 constexpr int kMaxRejects = 1000;  // consecutive unusable draws before giving up
@@ -25,14 +35,6 @@ double plcm(double x, double p) {
   return x < p ? x / p : (x - p) / (0.5 - p);
 }
 
-const cv::crsin::LdsTable& host_table() {
-  static const cv::crsin::LdsTable t = [] {
-    cv::crsin::LdsTable v;
-    for (uint32_t i = 0; i < (uint32_t)cv::crsin::kTab; i++) cv::crsin::fill_entry(&v, i);
-    return v;
-  }();
-  return t;
-}
 
 // One draw (u, v) of PRBG_m: PLCM master -> the new iterates of its two
 // maps; 2DLASM master -> the new (x, y) of its map (Eq. 6).
@@ -50,9 +52,9 @@ struct Master {
     }
     const double pm = cv::crsin::kPiHi * c;
     const double ax = ((pm * (b + 3.0)) * a) * (1.0 - a);
-    const double nx = cv::crsin::cr_sin(ax, &host_table(), false, &undecided);
+    const double nx = cv::crsin::cr_sin(ax, &crsin_host_table(), false, &undecided);
     const double ay = ((pm * (nx + 3.0)) * b) * (1.0 - b);
-    b = cv::crsin::cr_sin(ay, &host_table(), false, &undecided);
+    b = cv::crsin::cr_sin(ay, &crsin_host_table(), false, &undecided);
     a = nx;
     u = a;
     v = b;
@@ -72,6 +74,15 @@ bool in_open(double v, double lo, double hi) { return v > lo && v < hi; }
 }  // namespace
 
 extern "C" {
+
+cv_status cv_sin_stage1(const double* t, double* hi, double* lo, int* decided, size_t n) {
+  if (n && (!t || !hi || !lo || !decided)) return fail(CV_E_INVAL, "NULL argument");
+  for (size_t i = 0; i < n; i++)
+    if (!(t[i] >= 0.0 && t[i] <= cv::crsin::kPiHi)) return fail(CV_E_INVAL, "t outside [0, RN(pi)]");
+  for (size_t i = 0; i < n; i++)
+    decided[i] = cv::crsin::sin_quick(t[i], &crsin_host_table(), &hi[i], &lo[i]) ? 1 : 0;
+  return CV_OK;
+}
 
 cv_status cv_key_schedule(cv_map map, const double* K, size_t n_k, uint32_t n_sub, double* p_m,
                           size_t n_pm, uint64_t first_frame, uint32_t* s_c, size_t n_frames) {

@@ -154,3 +154,13 @@ bool batch_flag_set(const cv_batch* b);
 
 }  // namespace rt
 }  // namespace cv
+
+namespace cv {
+namespace crsin {
+struct LdsTable;
+}
+namespace rt {
+// The 2DLASM sine's tables for host evaluation (key schedule, cv_sin_stage1).
+const crsin::LdsTable& crsin_host_table();
+}  // namespace rt
+}  // namespace cv
