@@ -102,10 +102,13 @@ typedef struct {
                                 for keys with p >= 2^-64 and states 0 or >= 2^-800),
                               3 as 2 with one lane per piece of the map,
                               4 two-operation quotient (multiply + FMA with a double-word
-                                reciprocal) on the chain, every step checked against 2 by
-                                other wavefronts and repaired from the first mismatch,
-                              5 as 4 with a one-bit error planted in every 29th step of
-                                every map (testing the repair; slower).
+                                reciprocal) on the chain, every step recomputed from
+                                checkpoints and checked against 2 by other wavefronts and
+                                repaired from the first mismatch,
+                              5 as 4 with a one-bit error planted in every 29th producer
+                                step of every map and in every other one of those steps
+                                of the verifiers' recomputation (testing both checks and
+                                the repair; slower).
                               2..5 fall back to 1 for keys outside 2's domain. */
   uint32_t round_variant;  /* round kernels, all giving the same bytes: 0 auto (3 where it
                               applies), 1 byte kernels (any geometry), 2 pixel-word kernels

@@ -49,21 +49,25 @@
 // of a rounding midpoint.  Such quotients exist but are extremely rare (none
 // in 2e8 orbit steps, none in 2e6 quotients constructed next to midpoints),
 // and correctness may not rest on rarity: the producer wavefront runs the
-// map with this quotient, two verifier wavefronts check every step against
-// its predecessor (the remainder by one FMA and one Markstein correction
-// must give the value back, see plcm_wrong), and an emitter wavefront turns
-// the block into bytes.  On a mismatch every wavefront takes a repair
-// branch: the producer recomputes the chain from the first wrong step with
-// the correctly rounded fast path above (the rest of that block and the
-// whole block it has produced since), and the emitter writes that chain's
-// bytes again.  The checks run on other SIMDs while the producer iterates,
-// so they cost no time on the chain.
+// map with this quotient and keeps only two checkpoints per block; two
+// verifier wavefronts recompute the block's steps from the checkpoints with
+// the same operations, check every step against its predecessor (the
+// remainder by one FMA and one Markstein correction must give the value
+// back, see plcm_wrong) and the producer's checkpoints against their own
+// values; an emitter wavefront turns verified blocks into bytes.  On a
+// mismatch every wavefront takes a repair branch: the producer recomputes
+// the failed block and the one after it with the correctly rounded fast path
+// above.  The checks run on other SIMDs while the producer iterates, and the
+// producer writes to LDS only twice per block; the verifiers' recomputation
+// and checks, which take somewhat longer than the producer's block, set the
+// pace.
 #include "cv_internal.h"
 
 namespace cv {
 namespace {
 
 constexpr int kBlock = 32;  // steps per ring block
+constexpr uint32_t kSpecVerifiers = 2;  // verifier wavefronts of the speculative generator
 
 // Eq. (5), one step, exact IEEE division.  x in (1/2,1] is folded to 1-x
 // (exact by Sterbenz' lemma); min(x, 1-x) picks the same value.
@@ -153,6 +157,29 @@ __device__ __forceinline__ bool plcm_wrong(double x, double cur, double p, doubl
   // checks of a block overlap instead of running one masked branch at a time
   asm volatile("" : "+v"(c1), "+v"(c2));
   return (y < p ? c1 : c2) != cur;
+}
+
+// A verifier's step: plcm_two from x (the same operations, so the same value)
+// followed by plcm_wrong's check of that value, sharing the fold and the
+// piece test.  The asm statements here are not volatile, so the compiler may
+// move a step's check past the next steps and fill the chain's latency with
+// it.  `flip` (testing only) flips the last bit of the value before the check.
+__device__ __forceinline__ double plcm_two_checked(double x, double p, double h, double zp,
+                                                   double lp, double zh, double lh, bool flip,
+                                                   bool& wrong) {
+  double y;
+  asm("v_min_f64 %0, %1, %2" : "=v"(y) : "v"(x), "v"(1.0 - x));
+  const double g = y - p;
+  const bool first = y < p;
+  const double q1 = __builtin_fma(zp, y, lp * y);
+  const double q2 = __builtin_fma(zh, g, lh * g);
+  double cur = first ? q1 : q2;
+  if (flip) cur = __longlong_as_double(__double_as_longlong(cur) ^ 1);
+  double c1 = __builtin_fma(__builtin_fma(-cur, p, y), zp, cur);
+  double c2 = __builtin_fma(__builtin_fma(-cur, h, g), zh, cur);
+  asm("" : "+v"(c1), "+v"(c2));
+  wrong = (first ? c1 : c2) != cur;
+  return cur;
 }
 
 // Division variants of the generator (identical bytes).
@@ -326,26 +353,58 @@ __global__ __launch_bounds__(128) void prbg_plcm_kernel(const PlcmChain* __restr
   }
 }
 
-// Speculative generator (see the file comment).  Workgroup of four
-// wavefronts: 0 producer, 1 emitter, 2 and 3 verifiers of steps [0,16) and
-// [16,32) of each block.  Lane 2c+m is map m of chain c in every wavefront.
-// Iteration b: the producer fills ring block b while the others take block
-// b-1; a barrier; then, if any verifier found a wrong step, the repair.
-constexpr uint32_t kNoFix = 0xFFFFFFFFu;
+// Speculative generator (see the file comment).  Workgroup of 2 + kNV
+// wavefronts: 0 producer, 1 emitter, 2.. verifiers of kBlock/kNV steps each.
+// Lane 2c+m is map m of chain c in every wavefront.  The producer keeps only
+// kNV checkpoints per block (the value after the last step of each verifier's
+// segment); verifier v recomputes its segment from the preceding checkpoint
+// with the same two-operation step (bit-identical), writes the values to the
+// ring, checks every step (plcm_wrong's test, reusing the fold) and that its
+// last value equals the producer's checkpoint, which catches a producer that
+// diverged anywhere in the segment.  Iteration b: the producer runs block b,
+// the verifiers block b-1, the emitter block b-2; a barrier; then, if a
+// verifier reported a failure, the repair: the producer recomputes blocks b-1
+// and b from the verified end of block b-2 with the correctly rounded path,
+// and every wavefront notes that block b was repaired, so that its verifiers
+// skip it.  Blocks are emitted only after they are verified or repaired.
 
-__device__ __forceinline__ uint32_t ring_index(uint32_t s, uint32_t lane) {
-  return ((s >> 1) * 64 + lane) * 2 + (s & 1u);  // as doubles: step s of a producer lane
+// Testing only: whether step `pos` of lane `lane` receives a planted error.
+__device__ __forceinline__ bool planted(uint32_t pos, uint32_t lane, uint32_t period) {
+  return (pos + 7 * lane) % period == 0;
 }
 
-template <bool kPlant>
-__global__ __launch_bounds__(256) void prbg_plcm_spec_kernel(const PlcmChain* __restrict__ chains,
-                                                              uint32_t n_chains, uint8_t* ks_base,
-                                                              uint32_t n_frames) {
-  __shared__ double2 ring[2][(kBlock / 2) * 64];
-  __shared__ double lastv[2][64];        // last verified value of blocks of parity 0 / 1
-  __shared__ uint32_t fix_step[2][64];   // per verifier: first wrong step of the lane, or kNoFix
-  __shared__ double fix_val[2][64];      // the verified value before it
-  __shared__ uint32_t fix_count;         // blocks that needed a repair so far
+__device__ __forceinline__ uint32_t ring_index(uint32_t s, uint32_t lane) {
+  return ((s >> 1) * 64 + lane) * 2 + (s & 1u);  // as doubles: step s of a lane
+}
+
+// The two-operation step of plcm_two, also returning the fold y and y - p
+// for the check below.
+__device__ __forceinline__ double plcm_two_yg(double x, double p, double zp, double lp, double zh,
+                                              double lh, double& y, double& g) {
+  y = vmin(x, 1.0 - x);
+  g = y - p;
+  const double q1 = __builtin_fma(zp, y, lp * y);
+  const double q2 = __builtin_fma(zh, g, lh * g);
+  return y < p ? q1 : q2;
+}
+
+// plcm_wrong's test with the fold of the step's input given.
+__device__ __forceinline__ bool plcm_wrong_yg(double y, double g, double cur, double p, double h,
+                                              double ip, double ih) {
+  double c1 = __builtin_fma(__builtin_fma(-cur, p, y), ip, cur);
+  double c2 = __builtin_fma(__builtin_fma(-cur, h, g), ih, cur);
+  asm("" : "+v"(c1), "+v"(c2));  // both candidates: the select stays branch-free
+  return (y < p ? c1 : c2) != cur;
+}
+
+template <bool kPlant, uint32_t kNV>
+__global__ __launch_bounds__((2 + kNV) * 64) void prbg_plcm_spec_kernel(
+    const PlcmChain* __restrict__ chains, uint32_t n_chains, uint8_t* ks_base, uint32_t n_frames) {
+  static_assert(kBlock % kNV == 0, "verifier segments must tile a block");
+  constexpr uint32_t kSeg = kBlock / kNV;  // steps per verifier
+  __shared__ double2 ring[3][(kBlock / 2) * 64];  // values of blocks b-2 (emit), b-1, b (repaired)
+  __shared__ double ckpt[3][kNV][64];    // per block: the value after each segment
+  __shared__ uint32_t fix_count[2];      // repairs so far, of even and of odd iterations
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   const uint32_t c0 = blockIdx.x * 32;
   const uint32_t nch = min(32u, n_chains - c0);
@@ -360,103 +419,82 @@ __global__ __launch_bounds__(256) void prbg_plcm_spec_kernel(const PlcmChain* __
   const double ip = m ? ch.ip[1] : ch.ip[0], ih = m ? ch.ih[1] : ch.ih[0];
   const double lp = m ? ch.lp[1] : ch.lp[0], lh = m ? ch.lh[1] : ch.lh[0];
   double x = has ? ch.state[m] : 0.0;  // the producer's chain value
-  if (wave == 0) lastv[1][lane] = x;   // "block -1" ends with the launch's start state
-  if (threadIdx.x == 0) fix_count = 0;
+  if (wave == 0) ckpt[2][kNV - 1][lane] = x;  // "block -1" ends with the launch's start state
+  if (threadIdx.x < 2) fix_count[threadIdx.x] = 0;
   uint8_t* base = ks_base + ch.out_off;
   Cursor cu{0, 0};  // emitter lane 2c+q writes steps [16q, 16q+16) of each block
   advance(cu, (lane & 1u) * (kBlock / 2), cp.spf ? cp.spf : 1);
-  uint32_t seen = 0;
+  uint32_t seen0 = 0, seen1 = 0;  // fix_count values already acted on
+  bool repaired = false;          // block b-1 was written by a repair (the same in every wavefront)
   __syncthreads();
   __builtin_amdgcn_s_setprio(3);
 
-  for (uint32_t b = 0; b <= nblk; b++) {
-    const Cursor cu_before = cu;
+  for (uint32_t b = 0; b < nblk + 2; b++) {
     if (wave == 0) {
       if (b < nblk) {
-        double2* dst = &ring[b & 1u][lane];
-        double2 pend = make_double2(0.0, 0.0);
+        double* ck = &ckpt[b % 3][0][lane];
 #pragma unroll
-        for (int s = 0; s < kBlock; s += 2) {
-          double x0 = plcm_two(x, p, ip, lp, ih, lh);
+        for (uint32_t s = 0; s < kBlock; s++) {
+          x = plcm_two(x, p, ip, lp, ih, lh);
           if constexpr (kPlant)  // testing: a one-bit error in some steps of every lane
-            if ((b * kBlock + s + 7 * lane) % 29 == 0)
-              x0 = __longlong_as_double(__double_as_longlong(x0) ^ 1);
-          // the previous pair is stored one pair late, so that the store does not
-          // hold up the next step's writes to the registers it reads
-          if (s > 0) dst[(s / 2 - 1) * 64] = pend;
-          x = plcm_two(x0, p, ip, lp, ih, lh);
-          pend = make_double2(x0, x);
+            if (planted(b * kBlock + s, lane, 29))
+              x = __longlong_as_double(__double_as_longlong(x) ^ 1);
+          if (s % kSeg == kSeg - 1) ck[(s / kSeg) * 64] = x;
         }
-        dst[(kBlock / 2 - 1) * 64] = pend;
       }
     } else if (wave == 1) {
-      if (b > 0 && has)
-        emit_sub<2>(ring[(b - 1) & 1u], c, lane & 1u, b - 1, cp, base, ch.frame_stride, cu,
+      if (b >= 2 && has)
+        emit_sub<2>(ring[(b - 2) % 3], c, lane & 1u, b - 2, cp, base, ch.frame_stride, cu,
                     ch.state);
-    } else if (b > 0) {
-      const uint32_t v = wave - 2;
-      const double* rb = reinterpret_cast<const double*>(ring[(b - 1) & 1u]);
-      constexpr uint32_t kV = kBlock / 2;  // steps per verifier
-      const uint32_t s0 = v * kV;
-      // the claimed values first (all loads in flight together), then every
-      // step recomputed from its claimed predecessor: independent chains
-      double val[kV + 1];
-      val[0] = v == 0 ? lastv[b & 1u][lane] : rb[ring_index(s0 - 1, lane)];
+    } else if (b >= 1 && b - 1 < nblk && !repaired) {
+      // block b-1, unless a repair already wrote it (then its values are exact)
+      const uint32_t v = wave - 2, blk = b - 1, s0 = v * kSeg;
+      double* rv = reinterpret_cast<double*>(ring[blk % 3]);
+      const double start = v == 0 ? ckpt[(blk + 2) % 3][kNV - 1][lane] : ckpt[blk % 3][v - 1][lane];
+      const double end = ckpt[blk % 3][v][lane];  // the producer's checkpoint
+      double val[kSeg + 1], y[kSeg], g[kSeg];
+      val[0] = start;
 #pragma unroll
-      for (uint32_t k = 0; k < kV; k++) val[k + 1] = rb[ring_index(s0 + k, lane)];
-      if (v == 1) lastv[(b - 1) & 1u][lane] = val[kV];
-      bool wrong[kV];
+      for (uint32_t k = 0; k < kSeg; k++) {
+        double cur = plcm_two_yg(val[k], p, ip, lp, ih, lh, y[k], g[k]);
+        if constexpr (kPlant)  // half of the producer's planted errors, for the per-step check
+          if (planted(blk * kBlock + s0 + k, lane, 58))
+            cur = __longlong_as_double(__double_as_longlong(cur) ^ 1);
+        rv[ring_index(s0 + k, lane)] = cur;
+        val[k + 1] = cur;
+      }
+      bool bad = end != val[kSeg];
 #pragma unroll
-      for (uint32_t k = 0; k < kV; k++) wrong[k] = plcm_wrong(val[k], val[k + 1], p, h, ip, ih);
-      const uint32_t valid = has ? min(kV, cp.total - min(cp.total, (b - 1) * kBlock + s0)) : 0u;
-      uint32_t bad = kNoFix;
-      double want_bad = 0.0;  // the verified predecessor of the first wrong step
-#pragma unroll
-      for (int k = (int)kV - 1; k >= 0; k--)  // the earliest mismatch wins
-        if ((uint32_t)k < valid && wrong[k]) {
-          bad = s0 + (uint32_t)k;
-          want_bad = val[k];
-        }
-      fix_step[v][lane] = bad;
-      fix_val[v][lane] = want_bad;
-      if (__ballot(bad != kNoFix) != 0 && lane == 0) atomicAdd(&fix_count, 1u);
+      for (uint32_t k = 0; k < kSeg; k++) bad |= plcm_wrong_yg(y[k], g[k], val[k + 1], p, h, ip, ih);
+      // any lane of a chain (lanes past a chain's end hold further orbit
+      // values: a failure there costs a repair, never a wrong byte)
+      if (__ballot(has && bad) != 0 && lane == 0) atomicAdd(&fix_count[b & 1u], 1u);
     }
     __syncthreads();
-    const uint32_t fc = __builtin_amdgcn_readfirstlane(fix_count);
-    if (fc != seen) {  // the same in every wavefront
-      seen = fc;
-      const uint32_t f0 = fix_step[0][lane], f1 = fix_step[1][lane];
+    // Counter of this iteration's parity: a wavefront that runs ahead into
+    // iteration b+1 adds to the other one, so every wavefront reads the same
+    // value here and all or none take the repair branch (and its barrier).
+    const uint32_t fc = __builtin_amdgcn_readfirstlane(fix_count[b & 1u]);
+    const uint32_t seen = (b & 1u) ? seen1 : seen0;
+    repaired = false;
+    if (fc != seen) {  // only after a verifier ran (b >= 1)
+      if (b & 1u) seen1 = fc; else seen0 = fc;
       if (wave == 0) {
-        const uint32_t s0 = f0 != kNoFix ? f0 : f1;
-        const bool fix = s0 != kNoFix;
-        double y = f0 != kNoFix ? fix_val[0][lane] : fix_val[1][lane];  // step s0 - 1
-        double* rp = reinterpret_cast<double*>(ring[(b - 1) & 1u]);
-        for (uint32_t s = 0; s < kBlock; s++)
-          if (fix && s >= s0) {
+        // blocks b-1 and b again from the verified end of block b-2, with
+        // the correctly rounded step
+        const uint32_t blk = b - 1;
+        double y = ckpt[(blk + 2) % 3][kNV - 1][lane];
+        for (uint32_t bb = blk; bb <= b && bb < nblk; bb++) {
+          double* r = reinterpret_cast<double*>(ring[bb % 3]);
+          for (uint32_t s = 0; s < kBlock; s++) {
             y = plcm_fast(y, p, h, ip, ih);
-            rp[ring_index(s, lane)] = y;
+            r[ring_index(s, lane)] = y;
+            if (s % kSeg == kSeg - 1) ckpt[bb % 3][s / kSeg][lane] = y;
           }
-        if (fix) lastv[(b - 1) & 1u][lane] = y;
-        if (b < nblk) {
-          double* rn = reinterpret_cast<double*>(ring[b & 1u]);
-          for (uint32_t s = 0; s < kBlock; s++)
-            if (fix) {
-              y = plcm_fast(y, p, h, ip, ih);
-              rn[ring_index(s, lane)] = y;
-            }
-          if (fix) x = y;
         }
+        if (b < nblk) x = y;
       }
-      __syncthreads();
-      if (wave == 1 && has) {
-        const uint32_t g0 = fix_step[0][2 * c], g1 = fix_step[1][2 * c];
-        const uint32_t g2 = fix_step[0][2 * c + 1], g3 = fix_step[1][2 * c + 1];
-        if ((g0 & g1 & g2 & g3) != kNoFix) {  // some map of this chain was repaired
-          Cursor again = cu_before;
-          emit_sub<2>(ring[(b - 1) & 1u], c, lane & 1u, b - 1, cp, base, ch.frame_stride, again,
-                      ch.state);
-        }
-      }
+      repaired = b < nblk;
       __syncthreads();
     }
   }
@@ -469,11 +507,13 @@ hipError_t launch_prbg_plcm(const PlcmChain* d_chains, uint32_t n_chains, uint8_
   if (n_chains == 0) return hipSuccess;
   switch (variant) {
     case PRBG_SPEC:
-      hipLaunchKernelGGL(prbg_plcm_spec_kernel<false>, dim3((n_chains + 31) / 32), dim3(256), 0, s,
+      hipLaunchKernelGGL((prbg_plcm_spec_kernel<false, kSpecVerifiers>), dim3((n_chains + 31) / 32),
+                         dim3((2 + kSpecVerifiers) * 64), 0, s,
                          d_chains, n_chains, ks_base, n_frames);
       break;
     case PRBG_SPEC_PLANT:
-      hipLaunchKernelGGL(prbg_plcm_spec_kernel<true>, dim3((n_chains + 31) / 32), dim3(256), 0, s,
+      hipLaunchKernelGGL((prbg_plcm_spec_kernel<true, kSpecVerifiers>), dim3((n_chains + 31) / 32),
+                         dim3((2 + kSpecVerifiers) * 64), 0, s,
                          d_chains, n_chains, ks_base, n_frames);
       break;
     case PRBG_RECIP_PAIR:

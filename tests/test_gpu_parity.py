@@ -218,9 +218,11 @@ def test_long_keystream(B, variant):
     oracle: the reciprocal division over long chaotic orbits, 32 chains (two
     wavefronts in the per-piece variant), frames straddling ring blocks.
     Variant 4 is the verified two-operation quotient; variant 5 plants a
-    one-bit error in every 29th producer step of every lane, so the bytes
-    are right only if the verifiers catch every planted error and the
-    repair recomputes the orbit."""
+    one-bit error in every 29th producer step of every lane (found by the
+    checkpoint comparison) and in every 58th step of the verifiers'
+    recomputation (found by the per-step check), so the bytes are right
+    only if the verifiers catch every planted error and the repair
+    recomputes the orbit."""
     H, W, C, n, r, T = 1024, 1024, 3, 32, 5, 10
     pm = plcm_key(n, 4242)
     print(f"[case] long keystream H={H} W={W} C={C} n={n} T={T} variant={variant}", flush=True)
