@@ -67,7 +67,9 @@ namespace cv {
 namespace {
 
 constexpr int kBlock = 32;  // steps per ring block
-constexpr uint32_t kSpecVerifiers = 2;  // verifier wavefronts of the speculative generator
+constexpr uint32_t kSpecVerifiers = 3;  // verifier wavefronts of the speculative generator
+                                        // (two are too slow for the producer; more than
+                                        // three put a fourth wavefront on a shared SIMD)
 
 // Eq. (5), one step, exact IEEE division.  x in (1/2,1] is folded to 1-x
 // (exact by Sterbenz' lemma); min(x, 1-x) picks the same value.
@@ -354,19 +356,21 @@ __global__ __launch_bounds__(128) void prbg_plcm_kernel(const PlcmChain* __restr
 }
 
 // Speculative generator (see the file comment).  Workgroup of 2 + kNV
-// wavefronts: 0 producer, 1 emitter, 2.. verifiers of kBlock/kNV steps each.
-// Lane 2c+m is map m of chain c in every wavefront.  The producer keeps only
-// kNV checkpoints per block (the value after the last step of each verifier's
-// segment); verifier v recomputes its segment from the preceding checkpoint
-// with the same two-operation step (bit-identical), writes the values to the
-// ring, checks every step (plcm_wrong's test, reusing the fold) and that its
-// last value equals the producer's checkpoint, which catches a producer that
-// diverged anywhere in the segment.  Iteration b: the producer runs block b,
-// the verifiers block b-1, the emitter block b-2; a barrier; then, if a
-// verifier reported a failure, the repair: the producer recomputes blocks b-1
-// and b from the verified end of block b-2 with the correctly rounded path,
-// and every wavefront notes that block b was repaired, so that its verifiers
-// skip it.  Blocks are emitted only after they are verified or repaired.
+// wavefronts with the roles producer, emitter and kNV verifiers, assigned at
+// launch from the SIMD each wavefront landed on (the producer alone on its
+// SIMD).  Lane 2c+m is map m of chain c in every wavefront.  The producer
+// keeps only kNV checkpoints per block (the value after the last step of each
+// verifier's segment); verifier v recomputes its segment from the preceding
+// checkpoint with the same two-operation step (bit-identical), writes the
+// values to the ring, checks every step (plcm_wrong's test, reusing the fold)
+// and that its last value equals the producer's checkpoint, which catches a
+// producer that diverged anywhere in the segment.  Iteration b: the producer
+// runs block b, the verifiers block b-1, the emitter block b-2; a barrier;
+// then, if a verifier reported a failure, the repair: the producer recomputes
+// blocks b-1 and b from the verified end of block b-2 with the correctly
+// rounded path, and every wavefront notes that block b was repaired, so that
+// its verifiers skip it.  Blocks are emitted only after they are verified or
+// repaired.
 
 // Testing only: whether step `pos` of lane `lane` receives a planted error.
 __device__ __forceinline__ bool planted(uint32_t pos, uint32_t lane, uint32_t period) {
@@ -397,14 +401,54 @@ __device__ __forceinline__ bool plcm_wrong_yg(double y, double g, double cur, do
   return (y < p ? c1 : c2) != cur;
 }
 
+// Verifier segments: kNV-1 segments of kSegLong steps, then the rest of the
+// block.  With three verifiers the last, shorter one goes to the wavefront
+// that shares its SIMD with the emitter.
+template <uint32_t kNV>
+struct SpecSegments {
+  static constexpr uint32_t kSegLong = kNV == 3 ? 12 : kBlock / kNV;
+  static constexpr uint32_t kSegLast = kBlock - (kNV - 1) * kSegLong;
+  static_assert(kSegLong % 2 == 0 && kSegLast % 2 == 0 && kSegLast <= kSegLong && kSegLast > 0,
+                "segments of whole step pairs");
+  // index of the checkpoint holding the value after step s, or kNV if none
+  static __device__ __forceinline__ uint32_t ckpt_after(uint32_t s) {
+    if (s == kBlock - 1) return kNV - 1;
+    return (s % kSegLong == kSegLong - 1) ? s / kSegLong : kNV;
+  }
+};
+
+// One verifier's segment of kLen steps from `start`: the values go to the
+// ring; returns whether a step failed its check or the last value differs
+// from the producer's checkpoint `end`.
+template <uint32_t kLen, bool kPlant>
+__device__ __forceinline__ bool verify_segment(double start, double end, double* rv, uint32_t s0,
+                                               uint32_t pos0, uint32_t lane, double p, double h,
+                                               double ip, double ih, double lp, double lh) {
+  double val[kLen + 1], y[kLen], g[kLen];
+  val[0] = start;
+#pragma unroll
+  for (uint32_t k = 0; k < kLen; k++) {
+    double cur = plcm_two_yg(val[k], p, ip, lp, ih, lh, y[k], g[k]);
+    if constexpr (kPlant)  // half of the producer's planted errors, for the per-step check
+      if (planted(pos0 + k, lane, 58)) cur = __longlong_as_double(__double_as_longlong(cur) ^ 1);
+    rv[ring_index(s0 + k, lane)] = cur;
+    val[k + 1] = cur;
+  }
+  bool bad = end != val[kLen];
+#pragma unroll
+  for (uint32_t k = 0; k < kLen; k++) bad |= plcm_wrong_yg(y[k], g[k], val[k + 1], p, h, ip, ih);
+  return bad;
+}
+
 template <bool kPlant, uint32_t kNV>
 __global__ __launch_bounds__((2 + kNV) * 64) void prbg_plcm_spec_kernel(
     const PlcmChain* __restrict__ chains, uint32_t n_chains, uint8_t* ks_base, uint32_t n_frames) {
-  static_assert(kBlock % kNV == 0, "verifier segments must tile a block");
-  constexpr uint32_t kSeg = kBlock / kNV;  // steps per verifier
+  using Seg = SpecSegments<kNV>;
+  constexpr uint32_t kWaves = 2 + kNV;
   __shared__ double2 ring[3][(kBlock / 2) * 64];  // values of blocks b-2 (emit), b-1, b (repaired)
   __shared__ double ckpt[3][kNV][64];    // per block: the value after each segment
   __shared__ uint32_t fix_count[2];      // repairs so far, of even and of odd iterations
+  __shared__ uint32_t simd_of[kWaves];   // the SIMD each wavefront runs on
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   const uint32_t c0 = blockIdx.x * 32;
   const uint32_t nch = min(32u, n_chains - c0);
@@ -421,16 +465,40 @@ __global__ __launch_bounds__((2 + kNV) * 64) void prbg_plcm_spec_kernel(
   double x = has ? ch.state[m] : 0.0;  // the producer's chain value
   if (wave == 0) ckpt[2][kNV - 1][lane] = x;  // "block -1" ends with the launch's start state
   if (threadIdx.x < 2) fix_count[threadIdx.x] = 0;
+  uint32_t hwid;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_HW_ID)" : "=s"(hwid));
+  if (lane == 0) simd_of[wave] = (hwid >> 4) & 3u;
   uint8_t* base = ks_base + ch.out_off;
   Cursor cu{0, 0};  // emitter lane 2c+q writes steps [16q, 16q+16) of each block
   advance(cu, (lane & 1u) * (kBlock / 2), cp.spf ? cp.spf : 1);
   uint32_t seen0 = 0, seen1 = 0;  // fix_count values already acted on
   bool repaired = false;          // block b-1 was written by a repair (the same in every wavefront)
   __syncthreads();
+
+  // Roles (the same table in every wavefront): the producer is the first
+  // wavefront alone on its SIMD, the emitter the first other one that shares
+  // a SIMD (else the first other one), the rest verify, ordered by index
+  // except that one sharing the emitter's SIMD comes last.
+  uint32_t per_simd = 0;  // 8 bits per SIMD: wavefronts on it
+  for (uint32_t w = 0; w < kWaves; w++) per_simd += 1u << (8 * simd_of[w]);
+  auto alone = [&](uint32_t w) { return ((per_simd >> (8 * simd_of[w])) & 255u) == 1u; };
+  uint32_t prod = kWaves, emit = kWaves;
+  for (uint32_t w = 0; w < kWaves; w++)
+    if (prod == kWaves && alone(w)) prod = w;
+  if (prod == kWaves) prod = 0;
+  for (uint32_t w = 0; w < kWaves; w++)
+    if (emit == kWaves && w != prod && !alone(w)) emit = w;
+  if (emit == kWaves) emit = prod == 0 ? 1 : 0;
+  auto vkey = [&](uint32_t w) { return (simd_of[w] == simd_of[emit] ? kWaves : 0u) + w; };
+  uint32_t role = wave == prod ? 0u : wave == emit ? 1u : 2u;
+  if (role == 2)
+    for (uint32_t w = 0; w < kWaves; w++)
+      if (w != prod && w != emit && vkey(w) < vkey(wave)) role++;
+  role = __builtin_amdgcn_readfirstlane(role);
   __builtin_amdgcn_s_setprio(3);
 
   for (uint32_t b = 0; b < nblk + 2; b++) {
-    if (wave == 0) {
+    if (role == 0) {
       if (b < nblk) {
         double* ck = &ckpt[b % 3][0][lane];
 #pragma unroll
@@ -439,33 +507,25 @@ __global__ __launch_bounds__((2 + kNV) * 64) void prbg_plcm_spec_kernel(
           if constexpr (kPlant)  // testing: a one-bit error in some steps of every lane
             if (planted(b * kBlock + s, lane, 29))
               x = __longlong_as_double(__double_as_longlong(x) ^ 1);
-          if (s % kSeg == kSeg - 1) ck[(s / kSeg) * 64] = x;
+          if (Seg::ckpt_after(s) < kNV) ck[Seg::ckpt_after(s) * 64] = x;
         }
       }
-    } else if (wave == 1) {
+    } else if (role == 1) {
       if (b >= 2 && has)
         emit_sub<2>(ring[(b - 2) % 3], c, lane & 1u, b - 2, cp, base, ch.frame_stride, cu,
                     ch.state);
     } else if (b >= 1 && b - 1 < nblk && !repaired) {
       // block b-1, unless a repair already wrote it (then its values are exact)
-      const uint32_t v = wave - 2, blk = b - 1, s0 = v * kSeg;
+      const uint32_t v = role - 2, blk = b - 1, s0 = v * Seg::kSegLong;
       double* rv = reinterpret_cast<double*>(ring[blk % 3]);
       const double start = v == 0 ? ckpt[(blk + 2) % 3][kNV - 1][lane] : ckpt[blk % 3][v - 1][lane];
       const double end = ckpt[blk % 3][v][lane];  // the producer's checkpoint
-      double val[kSeg + 1], y[kSeg], g[kSeg];
-      val[0] = start;
-#pragma unroll
-      for (uint32_t k = 0; k < kSeg; k++) {
-        double cur = plcm_two_yg(val[k], p, ip, lp, ih, lh, y[k], g[k]);
-        if constexpr (kPlant)  // half of the producer's planted errors, for the per-step check
-          if (planted(blk * kBlock + s0 + k, lane, 58))
-            cur = __longlong_as_double(__double_as_longlong(cur) ^ 1);
-        rv[ring_index(s0 + k, lane)] = cur;
-        val[k + 1] = cur;
-      }
-      bool bad = end != val[kSeg];
-#pragma unroll
-      for (uint32_t k = 0; k < kSeg; k++) bad |= plcm_wrong_yg(y[k], g[k], val[k + 1], p, h, ip, ih);
+      const bool bad =
+          v < kNV - 1
+              ? verify_segment<Seg::kSegLong, kPlant>(start, end, rv, s0, blk * kBlock + s0, lane,
+                                                      p, h, ip, ih, lp, lh)
+              : verify_segment<Seg::kSegLast, kPlant>(start, end, rv, s0, blk * kBlock + s0, lane,
+                                                      p, h, ip, ih, lp, lh);
       // any lane of a chain (lanes past a chain's end hold further orbit
       // values: a failure there costs a repair, never a wrong byte)
       if (__ballot(has && bad) != 0 && lane == 0) atomicAdd(&fix_count[b & 1u], 1u);
@@ -479,7 +539,7 @@ __global__ __launch_bounds__((2 + kNV) * 64) void prbg_plcm_spec_kernel(
     repaired = false;
     if (fc != seen) {  // only after a verifier ran (b >= 1)
       if (b & 1u) seen1 = fc; else seen0 = fc;
-      if (wave == 0) {
+      if (role == 0) {
         // blocks b-1 and b again from the verified end of block b-2, with
         // the correctly rounded step
         const uint32_t blk = b - 1;
@@ -489,7 +549,7 @@ __global__ __launch_bounds__((2 + kNV) * 64) void prbg_plcm_spec_kernel(
           for (uint32_t s = 0; s < kBlock; s++) {
             y = plcm_fast(y, p, h, ip, ih);
             r[ring_index(s, lane)] = y;
-            if (s % kSeg == kSeg - 1) ckpt[bb % 3][s / kSeg][lane] = y;
+            if (Seg::ckpt_after(s) < kNV) ckpt[bb % 3][Seg::ckpt_after(s)][lane] = y;
           }
         }
         if (b < nblk) x = y;
