@@ -139,7 +139,14 @@ __device__ __forceinline__ double plcm_two(double x, double p, double zp, double
   const double g = y - p;
   const double q1 = __builtin_fma(zp, y, lp * y);
   const double q2 = __builtin_fma(zh, g, lh * g);
-  return y < p ? q1 : q2;
+  // select q1 when y < p, i.e. when g is negative (g = +0 when y = p): a
+  // mask from g's sign bit and two bit-field inserts, so the select does not
+  // wait for a compare (measured 1% faster on the chain than the compare)
+  uint32_t m, lo, hi;
+  asm("v_ashrrev_i32 %0, 31, %1" : "=v"(m) : "v"(__double2hiint(g)));
+  asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(lo) : "v"(m), "v"(__double2loint(q1)), "v"(__double2loint(q2)));
+  asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(hi) : "v"(m), "v"(__double2hiint(q1)), "v"(__double2hiint(q2)));
+  return __hiloint2double((int)hi, (int)lo);
 }
 
 // Whether `cur` differs from the correctly rounded Eq. (5) step from `x`
@@ -457,7 +464,8 @@ __global__ __launch_bounds__((2 + kNV) * 64) void prbg_plcm_spec_kernel(
   PlcmChain ch{};
   if (has) ch = chains[c0 + c];
   const ChainPlan cp = plan(ch, n_frames);
-  const uint32_t nblk = (wave_max(has ? cp.total : 0u) + kBlock - 1) / kBlock;
+  const uint32_t nblk =
+      __builtin_amdgcn_readfirstlane((wave_max(has ? cp.total : 0u) + kBlock - 1) / kBlock);
   // per-lane map parameters, selected without indexing (which would put `ch` in scratch)
   const double p = m ? ch.p[1] : ch.p[0], h = m ? ch.h[1] : ch.h[0];
   const double ip = m ? ch.ip[1] : ch.ip[0], ih = m ? ch.ih[1] : ch.ih[0];
