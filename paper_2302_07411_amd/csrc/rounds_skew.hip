@@ -167,9 +167,21 @@ __device__ uint32_t skew_tile(const View& v, const Geom& g, uint32_t j, uint32_t
     const bool ok = p < np && q < nruns;
     uint32_t P[DW], K[DW];
     {
-      const gcu32* ks32 = (const gcu32*)(kt + (uint64_t)q * KQ * C);
+      // the run's keystream words by 16-byte loads (a lane's KQ*C bytes are
+      // only 4-byte aligned); lanes without a run read run 0 and drop it
+      const uint8_t* kp = kt + (uint64_t)(ok ? q : 0u) * KQ * C;
 #pragma unroll
-      for (uint32_t i = 0; i < DW; i++) K[i] = ok ? ks32[i] : 0u;
+      for (uint32_t i = 0; i + 4 <= DW; i += 4) {
+        const v4u32a4 w = gload4u(kp + 4 * i);
+        K[i] = w.x;
+        K[i + 1] = w.y;
+        K[i + 2] = w.z;
+        K[i + 3] = w.w;
+      }
+#pragma unroll
+      for (uint32_t i = DW / 4 * 4; i < DW; i++) K[i] = g32(kp)[i];
+#pragma unroll
+      for (uint32_t i = 0; i < DW; i++) K[i] = ok ? K[i] : 0u;
     }
     if (ok) {
       const uint32_t k = q / rpr, b0 = (q - k * rpr) * KQ;
@@ -214,6 +226,11 @@ __device__ uint32_t skew_tile(const View& v, const Geom& g, uint32_t j, uint32_t
   const uint32_t wincl = wave_xor_incl(wl);
   const uint32_t before = wave == 0 ? 0u : (uint32_t)__builtin_amdgcn_readlane((int)wincl, (int)wave - 1);
   const uint32_t all = (uint32_t)__builtin_amdgcn_readlane((int)wincl, kWaves - 1);
+  // Stores staged through the tile (free: every wavefront has read it before
+  // the block scan's barrier; run q's output words go to words [q*OW, (q+1)*OW),
+  // within the tile since q*KQ is a pixel of it), so that each store
+  // instruction writes 1 KB of consecutive bytes.
+  constexpr uint32_t OW = kDstPacked ? DW : KQ;   // output words per run
 #pragma unroll
   for (uint32_t p = 0; p < NP; p++) {
     const uint32_t q = (wave * np + p) * 64 + lane;
@@ -222,12 +239,11 @@ __device__ uint32_t skew_tile(const View& v, const Geom& g, uint32_t j, uint32_t
     uint32_t out[DW];
 #pragma unroll
     for (uint32_t i = 0; i < DW; i++) out[i] = Z[p][i] ^ c;
+    uint32_t* st = lds + q * OW;
     if constexpr (kDstPacked) {
-      gu32* o = (gu32*)(v.dst + ((uint64_t)t0 * W + (uint64_t)q * KQ) * C);
 #pragma unroll
-      for (uint32_t i = 0; i < DW; i++) o[i] = out[i];
+      for (uint32_t i = 0; i < DW; i++) st[i] = out[i];
     } else {
-      uint8_t* o = v.dst + ((uint64_t)t0 * W + (uint64_t)q * KQ) * 4;
 #pragma unroll
       for (uint32_t i = 0; i < KQ / 4; i++) {
         uint32_t w4[4];
@@ -237,9 +253,28 @@ __device__ uint32_t skew_tile(const View& v, const Geom& g, uint32_t j, uint32_t
 #pragma unroll
           for (uint32_t e = 0; e < 4; e++) w4[e] = out[4 * i + e];
         }
-        gstore4(o + 16 * i, make_uint4(w4[0], w4[1], w4[2], w4[3]));
+        *reinterpret_cast<uint4*>(st + 4 * i) = make_uint4(w4[0], w4[1], w4[2], w4[3]);
       }
     }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  constexpr uint32_t OB = kDstPacked ? C : 4;      // output bytes per pixel
+#pragma unroll
+  for (uint32_t p = 0; p < NP; p++) {
+    const uint32_t q0 = (wave * np + p) * 64;
+    if (!(p < np && q0 < nruns)) continue;
+    const uint32_t words = min(64u, nruns - q0) * OW;
+    const uint32_t chunks = words / 4;            // whole 16-byte chunks of this pass
+    uint8_t* ob = v.dst + ((uint64_t)t0 * W + (uint64_t)q0 * KQ) * OB;
+    const uint32_t* sp = lds + q0 * OW;
+#pragma unroll
+    for (uint32_t i = 0; i < (64 * OW / 4 + 63) / 64; i++) {
+      const uint32_t ch = 64 * i + lane;
+      if (ch < chunks) gstore4(ob + 16 * ch, *reinterpret_cast<const uint4*>(sp + 4 * ch));
+    }
+    if (lane < words % 4) ((gu32*)ob)[4 * chunks + lane] = sp[4 * chunks + lane];
   }
   return (carry ^ all) & 0xFFu;
 }

@@ -24,6 +24,12 @@ __device__ __forceinline__ uint4 gload4(const void* p) {
   const v4u32 x = *(const gv4*)p;
   return make_uint4(x.x, x.y, x.z, x.w);
 }
+// 16 bytes from a global address that is only 4-byte aligned: one
+// global_load_dwordx4 instead of four dword loads.
+typedef uint32_t v4u32a4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef __attribute__((address_space(1))) const v4u32a4 gcv4a4;
+__device__ __forceinline__ v4u32a4 gload4u(const void* p) { return *(gcv4a4*)p; }
+
 __device__ __forceinline__ void gstore4(void* p, uint4 v) {
   v4u32 x;
   x.x = v.x;
