@@ -204,11 +204,33 @@ __device__ uint32_t enc_tile(const View& v, const Geom& g, uint32_t j, uint32_t 
   const uint8_t* kt = v.ks + (uint64_t)g.r * lo * W * C + (uint64_t)j * S + (uint64_t)(t0 - lo) * W * C;
   const uint32_t p0 = tid * kPix;
   const bool mine = p0 < npix;  // npix is a multiple of kPix
-  // keystream of this thread's pixels first: its latency hides behind the gather
+  // keystream of this thread's pixels first: its latency hides behind the
+  // gather.  With C = 3 the thread's 3*kPix bytes come in 16-byte loads (a
+  // dword load instruction at this lane stride touches 24 cache lines).
   uint4 b[kPix / 4];
+  if constexpr (C == 3) {
+    uint32_t kw[kPix * 3 / 4];
+    const uint8_t* kp = kt + (uint64_t)(mine ? p0 : 0u) * 3;
 #pragma unroll
-  for (uint32_t i = 0; i < kPix / 4; i++)
-    b[i] = mine ? load4_packed<C>(kt + (uint64_t)(p0 + 4 * i) * C) : make_uint4(0, 0, 0, 0);
+    for (uint32_t i = 0; i < kPix * 3 / 16; i++) {
+      const v4u32a4 w = gload4u(kp + 16 * i);
+      kw[4 * i] = w.x;
+      kw[4 * i + 1] = w.y;
+      kw[4 * i + 2] = w.z;
+      kw[4 * i + 3] = w.w;
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < kPix / 4; i++) {
+      const uint32_t k0 = kw[3 * i], k1 = kw[3 * i + 1], k2 = kw[3 * i + 2];
+      b[i] = mine ? make_uint4(k0 & 0xFFFFFFu, (k0 >> 24) | ((k1 & 0xFFFFu) << 8),
+                               (k1 >> 16) | ((k2 & 0xFFu) << 16), k2 >> 8)
+                  : make_uint4(0, 0, 0, 0);
+    }
+  } else {
+#pragma unroll
+    for (uint32_t i = 0; i < kPix / 4; i++)
+      b[i] = mine ? load4_packed<C>(kt + (uint64_t)(p0 + 4 * i) * C) : make_uint4(0, 0, 0, 0);
+  }
   gather_rows<C, kSrcPacked>(v, g, t0, R, tile);
   __syncthreads();
   constexpr uint32_t msk = pixel_mask<C>();
@@ -237,17 +259,40 @@ __device__ uint32_t enc_tile(const View& v, const Geom& g, uint32_t j, uint32_t 
     c = z >> 24;
     d[i] = z & msk;
   }
+  // Stores staged through the thread's own tile words (it alone read them),
+  // so that each store instruction of a wavefront writes 1 KB of
+  // consecutive bytes: packed (C = 3) a thread's 16 pixels are 12 words.
+  constexpr uint32_t OW = kDstPacked && C == 3 ? kPix * 3 / 4 : kPix;  // output words per thread
   if (mine) {
-    if constexpr (kDstPacked) {
-      uint8_t* o = v.dst + ((uint64_t)t0 * W + p0) * C;
 #pragma unroll
-      for (uint32_t i = 0; i < kPix / 4; i++)
-        store4_packed<C>(o + 4 * i * C, make_uint4(d[4 * i], d[4 * i + 1], d[4 * i + 2], d[4 * i + 3]));
-    } else {
-      uint8_t* o = v.dst + ((uint64_t)t0 * W + p0) * 4;
+    for (uint32_t i = 0; i < kPix / 4; i++) {
+      if constexpr (OW == kPix) {
+        reinterpret_cast<uint4*>(tile)[p0 / 4 + i] = make_uint4(d[4 * i], d[4 * i + 1], d[4 * i + 2], d[4 * i + 3]);
+      } else {
+        uint32_t* w = tile + p0 + 3 * i;
+        w[0] = (d[4 * i] & 0xFFFFFFu) | (d[4 * i + 1] << 24);
+        w[1] = ((d[4 * i + 1] >> 8) & 0xFFFFu) | (d[4 * i + 2] << 16);
+        w[2] = ((d[4 * i + 2] >> 16) & 0xFFu) | (d[4 * i + 3] << 8);
+      }
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  {
+    const uint32_t lane = tid & 63u, pw = (tid - lane) * kPix;  // the wavefront's first pixel
+    if (pw < npix) {
+      const uint32_t threads = min(64u, (npix - pw) / kPix);    // threads of the wavefront with pixels
+      const uint32_t chunks = threads * OW / 4;                 // 16-byte chunks (OW % 4 == 0)
+      uint8_t* o = v.dst + ((uint64_t)t0 * W + pw) * (kDstPacked ? C : 4);
 #pragma unroll
-      for (uint32_t i = 0; i < kPix / 4; i++)
-        gstore4(o + 16 * i, make_uint4(d[4 * i], d[4 * i + 1], d[4 * i + 2], d[4 * i + 3]));
+      for (uint32_t i = 0; i < OW / 4; i++) {
+        const uint32_t c = 64 * i + lane;  // chunk c: thread c / (OW/4), its words 4*(c % (OW/4))
+        if (c < chunks) {
+          const uint32_t th = c / (OW / 4), wd = 4 * (c % (OW / 4));
+          gstore4(o + 16 * c, *reinterpret_cast<const uint4*>(tile + pw + th * kPix + wd));
+        }
+      }
     }
   }
   return (carry ^ total) & 0xFFu;
