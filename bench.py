@@ -646,9 +646,11 @@ def main():
         round_kernel = "round_enc_pw_kernel"
     round_gbs = round_bytes / (round_launch_ms * 1e-3) / 1e9
     dominant_prbg = prof["prbg_ms"] >= prof["round_ms"]
+    prbg_kernel = PRBG_KERNEL[key.get_launch()["prbg_variant"]]
     roof_prbg = {"bound": "alu", "achieved": prbg_tflops, "peak": FP64_PEAK_TFLOPS,
-                 "unit": "TFLOP/s", "frac": prbg_tflops / FP64_PEAK_TFLOPS, "traffic": None,
-                 "kernel": PRBG_KERNEL[key.get_launch()["prbg_variant"]], "launch_ms": prbg_launch_ms,
+                 "unit": "TFLOP/s", "frac": prbg_tflops / FP64_PEAK_TFLOPS,
+                 "traffic": recorded_traffic(prbg_kernel) if batch == 48 else None,
+                 "kernel": prbg_kernel, "launch_ms": prbg_launch_ms,
                  "per_launch": f"{prof['prbg_steps'] // max(1, prof['prbg_launches'])} chain steps x "
                                f"{FLOPS_PER_STEP} FP64 ops",
                  "ns_per_step": prof["prbg_ms"] * 1e6 / max(1, prof["prbg_steps"] / N_SUB)}
