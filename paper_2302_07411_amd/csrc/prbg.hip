@@ -247,13 +247,13 @@ __device__ __forceinline__ void advance(Cursor& cu, uint32_t steps, uint32_t spf
 
 // Consumer lane q (of kLanes per chain) of chain c: steps [q*kSub, (q+1)*kSub)
 // of ring block `blk` become keystream bytes.
-template <uint32_t kLanes>
+template <uint32_t kLanes, uint32_t kB = kBlock>
 __device__ void emit_sub(const double2* ring, uint32_t c, uint32_t q, uint32_t blk,
                          const ChainPlan& cp, uint8_t* base, uint64_t stride, Cursor& cu,
                          double* state) {
-  constexpr uint32_t kSub = kBlock / kLanes;  // steps per consumer lane
+  constexpr uint32_t kSub = kB / kLanes;  // steps per consumer lane
   const uint32_t s0 = q * kSub;
-  const uint32_t g0 = blk * kBlock + s0;     // global step of the sub-block start
+  const uint32_t g0 = blk * kB + s0;     // global step of the sub-block start
   if (g0 < cp.total) {
     const uint32_t last = cp.total - 1;      // state after the launch's last step
     if (last >= g0 && last < g0 + kSub) {
@@ -296,7 +296,7 @@ __device__ void emit_sub(const double2* ring, uint32_t c, uint32_t q, uint32_t b
       }
     }
   }
-  advance(cu, kBlock, cp.spf);
+  advance(cu, kB, cp.spf);
 }
 
 template <int kMode>
@@ -411,15 +411,16 @@ __device__ __forceinline__ bool plcm_wrong_yg(double y, double g, double cur, do
 // Verifier segments: kNV-1 segments of kSegLong steps, then the rest of the
 // block.  With three verifiers the last, shorter one goes to the wavefront
 // that shares its SIMD with the emitter.
-template <uint32_t kNV>
+template <uint32_t kNV, uint32_t kB>
 struct SpecSegments {
-  static constexpr uint32_t kSegLong = kNV == 3 ? 12 : kBlock / kNV;
-  static constexpr uint32_t kSegLast = kBlock - (kNV - 1) * kSegLong;
+  static_assert(kB == 32 || kB == 64, "block of 32 or 64 steps");
+  static constexpr uint32_t kSegLong = kNV == 3 ? (kB == 32 ? 12 : 22) : kB / kNV;
+  static constexpr uint32_t kSegLast = kB - (kNV - 1) * kSegLong;
   static_assert(kSegLong % 2 == 0 && kSegLast % 2 == 0 && kSegLast <= kSegLong && kSegLast > 0,
                 "segments of whole step pairs");
   // index of the checkpoint holding the value after step s, or kNV if none
   static __device__ __forceinline__ uint32_t ckpt_after(uint32_t s) {
-    if (s == kBlock - 1) return kNV - 1;
+    if (s == kB - 1) return kNV - 1;
     return (s % kSegLong == kSegLong - 1) ? s / kSegLong : kNV;
   }
 };
@@ -447,12 +448,12 @@ __device__ __forceinline__ bool verify_segment(double start, double end, double*
   return bad;
 }
 
-template <bool kPlant, uint32_t kNV>
+template <bool kPlant, uint32_t kNV, uint32_t kB>
 __global__ __launch_bounds__((2 + kNV) * 64) void prbg_plcm_spec_kernel(
     const PlcmChain* __restrict__ chains, uint32_t n_chains, uint8_t* ks_base, uint32_t n_frames) {
-  using Seg = SpecSegments<kNV>;
+  using Seg = SpecSegments<kNV, kB>;
   constexpr uint32_t kWaves = 2 + kNV;
-  __shared__ double2 ring[3][(kBlock / 2) * 64];  // values of blocks b-2 (emit), b-1, b (repaired)
+  __shared__ double2 ring[3][(kB / 2) * 64];  // values of blocks b-2 (emit), b-1, b (repaired)
   __shared__ double ckpt[3][kNV][64];    // per block: the value after each segment
   __shared__ uint32_t fix_count[2];      // repairs so far, of even and of odd iterations
   __shared__ uint32_t simd_of[kWaves];   // the SIMD each wavefront runs on
@@ -465,7 +466,7 @@ __global__ __launch_bounds__((2 + kNV) * 64) void prbg_plcm_spec_kernel(
   if (has) ch = chains[c0 + c];
   const ChainPlan cp = plan(ch, n_frames);
   const uint32_t nblk =
-      __builtin_amdgcn_readfirstlane((wave_max(has ? cp.total : 0u) + kBlock - 1) / kBlock);
+      __builtin_amdgcn_readfirstlane((wave_max(has ? cp.total : 0u) + kB - 1) / kB);
   // per-lane map parameters, selected without indexing (which would put `ch` in scratch)
   const double p = m ? ch.p[1] : ch.p[0], h = m ? ch.h[1] : ch.h[0];
   const double ip = m ? ch.ip[1] : ch.ip[0], ih = m ? ch.ih[1] : ch.ih[0];
@@ -478,7 +479,7 @@ __global__ __launch_bounds__((2 + kNV) * 64) void prbg_plcm_spec_kernel(
   if (lane == 0) simd_of[wave] = (hwid >> 4) & 3u;
   uint8_t* base = ks_base + ch.out_off;
   Cursor cu{0, 0};  // emitter lane 2c+q writes steps [16q, 16q+16) of each block
-  advance(cu, (lane & 1u) * (kBlock / 2), cp.spf ? cp.spf : 1);
+  advance(cu, (lane & 1u) * (kB / 2), cp.spf ? cp.spf : 1);
   uint32_t seen0 = 0, seen1 = 0;  // fix_count values already acted on
   bool repaired = false;          // block b-1 was written by a repair (the same in every wavefront)
   __syncthreads();
@@ -510,17 +511,17 @@ __global__ __launch_bounds__((2 + kNV) * 64) void prbg_plcm_spec_kernel(
       if (b < nblk) {
         double* ck = &ckpt[b % 3][0][lane];
 #pragma unroll
-        for (uint32_t s = 0; s < kBlock; s++) {
+        for (uint32_t s = 0; s < kB; s++) {
           x = plcm_two(x, p, ip, lp, ih, lh);
           if constexpr (kPlant)  // testing: a one-bit error in some steps of every lane
-            if (planted(b * kBlock + s, lane, 29))
+            if (planted(b * kB + s, lane, 29))
               x = __longlong_as_double(__double_as_longlong(x) ^ 1);
           if (Seg::ckpt_after(s) < kNV) ck[Seg::ckpt_after(s) * 64] = x;
         }
       }
     } else if (role == 1) {
       if (b >= 2 && has)
-        emit_sub<2>(ring[(b - 2) % 3], c, lane & 1u, b - 2, cp, base, ch.frame_stride, cu,
+        emit_sub<2, kB>(ring[(b - 2) % 3], c, lane & 1u, b - 2, cp, base, ch.frame_stride, cu,
                     ch.state);
     } else if (b >= 1 && b - 1 < nblk && !repaired) {
       // block b-1, unless a repair already wrote it (then its values are exact)
@@ -530,9 +531,9 @@ __global__ __launch_bounds__((2 + kNV) * 64) void prbg_plcm_spec_kernel(
       const double end = ckpt[blk % 3][v][lane];  // the producer's checkpoint
       const bool bad =
           v < kNV - 1
-              ? verify_segment<Seg::kSegLong, kPlant>(start, end, rv, s0, blk * kBlock + s0, lane,
+              ? verify_segment<Seg::kSegLong, kPlant>(start, end, rv, s0, blk * kB + s0, lane,
                                                       p, h, ip, ih, lp, lh)
-              : verify_segment<Seg::kSegLast, kPlant>(start, end, rv, s0, blk * kBlock + s0, lane,
+              : verify_segment<Seg::kSegLast, kPlant>(start, end, rv, s0, blk * kB + s0, lane,
                                                       p, h, ip, ih, lp, lh);
       // any lane of a chain (lanes past a chain's end hold further orbit
       // values: a failure there costs a repair, never a wrong byte)
@@ -554,7 +555,7 @@ __global__ __launch_bounds__((2 + kNV) * 64) void prbg_plcm_spec_kernel(
         double y = ckpt[(blk + 2) % 3][kNV - 1][lane];
         for (uint32_t bb = blk; bb <= b && bb < nblk; bb++) {
           double* r = reinterpret_cast<double*>(ring[bb % 3]);
-          for (uint32_t s = 0; s < kBlock; s++) {
+          for (uint32_t s = 0; s < kB; s++) {
             y = plcm_fast(y, p, h, ip, ih);
             r[ring_index(s, lane)] = y;
             if (Seg::ckpt_after(s) < kNV) ckpt[bb % 3][Seg::ckpt_after(s)][lane] = y;
@@ -575,15 +576,27 @@ hipError_t launch_prbg_plcm(const PlcmChain* d_chains, uint32_t n_chains, uint8_
   if (n_chains == 0) return hipSuccess;
   switch (variant) {
     case PRBG_SPEC:
-      hipLaunchKernelGGL((prbg_plcm_spec_kernel<false, kSpecVerifiers>), dim3((n_chains + 31) / 32),
-                         dim3((2 + kSpecVerifiers) * 64), 0, s,
-                         d_chains, n_chains, ks_base, n_frames);
+    case PRBG_SPEC_PLANT: {
+      // Up to 64 workgroups (a compute unit each, also on a stream limited
+      // to a quarter of the chip): blocks of 64 steps halve the per-block
+      // barrier and repair check (103 KB of LDS).  More workgroups: blocks
+      // of 32 (54 KB), so that three share a compute unit.
+      const bool plant = variant == PRBG_SPEC_PLANT, few = (n_chains + 31) / 32 <= 64;
+      const dim3 grid((n_chains + 31) / 32), block((2 + kSpecVerifiers) * 64);
+      if (few && !plant)
+        hipLaunchKernelGGL((prbg_plcm_spec_kernel<false, kSpecVerifiers, 64>), grid, block, 0, s,
+                           d_chains, n_chains, ks_base, n_frames);
+      else if (few)
+        hipLaunchKernelGGL((prbg_plcm_spec_kernel<true, kSpecVerifiers, 64>), grid, block, 0, s,
+                           d_chains, n_chains, ks_base, n_frames);
+      else if (!plant)
+        hipLaunchKernelGGL((prbg_plcm_spec_kernel<false, kSpecVerifiers, 32>), grid, block, 0, s,
+                           d_chains, n_chains, ks_base, n_frames);
+      else
+        hipLaunchKernelGGL((prbg_plcm_spec_kernel<true, kSpecVerifiers, 32>), grid, block, 0, s,
+                           d_chains, n_chains, ks_base, n_frames);
       break;
-    case PRBG_SPEC_PLANT:
-      hipLaunchKernelGGL((prbg_plcm_spec_kernel<true, kSpecVerifiers>), dim3((n_chains + 31) / 32),
-                         dim3((2 + kSpecVerifiers) * 64), 0, s,
-                         d_chains, n_chains, ks_base, n_frames);
-      break;
+    }
     case PRBG_RECIP_PAIR:
       hipLaunchKernelGGL(prbg_plcm_kernel<kRecipPair>, dim3((n_chains + 15) / 16), dim3(128), 0, s,
                          d_chains, n_chains, ks_base, n_frames);
