@@ -238,6 +238,27 @@ def test_long_keystream(B, variant):
     assert np.array_equal(x[:, 0], ref.x1) and np.array_equal(x[:, 1], ref.x2)
 
 
+@pytest.mark.parametrize("variant", [4, 5])
+def test_many_workgroups_keystream(B, variant):
+    """2112 chains in 66 workgroups: past 64 workgroups the speculative
+    generator runs 32-step blocks (the configuration the serving loop
+    uses), below it 64-step blocks; both against the oracle, with and
+    without planted errors."""
+    H, W, C, n, r, T = 2112, 64, 1, 2112, 5, 4
+    pm = plcm_key(n, 4343)
+    print(f"[case] many workgroups H={H} W={W} n={n} T={T} variant={variant}", flush=True)
+    ref = oracle.PlcmKey(H, W, C, n, r, pm)
+    want = ref.keystream(T)
+    key = B.Key(H, W, C, n, r, pm)
+    key.set_launch(prbg_variant=variant)
+    ks = torch.empty(T * r * H * W * C, dtype=torch.uint8, device="cuda:0")
+    key.keystream(ks, T)
+    got = _host(ks, want.shape)
+    assert np.array_equal(got, want), f"{np.count_nonzero(got != want)} bytes differ"
+    x, _ = key.get_state()
+    assert np.array_equal(x[:, 0], ref.x1) and np.array_equal(x[:, 1], ref.x2)
+
+
 @pytest.mark.parametrize("name,H,W,C,n,r,T", [
     ("rgb480", 480, 480, 3, 8, 5, 3),
     ("rgb768", 768, 768, 3, 16, 5, 3),
