@@ -150,7 +150,9 @@ CRSIN_HD bool sin_quick(double t, const LdsTable* tab, double* hi, double* lo) {
     uh = t;
     ul = 0.0;
   } else {
-    const DD s = two_sum(kPiHi - t, kPiMid);  // kPiHi - t exact (Sterbenz)
+    // kPiHi - t is exact (Sterbenz) and a multiple of 2^-52, so it is 0 or
+    // above kPiMid (about 1.2e-16): the three-operation exact sum applies
+    const DD s = fast_two_sum(kPiHi - t, kPiMid);
     uh = s.hi;
     ul = s.lo + kPiLo;
   }
