@@ -49,7 +49,7 @@
 // of a rounding midpoint.  Such quotients exist but are extremely rare (none
 // in 2e8 orbit steps, none in 2e6 quotients constructed next to midpoints),
 // and correctness may not rest on rarity: the producer wavefront runs the
-// map with this quotient and keeps only two checkpoints per block; two
+// map with this quotient and keeps only a few checkpoints per block; three
 // verifier wavefronts recompute the block's steps from the checkpoints with
 // the same operations, check every step against its predecessor (the
 // remainder by one FMA and one Markstein correction must give the value
@@ -58,9 +58,8 @@
 // mismatch every wavefront takes a repair branch: the producer recomputes
 // the failed block and the one after it with the correctly rounded fast path
 // above.  The checks run on other SIMDs while the producer iterates, and the
-// producer writes to LDS only twice per block; the verifiers' recomputation
-// and checks, which take somewhat longer than the producer's block, set the
-// pace.
+// producer writes to LDS only three times per block, so the chain runs at
+// the producer's own issue rate: seven FP64 instructions per step.
 #include "cv_internal.h"
 
 namespace cv {
