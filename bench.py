@@ -405,6 +405,35 @@ def bench_quality(B, torch, np, args, src, dst, s_c, pm):
     return out
 
 
+def bench_decrypt(B, torch, src, s_c, pm, batch, reps=20):
+    """Decryption rounds of one batch of the video on the fused path (the
+    keystream generated beforehand, as for the rounds roofline), timed with
+    HIP events on the launch stream; the decrypted frames must equal the
+    plaintext byte for byte."""
+    key = B.Key(H, W, C, N_SUB, R, pm)
+    key.set_path(B.CV_PATH_FUSED)
+    key.set_launch(batch_frames=batch)
+    ks = torch.empty(batch * R * F, dtype=torch.uint8, device=src.device)
+    key.keystream(ks, batch)
+    enc, dec = torch.empty_like(src[:batch]), torch.empty_like(src[:batch])
+    key.apply_rounds(False, src[:batch], enc, ks, s_c[:batch])
+    key.apply_rounds(True, enc, dec, ks, s_c[:batch])  # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        key.apply_rounds(True, enc, dec, ks, s_c[:batch])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    exact = bool(torch.equal(dec, src[:batch]))
+    gbs = (2 + R) * F * batch / (ms * 1e-3) / 1e9
+    return {"workload": f"{batch} frames of the {H}x{W}x{C} video, {R} rounds, keystream precomputed",
+            "kernel": "rounds_fused_kernel (decryption)", "launch_ms": ms, "gb_per_s": gbs,
+            "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "frames_per_s": batch / (ms * 1e-3),
+            "round_trip_exact": exact}
+
+
 def decrypt_frame(B, torch, cipher_np, pm, s_c):
     k = B.Key(H, W, C, N_SUB, R, pm)
     c = torch.from_numpy(np_contig(cipher_np)).cuda()
@@ -539,6 +568,7 @@ def main():
     ap.add_argument("--no-served", action="store_true", help="skip the 256-stream served workload")
     ap.add_argument("--batched-ticks", type=int, default=20)
     ap.add_argument("--no-lasm", action="store_true", help="skip the 2DLASM stream")
+    ap.add_argument("--no-decrypt", action="store_true", help="skip the decryption rounds")
     ap.add_argument("--no-quality", action="store_true", help="skip the statistical measures")
     ap.add_argument("--no-sweeps", action="store_true", help="skip the r and n sweeps")
     ap.add_argument("--lasm-frames", type=int, default=13)
@@ -685,10 +715,14 @@ def main():
         "roofline_prbg": roof_prbg,
         "cpu_baseline": cpu,
     }
+    bad = cpu is not None and cpu["parity_mismatched_bytes"]
+    if not args.no_decrypt:
+        print("[bench] decryption rounds", file=sys.stderr, flush=True)
+        out["decrypt"] = bench_decrypt(B, torch, src, s_c, pm, batch)
+        bad = bad or not out["decrypt"]["round_trip_exact"]
     if args.cpu_all_frames > 0:
         print("[bench] oracle on all host cores", file=sys.stderr, flush=True)
         out["cpu_all_cores"] = cpu_all_cores(args.cpu_all_frames)
-    bad = cpu is not None and cpu["parity_mismatched_bytes"]
     if args.paper_cpu_frames > 0:
         print("[bench] the paper's multithreaded CPU design", file=sys.stderr, flush=True)
         out["cpu_paper_design"] = cpu_paper_design(src, dst, s_c, min(args.paper_cpu_frames, total), pm)
