@@ -238,13 +238,14 @@ def test_long_keystream(B, variant):
     assert np.array_equal(x[:, 0], ref.x1) and np.array_equal(x[:, 1], ref.x2)
 
 
+@pytest.mark.parametrize("n", [2048, 2049, 2112])
 @pytest.mark.parametrize("variant", [4, 5])
-def test_many_workgroups_keystream(B, variant):
-    """2112 chains in 66 workgroups: past 64 workgroups the speculative
-    generator runs 32-step blocks (the configuration the serving loop
-    uses), below it 64-step blocks; both against the oracle, with and
-    without planted errors."""
-    H, W, C, n, r, T = 2112, 64, 1, 2112, 5, 4
+def test_many_workgroups_keystream(B, variant, n):
+    """2048 chains fill 64 workgroups, the most that still run 64-step
+    blocks; 2049 and 2112 chains take 65 and 66 workgroups and 32-step
+    blocks (the configuration the serving loop uses). All against the
+    oracle, with and without planted errors."""
+    H, W, C, r, T = n, 64, 1, 5, 4
     pm = plcm_key(n, 4343)
     print(f"[case] many workgroups H={H} W={W} n={n} T={T} variant={variant}", flush=True)
     ref = oracle.PlcmKey(H, W, C, n, r, pm)
