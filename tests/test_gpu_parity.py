@@ -54,13 +54,18 @@ def _case(name, H, W, C, n, r, T, seed=0):
     return pm, frames, s_c
 
 
+@pytest.mark.parametrize("variant", [0, 5])
 @pytest.mark.parametrize("geom", GEOMS, ids=IDS)
-def test_keystream_parity(B, geom):
+def test_keystream_parity(B, geom, variant):
+    """Every geometry's keystream and final state against the oracle, with
+    the default generator and with planted errors (chains of one step to a
+    few blocks: repairs of a first, a last and a single block)."""
     name, H, W, C, n, r, T = geom
     pm, _, _ = _case(*geom)
     ref = oracle.PlcmKey(H, W, C, n, r, pm)
     want = ref.keystream(T)
     key = B.Key(H, W, C, n, r, pm)
+    key.set_launch(prbg_variant=variant)
     ks = torch.empty(T * r * H * W * C, dtype=torch.uint8, device="cuda:0")
     key.keystream(ks, T)
     got = _host(ks, want.shape)
