@@ -279,6 +279,21 @@ def bench_served(B, torch, np, args):
         ref = oracle.PlcmKey(h, w, c, n, R, pms[i])
         want = (ref.decrypt if dec else ref.encrypt)(src, seeds[i][:1])
         mism += int(np.count_nonzero(first[i].cpu().numpy().reshape(want.shape) != want))
+    oracle_s = time.perf_counter() - t_or
+    # admission by device-memory budget: further 3840x2160 streams until the
+    # server refuses one (after the measurement, so they do not disturb it)
+    n4k = next((sp[3] for sp in specs if sp[:2] == (2160, 3840)), 32)
+    extra, refused = 0, False
+    while extra < 256:
+        try:
+            srv.open(2160, 3840, 3, n4k, R, plcm_key(n4k, 9900 + extra))
+        except B.CvError as e:
+            if e.status != B.CV_E_AGAIN:
+                raise
+            refused = True
+            break
+        extra += 1
+    adm = srv.stats()
     srv.close()
     lat_np = np.asarray(lat)
     return {
@@ -299,7 +314,10 @@ def bench_served(B, torch, np, args):
         "decrypt_streams": sum(1 for s in specs if s[4]),
         "split_cus": bool(stats["split_cus"]), "ring_frames": args.serve_ring, "queue_frames": Q,
         "oracle_sample_streams": len(sample), "oracle_mismatched_bytes": mism,
-        "oracle_sample_s": time.perf_counter() - t_or,
+        "oracle_sample_s": oracle_s,
+        "admission": {"workload_streams_admitted": N, "extra_3840x2160_admitted": extra,
+                      "refused_next": refused, "hbm_budget_gb": adm["hbm_budget"] / 1e9,
+                      "hbm_used_gb": adm["hbm_used"] / 1e9},
     }
 
 
