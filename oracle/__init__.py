@@ -247,6 +247,24 @@ def undiffuse(Z: np.ndarray, n: int, r: int, j: int, ks: np.ndarray) -> np.ndarr
     return Y
 
 
+def rounds(H: int, W: int, C: int, n: int, r: int, decrypt: bool, ks: np.ndarray,
+           frames: np.ndarray, s_c) -> np.ndarray:
+    """The r rounds of T frames with a given keystream (T*r*F bytes, frame
+    after frame): Eq. (1) then Eq. (3) per round, or Eq. (4) then Eq. (2) in
+    reverse round order (Algorithm 2's round loop)."""
+    frames = np.ascontiguousarray(frames, np.uint8).reshape(-1, H, W, C)
+    T = frames.shape[0]
+    ks = np.ascontiguousarray(np.asarray(ks, np.uint8).reshape(-1))
+    assert ks.size == T * r * H * W * C
+    s_c = np.ascontiguousarray(np.asarray(s_c, np.uint32).reshape(-1))
+    assert s_c.size == T
+    out = np.zeros_like(frames)
+    if lib().oracle_rounds(H, W, C, n, r, int(decrypt), _u8(ks), _u8(frames), _u8(out),
+                           s_c.ctypes.data_as(ct.POINTER(ct.c_uint32)), T):
+        raise MemoryError("oracle allocation failed")
+    return out
+
+
 # ---------------------------------------------------------- stateful key ---
 
 class PlcmKey:
@@ -324,12 +342,7 @@ class LasmKey:
         T = frames.shape[0]
         s_c = np.ascontiguousarray(np.asarray(s_c, np.uint32).reshape(-1))
         assert s_c.size == T
-        ks = np.ascontiguousarray(self.keystream(T).reshape(-1))
-        out = np.zeros_like(frames)
-        if lib().oracle_rounds(H, W, C, n, r, int(decrypt), _u8(ks), _u8(frames), _u8(out),
-                               s_c.ctypes.data_as(ct.POINTER(ct.c_uint32)), T):
-            raise MemoryError("oracle allocation failed")
-        return out
+        return rounds(H, W, C, n, r, decrypt, self.keystream(T), frames, s_c)
 
     def encrypt(self, frames, s_c) -> np.ndarray:
         return self._rounds(False, frames, s_c)
