@@ -4,7 +4,11 @@
 
 Flags: -ffp-contract=off and no fast-math keep every binary64 operation of
 the chaotic maps a single correctly rounded IEEE operation (no FMA
-contraction); packed FP32 instructions are disabled.
+contraction).  `-Xclang -target-feature -Xclang -packed-fp32-ops` turns off
+the packed two-lane FP32 add/multiply/FMA instructions in the gfx950 device
+pass (tests/test_build_flags.py compiles a float2 kernel with these flags and
+checks that none is emitted, and that one is emitted without the flag); the
+host pass does not know the feature, warns and ignores it.
 """
 from __future__ import annotations
 
