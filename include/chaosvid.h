@@ -35,12 +35,25 @@
  *    12 bytes per step, ceil(r*S_i/12) steps per band and frame.
  *
  * Conventions.  All functions return cv_status; no C++ exception crosses the
- * ABI.  On error the key state is unchanged and cv_last_error() (thread
- * local) describes the failure.  Frame and keystream buffers are DEVICE
- * pointers owned by the caller; `stream` is a hipStream_t (NULL = the null
- * stream).  Calls that take a stream are asynchronous and stream-ordered.
- * A key is not thread-safe.  Errors reported by the HIP runtime surface as
- * CV_E_HIP, asynchronous ones on a later call.
+ * ABI.  On an error found when a call is made (arguments, allocation, a
+ * launch the runtime refuses) the key state is unchanged and cv_last_error()
+ * (thread local) describes the failure.  Frame and keystream buffers are
+ * DEVICE pointers owned by the caller; `stream` is a hipStream_t (NULL = the
+ * null stream).  Calls that take a stream are asynchronous and
+ * stream-ordered.  A key is not thread-safe.
+ *
+ * Asynchronous device errors.  A fused launch whose group barrier times out
+ * (or finds a group spread over XCDs) and a 2DLASM sine that cannot be
+ * rounded with certainty set the key's device error word; the call that
+ * enqueued that work has already returned CV_OK.  The error is reported, as
+ * CV_E_HIP, by the first later call on the key that finds the word's
+ * read-back complete (cv_key_sync, cv_key_get_state and cv_key_set_state
+ * always wait for it); calls made before that may also return CV_OK.  From
+ * the failing launch on, every output of the key is invalid, and after the
+ * report the key is dead: every call that uses it fails with CV_E_STATE.
+ * Free it and set up a new key (the generator state of a 2DLASM key that
+ * failed is itself invalid).  A caller that must know that a batch of frames
+ * is valid calls cv_key_sync after it.
  */
 #ifndef CHAOSVID_H
 #define CHAOSVID_H
@@ -205,6 +218,18 @@ cv_status cv_key_get_state(const cv_key *key, double *x, size_t n_doubles, uint6
  * Synchronises the key's device.  CV_E_INVAL as above or if any x is
  * outside [0,1]. */
 cv_status cv_key_set_state(cv_key *key, const double *x, size_t n_doubles, uint64_t frame_index);
+
+/* Wait for all work queued on the key's device and report the key's
+ * asynchronous device errors (see the conventions above): CV_OK if every
+ * frame the key has produced so far is valid, CV_E_HIP on the first report,
+ * CV_E_STATE afterwards. */
+cv_status cv_key_sync(cv_key *key);
+
+/* Testing hook: polls of the fused path's group barrier before it gives up
+ * and raises the key's device error (default 2^21, about two seconds).  With
+ * 0 and n >= 2 subframes the first workgroup to reach a barrier gives up, so
+ * every fused launch fails and every kernel still exits normally. */
+cv_status cv_key_set_spin_limit(cv_key *key, uint32_t polls);
 
 /* Choose the round implementation (CV_PATH_*).  CV_E_INVAL if unknown. */
 cv_status cv_key_set_path(cv_key *key, int path);

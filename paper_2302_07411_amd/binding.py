@@ -30,7 +30,8 @@ EXPORTS = (
     "cv_batch_get_info", "cv_batch_autotune", "cv_batch_set_profiling", "cv_batch_get_profile",
     "cv_server_create", "cv_server_tune", "cv_server_free", "cv_server_drain",
     "cv_server_get_stats", "cv_stream_open", "cv_stream_submit", "cv_stream_poll",
-    "cv_stream_close", "cv_cr_sin", "cv_key_schedule", "cv_sin_stage1",
+    "cv_stream_close", "cv_cr_sin", "cv_key_schedule", "cv_sin_stage1", "cv_key_sync",
+    "cv_key_set_spin_limit",
 )
 
 
@@ -111,6 +112,10 @@ def load() -> ct.CDLL:
     L.cv_key_get_state.argtypes = [vp, ct.POINTER(ct.c_double), sz, ct.POINTER(ct.c_uint64)]
     L.cv_key_set_state.restype = ct.c_int
     L.cv_key_set_state.argtypes = [vp, ct.POINTER(ct.c_double), sz, ct.c_uint64]
+    L.cv_key_sync.restype = ct.c_int
+    L.cv_key_sync.argtypes = [vp]
+    L.cv_key_set_spin_limit.restype = ct.c_int
+    L.cv_key_set_spin_limit.argtypes = [vp, ct.c_uint32]
     L.cv_key_set_path.restype = ct.c_int
     L.cv_key_set_path.argtypes = [vp, ct.c_int]
     for name in ("cv_encrypt_frames", "cv_decrypt_frames"):
@@ -288,6 +293,14 @@ class Key:
         x = np.ascontiguousarray(np.asarray(x, np.float64).reshape(-1))
         _check(load().cv_key_set_state(self._h, x.ctypes.data_as(ct.POINTER(ct.c_double)), x.size,
                                        frame_index))
+
+    def sync(self):
+        """cv_key_sync: wait for the key's work; raises CvError on a device error."""
+        _check(load().cv_key_sync(self._h))
+
+    def set_spin_limit(self, polls: int):
+        """Testing hook (cv_key_set_spin_limit)."""
+        _check(load().cv_key_set_spin_limit(self._h, polls))
 
     def set_path(self, path: int):
         _check(load().cv_key_set_path(self._h, path))

@@ -232,9 +232,16 @@ cv::RoundArgs round_args(const cv_key* k, const uint8_t* ks, uint32_t T) {
 // lands in `out` and no round reads the buffer it writes.
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
-// A fused launch that timed out at a group barrier left its flag set; report
-// it on the first call after the copy of the flag has completed.
+// A device-side error (a fused launch that timed out at a group barrier or
+// found a group spread over XCDs, a 2DLASM sine that could not be rounded)
+// leaves the key's error word set.  It is reported (CV_E_HIP) by the first
+// call that finds the word's read-back complete -- every call when `wait` --
+// and from then on the key is dead: every later call fails with CV_E_STATE.
+// The word itself is never cleared, so the kernels of a dead key that were
+// already queued give up at once instead of producing more output.
 cv_status check_async_errors(cv_key* k, bool wait) {
+  if (k->dead) return fail(CV_E_STATE, "the key is unusable after an earlier device error (" +
+                                           k->dead_msg + "); free it and set up a new key");
   if (!k->err_pending) return CV_OK;
   if (wait) {
     CV_HIP(hipEventSynchronize(k->err_copied));
@@ -244,14 +251,13 @@ cv_status check_async_errors(cv_key* k, bool wait) {
   }
   k->err_pending = false;
   if (*k->h_err) {
-    const uint32_t v = *k->h_err;
-    *k->h_err = 0;
-    if (v == 2)
-      return fail(CV_E_HIP,
-                  "a 2DLASM sine could not be rounded with certainty; the keystream is invalid");
-    return fail(CV_E_HIP,
-                "a fused launch timed out at a group barrier or found a group spread over "
-                "XCDs; its output is invalid");
+    k->dead = true;
+    k->dead_msg = *k->h_err == 2
+                      ? "a 2DLASM sine could not be rounded with certainty; the keystream and "
+                        "the generator state are invalid"
+                      : "a fused launch timed out at a group barrier or found a group spread "
+                        "over XCDs; its output is invalid";
+    return fail(CV_E_HIP, k->dead_msg);
   }
   return CV_OK;
 }
@@ -326,7 +332,7 @@ cv_status run_rounds_fused(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* 
   const bool skew = !decrypt && k->round_variant != 2 && k->fused_cap_skew > 0;
   const uint32_t cap = skew ? std::min(k->fused_groups, k->fused_cap_skew) : k->fused_groups;
   a.groups = std::min<uint32_t>(cap, ((T + 7) / 8) * 8);
-  a.spin_limit = 1u << 21;  // about two seconds of polling
+  a.spin_limit = k->spin_limit;
   a.decrypt = decrypt;
   Timed tm(k, st);
   if (skew) CV_HIP(cv::launch_rounds_skew(a, k->tile_skew, st));
@@ -682,6 +688,8 @@ cv_status cv_key_set_state(cv_key* k, const double* x, size_t n_doubles, uint64_
     if (!(x[i] >= 0.0 && x[i] <= 1.0)) return fail(CV_E_INVAL, "state outside [0,1]");
   DeviceGuard dg(k->device);
   CV_HIP(hipDeviceSynchronize());
+  cv_status s = check_async_errors(k, true);
+  if (s != CV_OK) return s;
   CV_HIP(hipMemcpy(k->d_state, x, n_doubles * sizeof(double), hipMemcpyHostToDevice));
   k->frame_index = frame_index;
   if (k->map == CV_MAP_PLCM) {
@@ -697,6 +705,19 @@ cv_status cv_key_set_path(cv_key* k, int path) {
   if (!k) return fail(CV_E_INVAL, "key is NULL");
   if (path != CV_PATH_PLAIN && path != CV_PATH_FUSED) return fail(CV_E_INVAL, "unknown path");
   k->path = path;
+  return CV_OK;
+}
+
+cv_status cv_key_sync(cv_key* k) {
+  if (!k) return fail(CV_E_INVAL, "key is NULL");
+  DeviceGuard dg(k->device);
+  CV_HIP(hipDeviceSynchronize());
+  return check_async_errors(k, true);
+}
+
+cv_status cv_key_set_spin_limit(cv_key* k, uint32_t polls) {
+  if (!k) return fail(CV_E_INVAL, "key is NULL");
+  k->spin_limit = polls;
   return CV_OK;
 }
 

@@ -37,6 +37,12 @@ struct cv_key {
   uint32_t* h_err = nullptr;
   hipEvent_t err_copied = nullptr;
   bool err_pending = false;
+  // After a device-side error has been reported the key is unusable: its
+  // outputs since the failing launch are invalid and, for a 2DLASM sine that
+  // could not be rounded, so is its generator state.
+  bool dead = false;
+  std::string dead_msg;
+  uint32_t spin_limit = 1u << 21;  // group-barrier polls before giving up (about two seconds)
   cv::PlcmChain* d_chains = nullptr;
   std::vector<cv::PlcmChain> h_chains;  // host copy (tables of multi-stream batches)
   cv::LasmChain* d_lchains = nullptr;   // 2DLASM keys: generators of the bands
