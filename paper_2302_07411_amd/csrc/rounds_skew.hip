@@ -150,9 +150,10 @@ __device__ uint32_t skew_tile(const View& v, const Geom& g, uint32_t j, uint32_t
   if (seed_at >= 0) carry = (src_pixel<C, kSrcPacked>(v, (uint64_t)seed_at) >> (8 * (C - 1))) & 0xFFu;
   skew_gather<C, kSrcPacked, kFull, kGatherBatch>(v, g, t0, R, lds);
   __syncthreads();
-  // wrap words: columns 0..2 of every row again after column W-1
-  if (threadIdx.x < 3 * R) {
-    const uint32_t k = threadIdx.x / 3, o = threadIdx.x % 3;
+  // wrap words: columns 0..2 of every row again after column W-1 (a tile
+  // of narrow rows can have more than kThreads/3 rows)
+  for (uint32_t x = threadIdx.x; x < 3 * R; x += kThreads) {
+    const uint32_t k = x / 3, o = x % 3;
     const uint32_t rb = rowbase(k, W, v.gm[t0 + k]);
     lds[rb + W + o] = lds[rb + o];
   }

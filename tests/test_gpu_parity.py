@@ -362,6 +362,11 @@ def test_round_variants(B, geom, variant, tile):
 FUSED_GEOMS = PW_GEOMS + [
     ("wide1920-full", 64, 1920, 3, 2, 5, 2),
     ("wide1920", 100, 1920, 3, 3, 5, 2),
+    # tall narrow bands: LDS tiles of more rows than a third of the
+    # workgroup's threads (each row has three wrap words), one tile per band
+    # (512 rows) and two tiles per band (1017 + 383 rows)
+    ("tall-narrow", 4096, 16, 3, 8, 5, 2),
+    ("tall-narrow-rgba", 2800, 32, 4, 2, 3, 2),
 ]
 
 
