@@ -297,6 +297,35 @@ cv_status cv_keystream_frames(cv_key *key, uint8_t *ks, size_t n_frames, void *s
 cv_status cv_apply_rounds(cv_key *key, int decrypt, const uint8_t *in, uint8_t *out,
                           const uint8_t *ks, const uint32_t *s_c, size_t n_frames, void *stream);
 
+/* Size of the static device scratch of cv_apply_rounds_noalloc (per device). */
+#define CV_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* cv_apply_rounds for callers that cannot allocate device memory (code that
+ * must not call hipMalloc, such as a tight serving loop or a harness that
+ * forbids it): the same arguments, rounds and bytes, but every buffer the
+ * kernels need beyond the caller's frames and keystream -- shift tables,
+ * exchange frames and barrier counters of the fused kernels, the byte
+ * kernels' ping-pong frames, the error word -- lives in one static device
+ * array of CV_NOALLOC_SCRATCH_BYTES that each device the library runs on
+ * holds until the process ends.  The call allocates nothing (no hipMalloc,
+ * hipHostMalloc or event), whatever the key's workspace holds; it runs the
+ * fused kernels when the pixel-word conditions hold (see CV_PATH_FUSED),
+ * else the byte kernels, in chunks of frames that fit the scratch.
+ * Synchronous: it returns when its frames are done (the shift tables go up
+ * from a static host array, a copy the runtime performs synchronously).
+ * Calls are serialised within the process; calls that overlap on one GPU
+ * from different copies of the library would race on its scratch.
+ * Errors: as cv_apply_rounds; CV_E_INVAL if even one frame does not fit the
+ * scratch (fused kernels: two pixel-word frames of 4*H*W bytes plus one
+ * shift table of 4*H bytes; byte kernels: one frame plus its shift table;
+ * H at most 262144), with a message naming the limit; CV_E_HIP if a group
+ * barrier timed out, in which case this call's output frames are invalid
+ * (the error word is cleared at the start of every call, and the key is not
+ * affected). */
+cv_status cv_apply_rounds_noalloc(cv_key *key, int decrypt, const uint8_t *in, uint8_t *out,
+                                  const uint8_t *ks, const uint32_t *s_c, size_t n_frames,
+                                  void *stream);
+
 /* ------------------------------------------------------------------------
  * Many streams per tick.  A batch object runs one tick of several video
  * streams -- each with its own key, resolution and number of subframes --

@@ -31,7 +31,7 @@ EXPORTS = (
     "cv_server_create", "cv_server_tune", "cv_server_free", "cv_server_drain",
     "cv_server_get_stats", "cv_stream_open", "cv_stream_submit", "cv_stream_poll",
     "cv_stream_close", "cv_cr_sin", "cv_key_schedule", "cv_sin_stage1", "cv_key_sync",
-    "cv_key_set_spin_limit",
+    "cv_key_set_spin_limit", "cv_apply_rounds_noalloc",
 )
 
 
@@ -134,6 +134,9 @@ def load() -> ct.CDLL:
     L.cv_keystream_frames.argtypes = [vp, u8p, sz, vp]
     L.cv_apply_rounds.restype = ct.c_int
     L.cv_apply_rounds.argtypes = [vp, ct.c_int, u8p, u8p, u8p, ct.POINTER(ct.c_uint32), sz, vp]
+    L.cv_apply_rounds_noalloc.restype = ct.c_int
+    L.cv_apply_rounds_noalloc.argtypes = [vp, ct.c_int, u8p, u8p, u8p, ct.POINTER(ct.c_uint32), sz,
+                                          vp]
     L.cv_batch_create.restype = ct.c_int
     L.cv_batch_create.argtypes = [ct.c_int, ct.POINTER(vp)]
     L.cv_batch_free.restype = None
@@ -277,6 +280,17 @@ class Key:
         arr, p = _seeds(s_c, n)
         _check(load().cv_apply_rounds(self._h, int(bool(decrypt)), _ptr(src), _ptr(dst), _ptr(ks),
                                       p, n, _stream(stream)))
+
+    def apply_rounds_noalloc(self, decrypt: bool, src, dst, ks, s_c, stream=None):
+        """cv_apply_rounds_noalloc: as apply_rounds, with the library's static
+        device scratch instead of allocated workspace (synchronous)."""
+        n = self._nframes(src)
+        r = self.geom[4]
+        if ks.numel() != n * r * self.frame_bytes or dst.numel() != src.numel():
+            raise ValueError("buffer sizes do not match")
+        arr, p = _seeds(s_c, n)
+        _check(load().cv_apply_rounds_noalloc(self._h, int(bool(decrypt)), _ptr(src), _ptr(dst),
+                                              _ptr(ks), p, n, _stream(stream)))
 
     def get_state(self):
         """(state, frame_index): state is (n, 2) {x_1, x_2} for PLCM, (n, 4)

@@ -90,7 +90,7 @@ struct Timed {
   hipStream_t st;
   hipEvent_t a = nullptr;
   Timed(cv_key* key, hipStream_t s) : k(key), st(s) {
-    if (k->profiling && (a = pooled_event(k)) != nullptr) (void)hipEventRecord(a, st);
+    if (k && k->profiling && (a = pooled_event(k)) != nullptr) (void)hipEventRecord(a, st);
   }
   void end(int kind, uint64_t work) {
     if (!a) return;
@@ -313,30 +313,48 @@ cv_status ensure_fused(cv_key* k) {
   return ensure_err_flag(k);
 }
 
-cv_status run_rounds_fused(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
-                           const uint8_t* ks, uint32_t T, hipStream_t st) {
-  cv_status s = ensure_fused(k);
-  if (s != CV_OK) return s;
+// Encryption by whole source-row runs unless the pixel-word kernels are asked for.
+bool fused_uses_skew(const cv_key* k, bool decrypt) {
+  return !decrypt && k->round_variant != 2 && k->fused_cap_skew > 0;
+}
+
+uint32_t fused_group_cap(const cv_key* k, bool decrypt) {
+  return fused_uses_skew(k, decrypt) ? std::min(k->fused_groups, k->fused_cap_skew) : k->fused_groups;
+}
+
+// One fused launch over T frames with the workspace given explicitly: shift
+// tables `gm`, two pixel-word frames per group in `fscratch`, 128 bytes per
+// group in `counters`, the error word `err`; at most `groups` groups.
+cv_status launch_fused_ws(const cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
+                          const uint8_t* ks, uint32_t T, const uint32_t* gm, uint8_t* fscratch,
+                          uint32_t* counters, uint32_t* err, uint32_t groups, hipStream_t st) {
   cv::RoundsFusedArgs a{};
   a.in = in;
   a.out = out;
   a.ks = ks;
-  a.gm = k->d_gm;
-  a.scratch = k->d_fscratch;
-  a.counters = k->d_counters;
-  a.err = k->d_err;
+  a.gm = gm;
+  a.scratch = fscratch;
+  a.counters = counters;
+  a.err = err;
   a.g = k->g;
   a.tile_rows = k->tile_pw;
   a.n_frames = T;
-  // encryption by whole source-row runs unless the pixel-word kernels are asked for
-  const bool skew = !decrypt && k->round_variant != 2 && k->fused_cap_skew > 0;
-  const uint32_t cap = skew ? std::min(k->fused_groups, k->fused_cap_skew) : k->fused_groups;
-  a.groups = std::min<uint32_t>(cap, ((T + 7) / 8) * 8);
+  a.groups = std::min<uint32_t>(std::min(groups, fused_group_cap(k, decrypt)), ((T + 7) / 8) * 8);
   a.spin_limit = k->spin_limit;
   a.decrypt = decrypt;
-  Timed tm(k, st);
-  if (skew) CV_HIP(cv::launch_rounds_skew(a, k->tile_skew, st));
+  if (fused_uses_skew(k, decrypt)) CV_HIP(cv::launch_rounds_skew(a, k->tile_skew, st));
   else CV_HIP(cv::launch_rounds_fused(a, k->threads, st));
+  return CV_OK;
+}
+
+cv_status run_rounds_fused(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
+                           const uint8_t* ks, uint32_t T, hipStream_t st) {
+  cv_status s = ensure_fused(k);
+  if (s != CV_OK) return s;
+  Timed tm(k, st);
+  if ((s = launch_fused_ws(k, decrypt, in, out, ks, T, k->d_gm, k->d_fscratch, k->d_counters,
+                           k->d_err, k->fused_groups, st)) != CV_OK)
+    return s;
   tm.end(1, (uint64_t)T * k->g.r);
   return queue_err_readback(k, st);
 }
@@ -391,14 +409,23 @@ cv_status run_rounds(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out, c
       return run_rounds_fused(k, decrypt, in, out, ks, T, st);
     return run_rounds_pw(k, decrypt, in, out, ks, T, st);
   }
+  return run_rounds_bytes_ws(k, decrypt, in, out, ks, T, k->d_gm, k->d_scratch, st, true);
+}
+
+// The byte kernels (any geometry): r launches over T frames, alternating
+// between `out` and `scratch` (T frames) so that the last round lands in `out`.
+cv_status run_rounds_bytes_ws(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
+                              const uint8_t* ks, uint32_t T, const uint32_t* gm, uint8_t* scratch,
+                              hipStream_t st, bool timed) {
   const uint32_t r = k->g.r;
   cv::RoundArgs a = round_args(k, ks, T);
+  a.gm = gm;
   const uint8_t* cur = in;
   for (uint32_t s = 0; s < r; s++) {
-    uint8_t* target = ((r - 1 - s) % 2 == 0) ? out : k->d_scratch;
+    uint8_t* target = ((r - 1 - s) % 2 == 0) ? out : scratch;
     a.src = cur;
     a.dst = target;
-    Timed tm(k, st);
+    Timed tm(timed ? k : nullptr, st);
     if (!decrypt) {
       a.j = s;
       a.tile_rows = k->tile_enc;

@@ -132,6 +132,20 @@ cv_status ensure_workspace(cv_key* k, size_t frames);
 cv_status upload_shift_tables(cv_key* k, const uint32_t* s_c, size_t T, hipStream_t st);
 cv_status run_rounds(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out, const uint8_t* ks,
                      uint32_t T, hipStream_t st);
+// Pixel-word kernels apply to this key and these buffers.
+bool use_pw(const cv_key* k, const uint8_t* in, const uint8_t* out, const uint8_t* ks);
+// Groups a fused launch of this key and direction may use (resident capacity).
+uint32_t fused_group_cap(const cv_key* k, bool decrypt);
+// One fused launch over T frames on an explicit workspace (shift tables,
+// exchange frames of `groups` groups, barrier counters, error word).
+cv_status launch_fused_ws(const cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
+                          const uint8_t* ks, uint32_t T, const uint32_t* gm, uint8_t* fscratch,
+                          uint32_t* counters, uint32_t* err, uint32_t groups, hipStream_t st);
+// The byte round kernels over T frames on an explicit workspace (shift
+// tables, one T-frame scratch buffer); `timed` records profiling events.
+cv_status run_rounds_bytes_ws(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
+                              const uint8_t* ks, uint32_t T, const uint32_t* gm, uint8_t* scratch,
+                              hipStream_t st, bool timed);
 
 // Work of one multi-stream tick.  Keystream locations are byte offsets from
 // the tick's keystream base.
