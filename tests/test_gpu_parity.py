@@ -217,6 +217,37 @@ def test_exact_division_path_and_tiny_keys(B):
         assert np.array_equal(_host(ks, ref.shape), ref)
 
 
+@pytest.mark.parametrize("variant", [0, 2, 3, 4, 5])
+def test_fast_division_domain_edge(B, variant):
+    """Keys at the edge of the reciprocal division's domain (p >= 2^-64,
+    states 0 or >= 2^-800), which the key set-up accepts for the fast
+    generators: the smallest p (2^-64, so nearly every step takes the second
+    piece with numerators x - p down to ulp(p) = 2^-116), the largest p
+    (1/2 - ulp, so 1/2 - p = 2^-54), the smallest initial state (2^-800,
+    growing by at least 2 per step through the first piece), and the largest
+    (1 - 2^-53, which folds to 2^-53).  Keystream and final state against the
+    oracle for every fast variant, planted errors included."""
+    H, W, C, n, r, T = 64, 32, 3, 4, 5, 3
+    pm = plcm_key(n, 91)
+    pm[0, 1] = 2.0 ** -64
+    pm[1, 3] = np.nextafter(0.5, 0.0)
+    pm[2, 0] = 2.0 ** -800
+    pm[3, 2] = np.nextafter(1.0, 0.0)
+    for x0, p in ((pm[:, 0], pm[:, 1]), (pm[:, 2], pm[:, 3])):
+        assert np.all(p >= 2.0 ** -64) and np.all(x0 >= 2.0 ** -800)
+    print(f"[case] fast-division domain edge variant={variant}", flush=True)
+    ref = oracle.PlcmKey(H, W, C, n, r, pm)
+    want = ref.keystream(T)
+    key = B.Key(H, W, C, n, r, pm)
+    key.set_launch(prbg_variant=variant)
+    ks = torch.empty(T * r * H * W * C, dtype=torch.uint8, device="cuda:0")
+    key.keystream(ks, T)
+    got = _host(ks, want.shape)
+    assert np.array_equal(got, want), f"{np.count_nonzero(got != want)} keystream bytes differ"
+    x, _ = key.get_state()
+    assert np.array_equal(x[:, 0], ref.x1) and np.array_equal(x[:, 1], ref.x2)
+
+
 @pytest.mark.parametrize("variant", [2, 3, 4, 5])
 def test_long_keystream(B, variant):
     """About 26 million chain steps (52 million divisions) against the
