@@ -131,6 +131,12 @@ typedef struct {
   uint32_t tile_rows_pw;   /* frame rows per LDS tile of the pixel-word kernels */
   uint32_t fused_groups;   /* CV_PATH_FUSED: frame groups in flight (multiple of 8); 0 = as
                               many as can be resident (reading back gives the value used) */
+  uint32_t use_graph;      /* 1: cv_encrypt_frames / cv_decrypt_frames replay one HIP graph
+                              per internal batch (shift-table copy, keystream launch, round
+                              launches, error read-back), captured the first time a buffer
+                              set (in, out, frame count, direction) is seen; up to 16 graphs
+                              are kept, the least recently used dropped.  0: every kernel
+                              launched on its own.  Ignored while profiling is on. */
 } cv_launch;
 
 /* Version of the cipher readings above (CV_SPEC_VERSION). */
@@ -231,6 +237,10 @@ cv_status cv_key_sync(cv_key *key);
  * every fused launch fails and every kernel still exits normally. */
 cv_status cv_key_set_spin_limit(cv_key *key, uint32_t polls);
 
+/* Graphs captured and replayed by the key's calls since its set-up
+ * (cv_launch.use_graph).  Errors: CV_E_INVAL (NULL). */
+cv_status cv_key_graph_counts(const cv_key *key, uint64_t *captures, uint64_t *replays);
+
 /* Choose the round implementation (CV_PATH_*).  CV_E_INVAL if unknown. */
 cv_status cv_key_set_path(cv_key *key, int path);
 
@@ -238,7 +248,8 @@ cv_status cv_key_set_path(cv_key *key, int path);
  * the device's LDS size). */
 cv_status cv_key_get_launch(const cv_key *key, cv_launch *launch);
 
-/* Set the launch shape.  CV_E_INVAL if batch_frames = 0, threads is not a
+/* Set the launch shape (drops the key's captured graphs).  CV_E_INVAL if
+ * batch_frames = 0, use_graph > 1, threads is not a
  * multiple of 64 in 64..1024, a tile is 0 rows, larger than threads, or
  * needs more LDS than one workgroup may have.  Tile rows beyond a band's
  * height (encryption) or the frame height (decryption) are clamped. */

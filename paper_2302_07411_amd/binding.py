@@ -31,7 +31,7 @@ EXPORTS = (
     "cv_server_create", "cv_server_tune", "cv_server_free", "cv_server_drain",
     "cv_server_get_stats", "cv_stream_open", "cv_stream_submit", "cv_stream_poll",
     "cv_stream_close", "cv_cr_sin", "cv_key_schedule", "cv_sin_stage1", "cv_key_sync",
-    "cv_key_set_spin_limit", "cv_apply_rounds_noalloc",
+    "cv_key_set_spin_limit", "cv_apply_rounds_noalloc", "cv_key_graph_counts",
 )
 
 
@@ -44,7 +44,8 @@ class CvLaunch(ct.Structure):
     _fields_ = [("batch_frames", ct.c_uint32), ("threads", ct.c_uint32),
                 ("tile_rows_enc", ct.c_uint32), ("tile_rows_dec", ct.c_uint32),
                 ("prbg_variant", ct.c_uint32), ("round_variant", ct.c_uint32),
-                ("tile_rows_pw", ct.c_uint32), ("fused_groups", ct.c_uint32)]
+                ("tile_rows_pw", ct.c_uint32), ("fused_groups", ct.c_uint32),
+                ("use_graph", ct.c_uint32)]
 
 
 class CvProfile(ct.Structure):
@@ -118,6 +119,8 @@ def load() -> ct.CDLL:
     L.cv_key_set_spin_limit.argtypes = [vp, ct.c_uint32]
     L.cv_key_set_path.restype = ct.c_int
     L.cv_key_set_path.argtypes = [vp, ct.c_int]
+    L.cv_key_graph_counts.restype = ct.c_int
+    L.cv_key_graph_counts.argtypes = [vp, ct.POINTER(ct.c_uint64), ct.POINTER(ct.c_uint64)]
     for name in ("cv_encrypt_frames", "cv_decrypt_frames"):
         f = getattr(L, name)
         f.restype = ct.c_int
@@ -315,6 +318,12 @@ class Key:
     def set_spin_limit(self, polls: int):
         """Testing hook (cv_key_set_spin_limit)."""
         _check(load().cv_key_set_spin_limit(self._h, polls))
+
+    def graph_counts(self):
+        """(captures, replays) of the key's graphs (cv_launch.use_graph)."""
+        c, r = ct.c_uint64(), ct.c_uint64()
+        _check(load().cv_key_graph_counts(self._h, ct.byref(c), ct.byref(r)))
+        return c.value, r.value
 
     def set_path(self, path: int):
         _check(load().cv_key_set_path(self._h, path))

@@ -166,7 +166,18 @@ bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
   return x < y + nb && y < x + na;
 }
 
+// Executable graphs reference the key's workspace and launch shape: drop
+// them whenever either changes (waits for the device first, since a graph
+// may still be running).
+void drop_graphs(cv_key* k) {
+  if (k->graphs.empty()) return;
+  (void)hipDeviceSynchronize();
+  for (auto& g : k->graphs) (void)hipGraphExecDestroy(g.exec);
+  k->graphs.clear();
+}
+
 void free_workspace(cv_key* k) {
+  drop_graphs(k);
   if (k->d_ks) (void)hipFree(k->d_ks);
   if (k->d_scratch) (void)hipFree(k->d_scratch);
   if (k->d_scratch2) (void)hipFree(k->d_scratch2);
@@ -295,6 +306,10 @@ cv_status ensure_err_flag(cv_key* k) {
 // the next call on the key reports it.
 cv_status queue_err_readback(cv_key* k, hipStream_t st) {
   CV_HIP(hipMemcpyAsync(k->h_err, k->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  if (k->capturing) {  // the event is recorded after each replay instead
+    k->captured_err = true;
+    return CV_OK;
+  }
   CV_HIP(hipEventRecord(k->err_copied, st));
   k->err_pending = true;
   return CV_OK;
@@ -453,6 +468,79 @@ cv_status check_frames_args(const cv_key* k, const uint8_t* in, uint8_t* out, co
   return CV_OK;
 }
 
+// One batch of T frames through a graph of its work (cv_launch.use_graph):
+// the shift tables are written to the pinned staging buffer the graph copies
+// from, then the graph captured for this buffer set is replayed (captured on
+// the key's private stream the first time).  Everything else a capture
+// records -- workspace, launch shape, chain descriptors -- is fixed until
+// drop_graphs; what varies from call to call is in the signature.
+cv_status crypt_batch_graph(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
+                            const uint32_t* s_c, uint32_t T, hipStream_t st) {
+  const Geom& g = k->g;
+  if (k->gm_pending) {
+    CV_HIP(hipEventSynchronize(k->gm_done));
+    k->gm_pending = false;
+  }
+  for (uint32_t t = 0; t < T; t++) shift_table(g.H, g.W, s_c[t], k->h_gm + (uint64_t)t * g.H);
+  const uint64_t sig[8] = {(uint64_t)decrypt, (uint64_t)(uintptr_t)in, (uint64_t)(uintptr_t)out, T,
+                           (uint64_t)k->path, (uint64_t)prbg_variant(k), k->spin_limit, 0};
+  cv_key::GraphEntry* e = nullptr;
+  for (auto& x : k->graphs)
+    if (memcmp(x.sig, sig, sizeof(sig)) == 0) e = &x;
+  if (e) {
+    k->graph_replays++;
+  } else {
+    if (!k->cap) CV_HIP(hipStreamCreateWithFlags(&k->cap, hipStreamNonBlocking));
+    // the fused workspace (allocations are not allowed inside a capture)
+    if (use_pw(k, in, out, k->d_ks) && k->path == CV_PATH_FUSED && k->fused_groups > 0) {
+      cv_status s = ensure_fused(k);
+      if (s != CV_OK) return s;
+    }
+    if (k->graphs.size() >= cv_key::kMaxGraphs) {
+      size_t lru = 0;
+      for (size_t i = 1; i < k->graphs.size(); i++)
+        if (k->graphs[i].last_use < k->graphs[lru].last_use) lru = i;
+      CV_HIP(hipDeviceSynchronize());  // it may still be running
+      (void)hipGraphExecDestroy(k->graphs[lru].exec);
+      k->graphs.erase(k->graphs.begin() + lru);
+    }
+    CV_HIP(hipStreamBeginCapture(k->cap, hipStreamCaptureModeThreadLocal));
+    k->capturing = true;
+    k->captured_err = false;
+    cv_status s = CV_OK;
+    const hipError_t ce = hipMemcpyAsync(k->d_gm, k->h_gm, (uint64_t)T * g.H * sizeof(uint32_t),
+                                         hipMemcpyHostToDevice, k->cap);
+    if (ce != hipSuccess) s = hip_fail(ce, "hipMemcpyAsync (shift tables)");
+    if (s == CV_OK) s = launch_keystream(k, k->d_ks, T, k->cap);
+    if (s == CV_OK) s = run_rounds(k, decrypt, in, out, k->d_ks, T, k->cap);
+    k->capturing = false;
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(k->cap, &graph);
+    if (s != CV_OK || ee != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s != CV_OK ? s : hip_fail(ee, "hipStreamEndCapture");
+    }
+    cv_key::GraphEntry ne{};
+    memcpy(ne.sig, sig, sizeof(sig));
+    ne.reads_err = k->captured_err;
+    const hipError_t ie = hipGraphInstantiate(&ne.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate");
+    k->graphs.push_back(ne);
+    e = &k->graphs.back();
+    k->graph_captures++;
+  }
+  e->last_use = ++k->graph_clock;
+  CV_HIP(hipGraphLaunch(e->exec, st));
+  CV_HIP(hipEventRecord(k->gm_done, st));
+  k->gm_pending = true;
+  if (e->reads_err) {
+    CV_HIP(hipEventRecord(k->err_copied, st));
+    k->err_pending = true;
+  }
+  return CV_OK;
+}
+
 cv_status crypt_frames(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
                        const uint32_t* s_c, size_t n, void* stream) {
   cv_status s = check_frames_args(k, in, out, s_c, n);
@@ -462,12 +550,19 @@ cv_status crypt_frames(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
   hipStream_t st = (hipStream_t)stream;
   const size_t B = std::min<size_t>(n, k->batch_frames);
   if ((s = ensure_workspace(k, B)) != CV_OK) return s;
+  const bool graph = k->use_graph && !k->profiling;
   for (size_t f0 = 0; f0 < n; f0 += B) {
     const uint32_t T = (uint32_t)std::min(B, n - f0);
-    if ((s = upload_shift_tables(k, s_c + f0, T, st)) != CV_OK) return s;
-    if ((s = launch_keystream(k, k->d_ks, T, st)) != CV_OK) return s;
-    if ((s = run_rounds(k, decrypt, in + f0 * k->F, out + f0 * k->F, k->d_ks, T, st)) != CV_OK)
-      return s;
+    if (graph) {
+      if ((s = crypt_batch_graph(k, decrypt, in + f0 * k->F, out + f0 * k->F, s_c + f0, T, st)) !=
+          CV_OK)
+        return s;
+    } else {
+      if ((s = upload_shift_tables(k, s_c + f0, T, st)) != CV_OK) return s;
+      if ((s = launch_keystream(k, k->d_ks, T, st)) != CV_OK) return s;
+      if ((s = run_rounds(k, decrypt, in + f0 * k->F, out + f0 * k->F, k->d_ks, T, st)) != CV_OK)
+        return s;
+    }
     k->frame_index += T;
   }
   return CV_OK;
@@ -682,6 +777,7 @@ void cv_key_free(cv_key* k) {
   (void)drain_spans(k);
   for (hipEvent_t e : k->event_pool) (void)hipEventDestroy(e);
   free_workspace(k);
+  if (k->cap) (void)hipStreamDestroy(k->cap);
   if (k->d_fscratch) (void)hipFree(k->d_fscratch);
   if (k->d_counters) (void)hipFree(k->d_counters);
   if (k->d_err) (void)hipFree(k->d_err);
@@ -758,6 +854,14 @@ cv_status cv_key_get_launch(const cv_key* k, cv_launch* l) {
   l->round_variant = k->round_variant;
   l->tile_rows_pw = k->tile_pw;
   l->fused_groups = k->fused_groups;
+  l->use_graph = k->use_graph ? 1u : 0u;
+  return CV_OK;
+}
+
+cv_status cv_key_graph_counts(const cv_key* k, uint64_t* captures, uint64_t* replays) {
+  if (!k || !captures || !replays) return fail(CV_E_INVAL, "NULL argument");
+  *captures = k->graph_captures;
+  *replays = k->graph_replays;
   return CV_OK;
 }
 
@@ -766,6 +870,7 @@ cv_status cv_key_set_launch(cv_key* k, const cv_launch* l) {
   if (l->batch_frames == 0) return fail(CV_E_INVAL, "batch_frames must be >= 1");
   if (l->prbg_variant > 5) return fail(CV_E_INVAL, "prbg_variant must be 0..5");
   if (l->round_variant > 3) return fail(CV_E_INVAL, "round_variant must be 0..3");
+  if (l->use_graph > 1) return fail(CV_E_INVAL, "use_graph must be 0 or 1");
   const uint32_t tp = pw_tile_limit(k->g, l->threads, l->tile_rows_pw);
   if (tp == 0 && (k->g.C == 3 || k->g.C == 4))
     return fail(CV_E_INVAL, "tile_rows_pw must be >= 1 (and the frame not too wide for threads)");
@@ -786,6 +891,8 @@ cv_status cv_key_set_launch(cv_key* k, const cv_launch* l) {
   k->prbg_variant = l->prbg_variant;
   k->round_variant = l->round_variant;
   k->tile_pw = tp;
+  k->use_graph = l->use_graph != 0;
+  drop_graphs(k);
   // the fused workspace depends on the shape: drop it and size it anew
   if (k->d_fscratch) {
     CV_HIP(hipDeviceSynchronize());

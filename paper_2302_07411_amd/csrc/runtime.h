@@ -61,6 +61,21 @@ struct cv_key {
   uint32_t tile_enc = 0, tile_dec = 0;
   uint32_t max_band_rows = 0;
   size_t lds_max = 0;
+  // graph replay of each batch's work (cv_launch.use_graph): one executable
+  // graph per buffer set, least recently used dropped beyond kMaxGraphs
+  bool use_graph = false;
+  bool capturing = false;      // enqueueing into a capture: no events, no host state
+  bool captured_err = false;   // the capture holds the error word's read-back
+  hipStream_t cap = nullptr;   // private stream graphs are captured on
+  struct GraphEntry {
+    uint64_t sig[8];
+    hipGraphExec_t exec;
+    uint64_t last_use;
+    bool reads_err;
+  };
+  static constexpr size_t kMaxGraphs = 16;
+  std::vector<GraphEntry> graphs;
+  uint64_t graph_clock = 0, graph_captures = 0, graph_replays = 0;
   // event profiling
   bool profiling = false;
   struct Span {
