@@ -282,6 +282,8 @@ void set_fused_groups(cv_key* k, uint32_t want) {
     k->fused_cap = cv::rounds_fused_resident_groups(g, k->tile_pw, k->threads, k->device);
   k->tile_skew = cv::rounds_skew_tile_rows(g, k->lds_max);
   k->fused_cap_skew = cv::rounds_skew_resident_groups(g, k->tile_skew, k->device);
+  k->fused_cap_unskew = cv::rounds_unskew_applies(g, k->lds_max)
+                            ? cv::rounds_unskew_resident_groups(g, k->device) : 0;
   const uint32_t w = want / 8 * 8;
   k->fused_groups = (w == 0 || w > k->fused_cap) ? k->fused_cap : w;
 }
@@ -328,13 +330,23 @@ cv_status ensure_fused(cv_key* k) {
   return ensure_err_flag(k);
 }
 
-// Encryption by whole source-row runs unless the pixel-word kernels are asked for.
-bool fused_uses_skew(const cv_key* k, bool decrypt) {
-  return !decrypt && k->round_variant != 2 && k->fused_cap_skew > 0;
+// Fused kernel of a direction: the row-run kernels (encryption: any
+// geometry with the pixel-word conditions; decryption: every band one LDS
+// tile) unless the pixel-word kernels are asked for.
+enum FusedKernel { FUSED_PW = 0, FUSED_SKEW = 1, FUSED_UNSKEW = 2 };
+
+FusedKernel fused_kernel(const cv_key* k, bool decrypt) {
+  if (k->round_variant == 2) return FUSED_PW;
+  if (!decrypt) return k->fused_cap_skew > 0 ? FUSED_SKEW : FUSED_PW;
+  return k->fused_cap_unskew > 0 ? FUSED_UNSKEW : FUSED_PW;
 }
 
 uint32_t fused_group_cap(const cv_key* k, bool decrypt) {
-  return fused_uses_skew(k, decrypt) ? std::min(k->fused_groups, k->fused_cap_skew) : k->fused_groups;
+  switch (fused_kernel(k, decrypt)) {
+    case FUSED_SKEW: return std::min(k->fused_groups, k->fused_cap_skew);
+    case FUSED_UNSKEW: return std::min(k->fused_groups, k->fused_cap_unskew);
+    default: return k->fused_groups;
+  }
 }
 
 // One fused launch over T frames with the workspace given explicitly: shift
@@ -357,8 +369,11 @@ cv_status launch_fused_ws(const cv_key* k, bool decrypt, const uint8_t* in, uint
   a.groups = std::min<uint32_t>(std::min(groups, fused_group_cap(k, decrypt)), ((T + 7) / 8) * 8);
   a.spin_limit = k->spin_limit;
   a.decrypt = decrypt;
-  if (fused_uses_skew(k, decrypt)) CV_HIP(cv::launch_rounds_skew(a, k->tile_skew, st));
-  else CV_HIP(cv::launch_rounds_fused(a, k->threads, st));
+  switch (fused_kernel(k, decrypt)) {
+    case FUSED_SKEW: CV_HIP(cv::launch_rounds_skew(a, k->tile_skew, st)); break;
+    case FUSED_UNSKEW: CV_HIP(cv::launch_rounds_unskew(a, st)); break;
+    default: CV_HIP(cv::launch_rounds_fused(a, k->threads, st));
+  }
   return CV_OK;
 }
 

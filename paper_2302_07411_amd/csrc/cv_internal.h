@@ -145,6 +145,14 @@ uint32_t rounds_skew_tile_rows(const Geom& g, size_t lds_max);  // 0: not applic
 uint32_t rounds_skew_resident_groups(const Geom& g, uint32_t tile_rows, int device);
 hipError_t launch_rounds_skew(const RoundsFusedArgs& a, uint32_t tile_rows, hipStream_t s);
 
+// All r decryption rounds of a batch of frames by whole source-row runs
+// (rounds_unskew.hip): the same arguments as launch_rounds_fused (decrypt
+// must be true), for geometries where every band fits the LDS as one tile.
+bool rounds_unskew_applies(const Geom& g, size_t lds_max);
+size_t rounds_unskew_lds_bytes(const Geom& g);
+uint32_t rounds_unskew_resident_groups(const Geom& g, int device);
+hipError_t launch_rounds_unskew(const RoundsFusedArgs& a, hipStream_t s);
+
 // ------------------------------------------------------------- batch ----
 // One (stream, frame) of a multi-stream tick.
 struct BatchJob {

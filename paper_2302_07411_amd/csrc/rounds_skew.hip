@@ -113,21 +113,6 @@ __device__ __forceinline__ void skew_gather(const View& v, const Geom& g, uint32
   }
 }
 
-// Byte order <-> pixel words for 4 pixels (C = 3): 3 packed words hold the
-// 12 bytes of 4 pixel words.
-__device__ __forceinline__ void pack4(const uint32_t* w, uint32_t* P) {
-  P[0] = __builtin_amdgcn_perm(w[1], w[0], 0x04020100u);
-  P[1] = __builtin_amdgcn_perm(w[2], w[1], 0x05040201u);
-  P[2] = __builtin_amdgcn_perm(w[3], w[2], 0x06050402u);
-}
-
-__device__ __forceinline__ void unpack4(const uint32_t* P, uint32_t* w) {
-  w[0] = __builtin_amdgcn_perm(P[1], P[0], 0x0C020100u);
-  w[1] = __builtin_amdgcn_perm(P[1], P[0], 0x0C050403u);
-  w[2] = __builtin_amdgcn_perm(P[2], P[1], 0x0C040302u);
-  w[3] = __builtin_amdgcn_perm(P[2], P[2], 0x0C030201u);
-}
-
 // One tile of one round: gather, diffusion seeded with `carry`, store.
 // Returns the carry into the next tile of the band.
 // `seed_at` >= 0: the tile starts the band, and its carry is the diffusion

@@ -31,6 +31,7 @@ struct cv_key {
   uint32_t fused_cap = 0;      // resident capacity for the current launch shape
   uint32_t tile_skew = 0;      // rows per LDS tile of the row-run encryption kernel (0 = n/a)
   uint32_t fused_cap_skew = 0; // its resident capacity in groups
+  uint32_t fused_cap_unskew = 0;  // resident groups of the row-run decryption kernel (0 = n/a)
   uint8_t* d_fscratch = nullptr;
   uint32_t* d_counters = nullptr;
   uint32_t* d_err = nullptr;

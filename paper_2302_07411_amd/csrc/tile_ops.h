@@ -92,6 +92,21 @@ __device__ __forceinline__ void store4_packed(uint8_t* p, uint4 v) {
   }
 }
 
+// Byte order <-> pixel words for 4 pixels (C = 3): 3 packed words hold the
+// 12 bytes of 4 pixel words.
+__device__ __forceinline__ void pack4(const uint32_t* w, uint32_t* P) {
+  P[0] = __builtin_amdgcn_perm(w[1], w[0], 0x04020100u);
+  P[1] = __builtin_amdgcn_perm(w[2], w[1], 0x05040201u);
+  P[2] = __builtin_amdgcn_perm(w[3], w[2], 0x06050402u);
+}
+
+__device__ __forceinline__ void unpack4(const uint32_t* P, uint32_t* w) {
+  w[0] = __builtin_amdgcn_perm(P[1], P[0], 0x0C020100u);
+  w[1] = __builtin_amdgcn_perm(P[1], P[0], 0x0C050403u);
+  w[2] = __builtin_amdgcn_perm(P[2], P[1], 0x0C040302u);
+  w[3] = __builtin_amdgcn_perm(P[2], P[2], 0x0C030201u);
+}
+
 // Exclusive XOR scan over the block in thread order; the XOR of all inputs
 // comes back in `total`.
 __device__ uint32_t block_xor_scan_excl(uint32_t v, uint32_t* sh, uint32_t& total) {
@@ -427,16 +442,26 @@ __device__ __forceinline__ void check_group_xcc(uint32_t* slot, uint32_t* err) {
   }
 }
 
-__device__ __forceinline__ bool group_barrier(uint32_t* ctr, uint32_t target, uint32_t spin_limit,
-                                              uint32_t* err) {
-  __shared__ uint32_t ok_sh;
-  // release: this wavefront's global stores have reached the XCD's L2
+// Group barrier in two halves, so that work independent of the other
+// members (loads of the next round's keystream) can be issued in between.
+// Arrive: this wavefront's global stores have reached the XCD's L2
+// (release), then one atomic increment per workgroup.
+__device__ __forceinline__ void group_arrive(uint32_t* ctr) {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __builtin_amdgcn_s_waitcnt(0);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until the counter reaches `target` (bounded: gives up after
+// spin_limit polls or when another member raised `err`, raising it too),
+// then acquire: invalidate the CU's L1 before any wavefront of the workgroup
+// reads what the other members wrote.  False if the barrier failed.
+__device__ __forceinline__ bool group_wait(uint32_t* ctr, uint32_t target, uint32_t spin_limit,
+                                           uint32_t* err) {
+  __shared__ uint32_t ok_sh;
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint32_t spins = 0, ok = 1;
     while ((int32_t)(__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
       if (++spins > spin_limit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
@@ -447,13 +472,17 @@ __device__ __forceinline__ bool group_barrier(uint32_t* ctr, uint32_t target, ui
       __builtin_amdgcn_s_sleep(1);
     }
     if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
-    // acquire: invalidate the CU's L1 (and clean L2 lines) before any
-    // wavefront of the workgroup reads what the other members wrote
     asm volatile("buffer_inv sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
     ok_sh = ok;
   }
   __syncthreads();
   return ok_sh != 0;
+}
+
+__device__ __forceinline__ bool group_barrier(uint32_t* ctr, uint32_t target, uint32_t spin_limit,
+                                              uint32_t* err) {
+  group_arrive(ctr);
+  return group_wait(ctr, target, spin_limit, err);
 }
 
 }  // namespace tile
