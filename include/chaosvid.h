@@ -370,7 +370,11 @@ typedef struct {
 
 /* Launch shape of the batched rounds kernel; any shape gives the same bytes. */
 typedef struct {
-  uint32_t threads;     /* threads per workgroup: 256..1024, multiple of 64 */
+  uint32_t threads;     /* threads per workgroup: 256..1024, multiple of 64.  With 1024, a
+                           channel count's jobs run on the row-run kernel (encryption by
+                           whole source-row runs, decryption in one pass per tile) when
+                           every one of them has W a multiple of 12 and its tiles fit the
+                           LDS; otherwise, and with fewer threads, on the pixel-word kernel */
   uint32_t group_wgs;   /* G, workgroups per frame job: 1..64 */
   uint32_t max_groups;  /* frame jobs in flight at once; 0 = as many as can be resident */
   uint32_t use_graph;   /* 1: capture a tick in a HIP graph and replay it while the tick's

@@ -12,7 +12,13 @@
 // must share C (3 or 4); every frame width is a multiple of 16 and every
 // buffer 16-byte aligned (the host sends other streams down the per-key
 // path).
-#include "tile_ops.h"
+//
+// Two kernels: the pixel-word one (any workgroup size), and the row-run one
+// (1024 threads, frame widths a multiple of 12): encryption by whole
+// source-row runs with packed-byte diffusion, decryption in one pass per
+// tile reading the round input, its predecessors and keystream as
+// contiguous runs (skew_ops.h).
+#include "skew_ops.h"
 
 namespace cv {
 namespace {
@@ -82,6 +88,118 @@ __global__ __launch_bounds__(kMaxThreads) void batch_rounds_kernel(BatchArgs A) 
   }
 }
 
+// One encryption tile of the row-run kernel with the variant's flags.
+template <uint32_t C, bool kFull>
+__device__ __forceinline__ uint32_t enc_rows_tile(bool first, bool last, const View& v,
+                                                  const Geom& g, uint32_t j, uint32_t lo,
+                                                  uint32_t hi, uint32_t t0, uint32_t R,
+                                                  uint32_t carry, int64_t sa, uint32_t* lds,
+                                                  uint32_t* wsum) {
+  using skew::skew_tile;
+  if (first && last) return skew_tile<C, 12, true, true, kFull>(v, g, j, lo, hi, t0, R, carry, sa, lds, wsum);
+  if (first) return skew_tile<C, 12, true, false, kFull>(v, g, j, lo, hi, t0, R, carry, sa, lds, wsum);
+  if (last) return skew_tile<C, 12, false, true, kFull>(v, g, j, lo, hi, t0, R, carry, sa, lds, wsum);
+  return skew_tile<C, 12, false, false, kFull>(v, g, j, lo, hi, t0, R, carry, sa, lds, wsum);
+}
+
+// Rows [t0, t0+R) of the tile (row pitch W+4) to the round output: packed
+// bytes (last round) or pixel words, 4 pixels per lane.
+template <uint32_t C>
+__device__ __forceinline__ void store_rows(const uint32_t* tile, uint32_t W, uint32_t t0,
+                                           uint32_t R, uint8_t* dst, bool packed) {
+  const uint32_t pitch = W + 4;
+  for (uint32_t q = threadIdx.x; q < R * W / 4; q += blockDim.x) {
+    const uint32_t k = (4 * q) / W, c = 4 * q - k * W;
+    const uint4 y = *reinterpret_cast<const uint4*>(tile + k * pitch + c);
+    if (!packed) {
+      gstore4(dst + 4ull * ((uint64_t)t0 * W + 4 * q), y);
+    } else if constexpr (C == 4) {
+      gstore4(dst + 4ull * ((uint64_t)t0 * W + 4 * q), y);
+    } else {
+      const uint32_t w4[4] = {y.x, y.y, y.z, y.w};
+      uint32_t P[3];
+      pack4(w4, P);
+      gu32* o = (gu32*)(dst + 3ull * ((uint64_t)t0 * W + 4 * q));
+      o[0] = P[0];
+      o[1] = P[1];
+      o[2] = P[2];
+    }
+  }
+}
+
+template <uint32_t C>
+__global__ __launch_bounds__(skew::kThreads) void batch_rows_kernel(BatchArgs A) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  __shared__ uint32_t wsum[skew::kWaves];
+  const uint32_t i = blockIdx.x, xcd = i % 8, idx = i / 8;
+  const uint32_t group = xcd + 8 * (idx / A.G), w = idx % A.G;
+  if (group >= A.groups) return;
+  uint32_t* ctr = A.counters + 32 * group;
+  check_group_xcc(ctr + 1, A.err);
+  uint8_t* buf[2] = {A.scratch + (uint64_t)group * 2 * A.scratch_stride,
+                     A.scratch + (uint64_t)group * 2 * A.scratch_stride + A.scratch_stride};
+  uint32_t nbar = 0;
+  for (uint32_t q = A.group_off[group]; q < A.group_off[group + 1]; q++) {
+    const BatchJob J = A.jobs[A.group_jobs[q]];
+    const Geom g = J.g;
+    const uint64_t pwf = (uint64_t)g.H * g.W * 4;
+    const bool full = g.W % g.H == 0;
+    View v;
+    v.ks = J.ks;
+    v.gm = J.gm;
+    uint32_t* gsh = lds + J.tile_dec * (g.W + 4);  // decryption: shift table, bands, seeds
+    uint32_t* blo = gsh + g.H;
+    uint32_t* seed = blo + g.n + 1;
+    if (J.decrypt) {
+      __syncthreads();  // the previous job's last reads of the LDS are done
+      for (uint32_t a = threadIdx.x; a < g.H; a += blockDim.x) gsh[a] = J.gm[a];
+      __syncthreads();
+    }
+    for (uint32_t s = 0; s < g.r; s++) {
+      const bool first = s == 0, last = s + 1 == g.r;
+      v.src = first ? J.in : buf[(s + 1) & 1];
+      v.src_last = first ? J.in_last : buf[(s + 1) & 1] + pwf - 4;
+      v.dst = last ? J.out : buf[s & 1];
+      if (!J.decrypt) {
+        for (uint32_t band = w; band < g.n; band += A.G) {
+          const uint32_t lo = (uint32_t)band_lo(g.H, g.n, band), hi = (uint32_t)band_lo(g.H, g.n, band + 1);
+          const int64_t seed_at = (int64_t)enc_seed_index(v, g, band);
+          uint32_t carry = 0;
+          for (uint32_t t0 = lo; t0 < hi; t0 += J.tile_enc) {
+            const uint32_t R = min(J.tile_enc, hi - t0);
+            const int64_t sa = t0 == lo ? seed_at : -1;
+            carry = full ? enc_rows_tile<C, true>(first, last, v, g, s, lo, hi, t0, R, carry, sa, lds, wsum)
+                         : enc_rows_tile<C, false>(first, last, v, g, s, lo, hi, t0, R, carry, sa, lds, wsum);
+            __syncthreads();  // the next tile's gather overwrites the LDS tile and wsum
+          }
+        }
+      } else {
+        const uint32_t j = g.r - 1 - s;
+        if (first) dec_seeds<C, true>(v, g, j, blo, seed);
+        else dec_seeds<C, false>(v, g, j, blo, seed);
+        for (uint32_t band = w; band < g.n; band += A.G) {
+          const uint32_t lo = blo[band], hi = blo[band + 1];
+          for (uint32_t t0 = lo; t0 < hi; t0 += J.tile_dec) {
+            const uint32_t R = min(J.tile_dec, hi - t0);
+            if (first) {
+              if (full) skew::unskew_rows<C, true, true>(v, g, j, t0, R, gsh, blo, seed, lds);
+              else skew::unskew_rows<C, true, false>(v, g, j, t0, R, gsh, blo, seed, lds);
+            } else {
+              if (full) skew::unskew_rows<C, false, true>(v, g, j, t0, R, gsh, blo, seed, lds);
+              else skew::unskew_rows<C, false, false>(v, g, j, t0, R, gsh, blo, seed, lds);
+            }
+            __syncthreads();
+            store_rows<C>(lds, g.W, t0, R, v.dst, last);
+            __syncthreads();  // the next tile's pass overwrites the tile
+          }
+        }
+      }
+      nbar++;
+      if (!group_barrier(ctr, nbar * A.G, A.spin_limit, A.err)) return;
+    }
+  }
+}
+
 __global__ void reset_batch_groups(uint32_t* p, uint32_t groups) {
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < groups; k += gridDim.x * blockDim.x) {
     p[32 * k] = 0;
@@ -91,10 +209,21 @@ __global__ void reset_batch_groups(uint32_t* p, uint32_t groups) {
 
 }  // namespace
 
-hipError_t launch_batch_rounds(const BatchArgs& a, uint32_t C, uint32_t threads, size_t lds,
-                               hipStream_t s) {
+hipError_t launch_batch_rounds(const BatchArgs& a, uint32_t C, bool rows, uint32_t threads,
+                               size_t lds, hipStream_t s) {
   hipLaunchKernelGGL(reset_batch_groups, dim3(1), dim3(256), 0, s, a.counters, a.groups);
   const uint32_t slots = ((a.groups + 7) / 8) * 8 * a.G;
+  if (rows) {
+    const void* fn = C == 3 ? reinterpret_cast<const void*>(&batch_rows_kernel<3>)
+                            : reinterpret_cast<const void*>(&batch_rows_kernel<4>);
+    if (lds > 64 * 1024) {
+      const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    BatchArgs copy = a;
+    void* args[] = {&copy};
+    return hipLaunchKernel(fn, dim3(slots), dim3(skew::kThreads), args, lds, s);
+  }
   if (C == 3)
     hipLaunchKernelGGL(batch_rounds_kernel<3>, dim3(slots), dim3(threads), lds, s, a);
   else
@@ -102,16 +231,42 @@ hipError_t launch_batch_rounds(const BatchArgs& a, uint32_t C, uint32_t threads,
   return hipGetLastError();
 }
 
-uint32_t batch_resident_groups(uint32_t C, uint32_t G, uint32_t threads, size_t lds, int device) {
+uint32_t batch_resident_groups(uint32_t C, bool rows, uint32_t G, uint32_t threads, size_t lds,
+                               int device) {
   int per_cu = 0, cus = 0;
-  hipError_t e = C == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_rounds_kernel<3>,
-                                                                        threads, lds)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_rounds_kernel<4>,
-                                                                        threads, lds);
+  hipError_t e;
+  if (rows) {
+    const void* fn = C == 3 ? reinterpret_cast<const void*>(&batch_rows_kernel<3>)
+                            : reinterpret_cast<const void*>(&batch_rows_kernel<4>);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, skew::kThreads, lds);
+  } else {
+    e = C == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_rounds_kernel<3>, threads, lds)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_rounds_kernel<4>, threads, lds);
+  }
   if (e != hipSuccess || per_cu <= 0) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
   const uint32_t per_xcd = (uint32_t)per_cu * (uint32_t)cus / 8;
   return (per_xcd / G) * 8;
+}
+
+size_t batch_rows_lds_bytes(const Geom& g, bool decrypt, uint32_t tile_rows) {
+  if (!decrypt) return rounds_skew_lds_bytes(g, tile_rows);
+  return ((size_t)tile_rows * (g.W + 4) + g.H + 2 * (size_t)g.n + 2) * 4;
+}
+
+uint32_t batch_unskew_tile_rows(const Geom& g, size_t lds_max) {
+  if (!((g.C == 3 || g.C == 4) && g.W % 16 == 0)) return 0;
+  const size_t reserve = 1024;  // static LDS of the kernel and group-barrier words
+  const size_t fixed = ((size_t)g.H + 2 * (size_t)g.n + 2) * 4 + reserve;
+  if (lds_max <= fixed) return 0;
+  uint32_t rows = (uint32_t)((lds_max - fixed) / ((size_t)(g.W + 4) * 4));
+  uint32_t band_max = 0;
+  for (uint32_t i = 0; i < g.n; i++)
+    band_max = std::max<uint32_t>(band_max, (uint32_t)(band_lo(g.H, g.n, i + 1) - band_lo(g.H, g.n, i)));
+  rows = std::min(rows, band_max);
+  const uint32_t M = (g.W + g.H - 1) / g.H;
+  rows = std::min(rows, skew::kThreads / M);
+  return rows;
 }
 
 }  // namespace cv

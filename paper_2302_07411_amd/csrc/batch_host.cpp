@@ -45,6 +45,7 @@ struct Signature {
   size_t chain_off[cv::kPrbgVariants] = {};
   uint32_t groups[2] = {0, 0};  // C = 3, C = 4
   uint32_t G = 0, threads = 0;
+  bool rows[2] = {false, false};
   size_t lds[2] = {0, 0};
   size_t job_off[2] = {0, 0}, gj_off[2] = {0, 0}, go_off[2] = {0, 0};
   uint64_t scratch_stride = 0;
@@ -54,7 +55,8 @@ struct Signature {
               threads == o.threads && scratch_stride == o.scratch_stride;
     for (int v = 0; v < cv::kPrbgVariants; v++) eq = eq && n_chains[v] == o.n_chains[v] && chain_off[v] == o.chain_off[v];
     for (int c = 0; c < 2; c++)
-      eq = eq && groups[c] == o.groups[c] && lds[c] == o.lds[c] && job_off[c] == o.job_off[c] &&
+      eq = eq && groups[c] == o.groups[c] && rows[c] == o.rows[c] && lds[c] == o.lds[c] &&
+           job_off[c] == o.job_off[c] &&
            gj_off[c] == o.gj_off[c] && go_off[c] == o.go_off[c];
     return eq;
   }
@@ -117,6 +119,7 @@ struct Plan {
   std::vector<uint32_t> gm;              // shift tables of every frame job
   uint64_t scratch_stride = 0;
   uint32_t groups[2] = {0, 0};
+  bool rows[2] = {false, false};  // the row-run kernel (else the pixel-word one)
   size_t lds[2] = {0, 0};
   uint64_t steps = 0, frame_rounds = 0;
 };
@@ -195,13 +198,21 @@ cv_status plan_tick(const cv_batch* b, const std::vector<ChainJob>& cj,
   P.gm.resize(gm);
   gm = 0;
   std::vector<std::pair<uint64_t, uint32_t>> order[2];  // (cost, job) per C
+  // the row-run kernel takes a channel count's jobs when it takes every one
+  bool rows_ok[2] = {threads == 1024, threads == 1024};
+  size_t lds_pw[2] = {0, 0}, lds_rows[2] = {0, 0};
   for (const FrameJob& f : fj) {
     const Geom& g = f.k->g;
     shift_table(g.H, g.W, f.s_c, P.gm.data() + gm);
     const int ci = g.C == 4;
     const uint32_t tile = pw_tile_rows(g, threads, b->lds_max);
     if (tile == 0) return fail(CV_E_INVAL, "frame too wide for the batch's workgroup size");
-    P.lds[ci] = std::max(P.lds[ci], cv::round_pw_lds_bytes(g, tile));
+    lds_pw[ci] = std::max(lds_pw[ci], cv::round_pw_lds_bytes(g, tile));
+    const uint32_t te = cv::rounds_skew_tile_rows(g, b->lds_max);
+    const uint32_t td = cv::batch_unskew_tile_rows(g, b->lds_max);
+    rows_ok[ci] = rows_ok[ci] && g.W % 12 == 0 && te > 0 && td > 0;
+    if (rows_ok[ci])
+      lds_rows[ci] = std::max(lds_rows[ci], cv::batch_rows_lds_bytes(g, f.decrypt != 0, f.decrypt ? td : te));
     cv::BatchJob J{};
     J.in = f.in;
     J.out = f.out;
@@ -213,6 +224,8 @@ cv_status plan_tick(const cv_batch* b, const std::vector<ChainJob>& cj,
     J.g = g;
     J.decrypt = f.decrypt;
     J.tile_rows = tile;
+    J.tile_enc = te;
+    J.tile_dec = td;
     order[ci].push_back({job_cost(f.k, G), (uint32_t)P.jobs[ci].size()});
     P.jobs[ci].push_back(J);
     P.frame_rounds += g.r;
@@ -221,7 +234,9 @@ cv_status plan_tick(const cv_batch* b, const std::vector<ChainJob>& cj,
   // per channel count: longest job first onto the least loaded group
   for (int ci = 0; ci < 2; ci++) {
     if (P.jobs[ci].empty()) continue;
-    const uint32_t cap = cv::batch_resident_groups(3 + ci, G, threads, P.lds[ci], b->device);
+    P.rows[ci] = rows_ok[ci];
+    P.lds[ci] = rows_ok[ci] ? lds_rows[ci] : lds_pw[ci];
+    const uint32_t cap = cv::batch_resident_groups(3 + ci, P.rows[ci], G, threads, P.lds[ci], b->device);
     if (cap == 0) return fail(CV_E_INVAL, "batch launch shape does not fit on the device");
     uint32_t groups = std::min<uint64_t>(cap, P.jobs[ci].size());
     if (b->shape.max_groups) groups = std::min(groups, b->shape.max_groups);
@@ -354,6 +369,7 @@ Signature signature(const cv_batch* b, const Plan& P, const Layout& L, uint8_t* 
   }
   for (int c = 0; c < 2; c++) {
     s.groups[c] = P.groups[c];
+    s.rows[c] = P.rows[c];
     s.lds[c] = P.lds[c];
     s.job_off[c] = L.job_off[c];
     s.gj_off[c] = L.gj_off[c];
@@ -432,7 +448,7 @@ cv_status enqueue_tick(cv_batch* b, const Plan& P, const Layout& L, const Slot& 
     a.G = b->shape.group_wgs;
     a.groups = P.groups[c];
     a.spin_limit = kSpinLimit;
-    CV_HIP(cv::launch_batch_rounds(a, 3 + c, b->shape.threads, P.lds[c], st));
+    CV_HIP(cv::launch_batch_rounds(a, 3 + c, P.rows[c], b->shape.threads, P.lds[c], st));
   }
   if (ta) {
     hipEvent_t tb = pooled(b);

@@ -164,6 +164,8 @@ struct BatchJob {
   Geom g;
   uint32_t decrypt;
   uint32_t tile_rows;       // pixel-word tile rows for this geometry
+  uint32_t tile_enc;        // row-run kernel: encryption tile rows (rounds_skew_tile_rows)
+  uint32_t tile_dec;        // row-run kernel: decryption tile rows (batch_unskew_tile_rows)
 };
 
 struct BatchArgs {
@@ -177,9 +179,16 @@ struct BatchArgs {
   uint32_t G, groups, spin_limit;
 };
 
-hipError_t launch_batch_rounds(const BatchArgs& a, uint32_t C, uint32_t threads, size_t lds,
-                               hipStream_t s);
-uint32_t batch_resident_groups(uint32_t C, uint32_t G, uint32_t threads, size_t lds, int device);
+// rows = true: the row-run kernel (1024 threads; every job with W a multiple
+// of 12 and tile_enc, tile_dec > 0); false: the pixel-word kernel.
+hipError_t launch_batch_rounds(const BatchArgs& a, uint32_t C, bool rows, uint32_t threads,
+                               size_t lds, hipStream_t s);
+uint32_t batch_resident_groups(uint32_t C, bool rows, uint32_t G, uint32_t threads, size_t lds,
+                               int device);
+// Row-run batch kernel: decryption tile rows for geometry g (0 = does not
+// fit) and the LDS a job needs in either direction.
+uint32_t batch_unskew_tile_rows(const Geom& g, size_t lds_max);
+size_t batch_rows_lds_bytes(const Geom& g, bool decrypt, uint32_t tile_rows);
 
 // LDS bytes a round kernel needs for a tile of `tile_rows` rows.
 size_t round_lds_bytes(const Geom& g, uint32_t tile_rows);
