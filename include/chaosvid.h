@@ -239,6 +239,20 @@ cv_status cv_key_sync(cv_key *key);
  * every fused launch fails and every kernel still exits normally. */
 cv_status cv_key_set_spin_limit(cv_key *key, uint32_t polls);
 
+/* Choose the key's fused-path launch shape for batches of n_frames frames
+ * in one direction: time the fused round kernels (the pixel-word and the
+ * row-run ones; frame groups in flight from 8 up to the resident capacity)
+ * on scratch frames with a scratch keystream, and set the fastest with
+ * cv_key_set_launch (the key's path becomes CV_PATH_FUSED; its generator
+ * state does not change).  With CV_TUNE_CACHE naming a file, the winner is
+ * stored there under the key's geometry, direction and n_frames, and a later
+ * call for the same class takes it from the file without timing (*cached =
+ * 1).  `best` (may be NULL) receives the launch shape.  Errors: CV_E_INVAL
+ * (NULL key, n_frames = 0, geometry without the pixel-word conditions),
+ * CV_E_NOMEM, CV_E_HIP. */
+cv_status cv_key_autotune(cv_key *key, int decrypt, uint32_t n_frames, void *stream,
+                          cv_launch *best, int *cached);
+
 /* Graphs captured and replayed by the key's calls since its set-up
  * (cv_launch.use_graph).  Errors: CV_E_INVAL (NULL). */
 cv_status cv_key_graph_counts(const cv_key *key, uint64_t *captures, uint64_t *replays);
@@ -373,13 +387,15 @@ typedef struct {
   uint32_t threads;     /* threads per workgroup: 256..1024, multiple of 64.  With 1024, a
                            channel count's jobs run on the row-run kernel (encryption by
                            whole source-row runs, decryption in one pass per tile) when
-                           every one of them has W a multiple of 12 and its tiles fit the
-                           LDS; otherwise, and with fewer threads, on the pixel-word kernel */
+                           every one of them has tiles that fit the LDS; otherwise, and
+                           with fewer threads, on the pixel-word kernel */
   uint32_t group_wgs;   /* G, workgroups per frame job: 1..64 */
   uint32_t max_groups;  /* frame jobs in flight at once; 0 = as many as can be resident */
   uint32_t use_graph;   /* 1: capture a tick in a HIP graph and replay it while the tick's
                            structure (items' geometries, frame counts and launch sizes) is
                            unchanged; 0: launch kernel by kernel */
+  uint32_t tile_rows_max; /* frame rows per LDS tile at most (the LDS tiling); 0 = as many
+                           as fit */
 } cv_batch_shape;
 
 /* Counters of a batch object (host-side, no synchronisation). */
@@ -391,6 +407,8 @@ typedef struct {
   uint32_t last_groups;         /* groups in flight in the last tick's rounds launches */
   uint32_t last_chains;         /* band generators of the last tick's keystream launches */
   uint32_t last_fallback_items; /* items of the last tick that ran on their key's own path */
+  uint32_t tune_cache_hits;     /* cv_batch_autotune calls answered from CV_TUNE_CACHE */
+  uint32_t tune_shapes_timed;   /* launch shapes the autotuner timed */
 } cv_batch_info;
 
 /* Create a batch object on HIP device `device` (the keys of its items must
@@ -424,10 +442,17 @@ cv_status cv_batch_sync(cv_batch *batch);
 cv_status cv_batch_get_info(const cv_batch *batch, cv_batch_info *info);
 
 /* Time the rounds kernel of the tick `items` describes for candidate shapes
- * (threads 512 and 1024; G from 2 to 32) and keep the fastest.  Keys are not
- * advanced and no keystream is generated: the out buffers of the items
- * receive meaningless bytes.  `best` (may be NULL) receives the chosen shape.
- * Same argument errors as cv_batch_run. */
+ * and keep the fastest: the kernel (threads 512: pixel-word; 1024: row-run
+ * where it applies), the band-to-workgroup mapping G in {4, 8, 16, 32}, the
+ * groups in flight (all resident, or half), and the LDS tiling (the largest
+ * tiles that fit, or half as many rows).  With the environment variable
+ * CV_TUNE_CACHE naming a file, the winner is stored there under the tick's
+ * shape class (its items' geometries, directions and frame counts) and a
+ * later call for the same class takes it from the file without timing
+ * (cv_batch_info.tune_cache_hits).  Keys are not advanced and no keystream
+ * is generated: the out buffers of the items receive meaningless bytes.
+ * `best` (may be NULL) receives the chosen shape.  Same argument errors as
+ * cv_batch_run. */
 cv_status cv_batch_autotune(cv_batch *batch, const cv_batch_item *items, size_t n_items,
                             void *stream, cv_batch_shape *best);
 

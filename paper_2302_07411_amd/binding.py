@@ -32,6 +32,7 @@ EXPORTS = (
     "cv_server_get_stats", "cv_stream_open", "cv_stream_submit", "cv_stream_poll",
     "cv_stream_close", "cv_cr_sin", "cv_key_schedule", "cv_sin_stage1", "cv_key_sync",
     "cv_key_set_spin_limit", "cv_apply_rounds_noalloc", "cv_key_graph_counts",
+    "cv_key_autotune",
 )
 
 
@@ -62,14 +63,16 @@ class CvBatchItem(ct.Structure):
 
 class CvBatchShape(ct.Structure):
     _fields_ = [("threads", ct.c_uint32), ("group_wgs", ct.c_uint32),
-                ("max_groups", ct.c_uint32), ("use_graph", ct.c_uint32)]
+                ("max_groups", ct.c_uint32), ("use_graph", ct.c_uint32),
+                ("tile_rows_max", ct.c_uint32)]
 
 
 class CvBatchInfo(ct.Structure):
     _fields_ = [("ticks", ct.c_uint64), ("graph_captures", ct.c_uint64),
                 ("graph_replays", ct.c_uint64), ("last_jobs", ct.c_uint32),
                 ("last_groups", ct.c_uint32), ("last_chains", ct.c_uint32),
-                ("last_fallback_items", ct.c_uint32)]
+                ("last_fallback_items", ct.c_uint32), ("tune_cache_hits", ct.c_uint32),
+                ("tune_shapes_timed", ct.c_uint32)]
 
 
 class CvServerStats(ct.Structure):
@@ -120,6 +123,9 @@ def load() -> ct.CDLL:
     L.cv_key_set_path.restype = ct.c_int
     L.cv_key_set_path.argtypes = [vp, ct.c_int]
     L.cv_key_graph_counts.restype = ct.c_int
+    L.cv_key_autotune.restype = ct.c_int
+    L.cv_key_autotune.argtypes = [vp, ct.c_int, ct.c_uint32, vp, ct.POINTER(CvLaunch),
+                                  ct.POINTER(ct.c_int)]
     L.cv_key_graph_counts.argtypes = [vp, ct.POINTER(ct.c_uint64), ct.POINTER(ct.c_uint64)]
     for name in ("cv_encrypt_frames", "cv_decrypt_frames"):
         f = getattr(L, name)
@@ -318,6 +324,13 @@ class Key:
     def set_spin_limit(self, polls: int):
         """Testing hook (cv_key_set_spin_limit)."""
         _check(load().cv_key_set_spin_limit(self._h, polls))
+
+    def autotune(self, decrypt: bool, n_frames: int, stream=None):
+        """cv_key_autotune: (launch shape dict, taken from the cache?)."""
+        l, c = CvLaunch(), ct.c_int()
+        _check(load().cv_key_autotune(self._h, int(bool(decrypt)), n_frames, _stream(stream),
+                                      ct.byref(l), ct.byref(c)))
+        return {f: getattr(l, f) for f, _ in CvLaunch._fields_}, bool(c.value)
 
     def graph_counts(self):
         """(captures, replays) of the key's graphs (cv_launch.use_graph)."""

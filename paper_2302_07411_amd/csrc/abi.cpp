@@ -8,6 +8,7 @@
 // at most `batch_frames` frames; per batch: shift tables H2D, one PRBG launch
 // for the whole batch, then r round launches over the whole batch.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <cmath>
@@ -870,6 +871,119 @@ cv_status cv_key_get_launch(const cv_key* k, cv_launch* l) {
   l->tile_rows_pw = k->tile_pw;
   l->fused_groups = k->fused_groups;
   l->use_graph = k->use_graph ? 1u : 0u;
+  return CV_OK;
+}
+
+cv_status cv_key_autotune(cv_key* k, int decrypt, uint32_t n_frames, void* stream, cv_launch* best,
+                          int* cached) {
+  if (!k) return fail(CV_E_INVAL, "key is NULL");
+  if (n_frames == 0) return fail(CV_E_INVAL, "n_frames must be >= 1");
+  if (cached) *cached = 0;
+  const Geom& g = k->g;
+  if (!((g.C == 3 || g.C == 4) && g.W % 16 == 0) || k->tile_pw == 0)
+    return fail(CV_E_INVAL, "the fused path needs C in {3,4} and W a multiple of 16");
+  cv_status s = check_async_errors(k, false);
+  if (s != CV_OK) return s;
+  DeviceGuard dg(k->device);
+  hipStream_t st = (hipStream_t)stream;
+  char kb[160];
+  snprintf(kb, sizeof kb, "key|lds%zu|%ux%ux%u/n%u/r%u/%c%u", k->lds_max, g.H, g.W, g.C, g.n, g.r,
+           decrypt ? 'd' : 'e', n_frames);
+  const std::string key = kb;
+  cv_launch cur{};
+  (void)cv_key_get_launch(k, &cur);
+  cur.batch_frames = std::max(cur.batch_frames, n_frames);  // one batch per call
+  std::map<std::string, int64_t> f;
+  if (tune_lookup(key, &f) && f.count("round_variant") && f.count("threads") &&
+      f.count("fused_groups")) {
+    cv_launch l = cur;
+    l.round_variant = (uint32_t)f["round_variant"];
+    l.threads = (uint32_t)f["threads"];
+    l.fused_groups = (uint32_t)f["fused_groups"];
+    if (cv_key_set_launch(k, &l) == CV_OK) {
+      k->path = CV_PATH_FUSED;
+      if (cached) *cached = 1;
+      if (best) (void)cv_key_get_launch(k, best);
+      return CV_OK;
+    }
+  }
+  // scratch frames and keystream (their bytes do not change the timing)
+  const uint64_t F = k->F, bytes = (uint64_t)n_frames * F;
+  uint8_t *d_in = nullptr, *d_out = nullptr, *d_ks = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto release = [&]() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (d_in) (void)hipFree(d_in);
+    if (d_out) (void)hipFree(d_out);
+    if (d_ks) (void)hipFree(d_ks);
+  };
+  if (hipMalloc(&d_in, bytes) != hipSuccess || hipMalloc(&d_out, bytes) != hipSuccess ||
+      hipMalloc(&d_ks, bytes * g.r) != hipSuccess) {
+    (void)hipGetLastError();
+    release();
+    return fail(CV_E_NOMEM, "autotuner scratch allocation failed");
+  }
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    release();
+    return hip_fail(hipErrorOutOfMemory, "hipEventCreate");
+  }
+  std::vector<uint32_t> seeds(n_frames);
+  for (uint32_t t = 0; t < n_frames; t++) seeds[t] = 1 + t;
+  const bool dec = decrypt != 0;
+  cv_launch win = cur;
+  float win_ms = -1.f;
+  // candidates: the fused kernels (pixel-word with 512 or 1024 threads,
+  // row-run) and the frame groups in flight, 8 at a time up to the capacity
+  for (uint32_t variant : {2u, 3u}) {
+    for (uint32_t th : {512u, 1024u}) {
+      if (variant == 3 && th != 1024) continue;
+      for (uint32_t groups = 8;; groups += 8) {
+        cv_launch l = cur;
+        l.round_variant = variant;
+        l.threads = th;
+        l.fused_groups = groups;
+        if (cv_key_set_launch(k, &l) != CV_OK) break;
+        if (fused_group_cap(k, dec) < groups) break;  // beyond the resident capacity
+        if (variant == 3 && fused_kernel(k, dec) == FUSED_PW) break;  // no row-run kernel here
+        if ((s = ensure_workspace(k, n_frames)) != CV_OK || (s = ensure_fused(k)) != CV_OK ||
+            (s = upload_shift_tables(k, seeds.data(), n_frames, st)) != CV_OK)
+          break;
+        float ms = 0.f;
+        for (int rep = 0; rep < 4 && s == CV_OK; rep++) {
+          if (rep == 1 && hipEventRecord(e0, st) != hipSuccess) s = hip_fail(hipErrorUnknown, "hipEventRecord");
+          if (s == CV_OK)
+            s = launch_fused_ws(k, dec, d_in, d_out, d_ks, n_frames, k->d_gm, k->d_fscratch,
+                                k->d_counters, k->d_err, k->fused_groups, st);
+        }
+        if (s != CV_OK) break;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          s = hip_fail(hipErrorUnknown, "autotuner timing");
+          break;
+        }
+        ms /= 3.f;
+        if (win_ms < 0 || ms < win_ms) {
+          win_ms = ms;
+          win = l;
+        }
+      }
+      if (s != CV_OK) break;
+    }
+    if (s != CV_OK) break;
+  }
+  (void)hipStreamSynchronize(st);
+  release();
+  if (s != CV_OK) {
+    (void)cv_key_set_launch(k, &cur);
+    return s;
+  }
+  if ((s = check_async_errors(k, true)) != CV_OK) return s;
+  if ((s = cv_key_set_launch(k, &win)) != CV_OK) return s;
+  k->path = CV_PATH_FUSED;
+  (void)tune_store(key, {{"round_variant", win.round_variant}, {"threads", win.threads},
+                         {"fused_groups", k->fused_groups}});
+  if (best) (void)cv_key_get_launch(k, best);
   return CV_OK;
 }
 

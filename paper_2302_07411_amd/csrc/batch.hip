@@ -14,7 +14,7 @@
 // path).
 //
 // Two kernels: the pixel-word one (any workgroup size), and the row-run one
-// (1024 threads, frame widths a multiple of 12): encryption by whole
+// (1024 threads): encryption by whole
 // source-row runs with packed-byte diffusion, decryption in one pass per
 // tile reading the round input, its predecessors and keystream as
 // contiguous runs (skew_ops.h).
@@ -88,18 +88,19 @@ __global__ __launch_bounds__(kMaxThreads) void batch_rounds_kernel(BatchArgs A) 
   }
 }
 
-// One encryption tile of the row-run kernel with the variant's flags.
-template <uint32_t C, bool kFull>
+// One encryption tile of the row-run kernel with the variant's flags (runs
+// of 12 pixels per lane when W is a multiple of 12, else of 4).
+template <uint32_t C, uint32_t KQ, bool kFull>
 __device__ __forceinline__ uint32_t enc_rows_tile(bool first, bool last, const View& v,
                                                   const Geom& g, uint32_t j, uint32_t lo,
                                                   uint32_t hi, uint32_t t0, uint32_t R,
                                                   uint32_t carry, int64_t sa, uint32_t* lds,
                                                   uint32_t* wsum) {
   using skew::skew_tile;
-  if (first && last) return skew_tile<C, 12, true, true, kFull>(v, g, j, lo, hi, t0, R, carry, sa, lds, wsum);
-  if (first) return skew_tile<C, 12, true, false, kFull>(v, g, j, lo, hi, t0, R, carry, sa, lds, wsum);
-  if (last) return skew_tile<C, 12, false, true, kFull>(v, g, j, lo, hi, t0, R, carry, sa, lds, wsum);
-  return skew_tile<C, 12, false, false, kFull>(v, g, j, lo, hi, t0, R, carry, sa, lds, wsum);
+  if (first && last) return skew_tile<C, KQ, true, true, kFull>(v, g, j, lo, hi, t0, R, carry, sa, lds, wsum);
+  if (first) return skew_tile<C, KQ, true, false, kFull>(v, g, j, lo, hi, t0, R, carry, sa, lds, wsum);
+  if (last) return skew_tile<C, KQ, false, true, kFull>(v, g, j, lo, hi, t0, R, carry, sa, lds, wsum);
+  return skew_tile<C, KQ, false, false, kFull>(v, g, j, lo, hi, t0, R, carry, sa, lds, wsum);
 }
 
 // Rows [t0, t0+R) of the tile (row pitch W+4) to the round output: packed
@@ -127,7 +128,7 @@ __device__ __forceinline__ void store_rows(const uint32_t* tile, uint32_t W, uin
   }
 }
 
-template <uint32_t C>
+template <uint32_t C, uint32_t KQ>
 __global__ __launch_bounds__(skew::kThreads) void batch_rows_kernel(BatchArgs A) {
   extern __shared__ __align__(16) uint32_t lds[];
   __shared__ uint32_t wsum[skew::kWaves];
@@ -168,8 +169,8 @@ __global__ __launch_bounds__(skew::kThreads) void batch_rows_kernel(BatchArgs A)
           for (uint32_t t0 = lo; t0 < hi; t0 += J.tile_enc) {
             const uint32_t R = min(J.tile_enc, hi - t0);
             const int64_t sa = t0 == lo ? seed_at : -1;
-            carry = full ? enc_rows_tile<C, true>(first, last, v, g, s, lo, hi, t0, R, carry, sa, lds, wsum)
-                         : enc_rows_tile<C, false>(first, last, v, g, s, lo, hi, t0, R, carry, sa, lds, wsum);
+            carry = full ? enc_rows_tile<C, KQ, true>(first, last, v, g, s, lo, hi, t0, R, carry, sa, lds, wsum)
+                         : enc_rows_tile<C, KQ, false>(first, last, v, g, s, lo, hi, t0, R, carry, sa, lds, wsum);
             __syncthreads();  // the next tile's gather overwrites the LDS tile and wsum
           }
         }
@@ -209,13 +210,19 @@ __global__ void reset_batch_groups(uint32_t* p, uint32_t groups) {
 
 }  // namespace
 
-hipError_t launch_batch_rounds(const BatchArgs& a, uint32_t C, bool rows, uint32_t threads,
-                               size_t lds, hipStream_t s) {
+static const void* rows_fn(uint32_t C, uint32_t KQ) {
+  if (C == 3) return KQ == 12 ? reinterpret_cast<const void*>(&batch_rows_kernel<3, 12>)
+                              : reinterpret_cast<const void*>(&batch_rows_kernel<3, 4>);
+  return KQ == 12 ? reinterpret_cast<const void*>(&batch_rows_kernel<4, 12>)
+                  : reinterpret_cast<const void*>(&batch_rows_kernel<4, 4>);
+}
+
+hipError_t launch_batch_rounds(const BatchArgs& a, uint32_t C, uint32_t KQ, bool rows,
+                               uint32_t threads, size_t lds, hipStream_t s) {
   hipLaunchKernelGGL(reset_batch_groups, dim3(1), dim3(256), 0, s, a.counters, a.groups);
   const uint32_t slots = ((a.groups + 7) / 8) * 8 * a.G;
   if (rows) {
-    const void* fn = C == 3 ? reinterpret_cast<const void*>(&batch_rows_kernel<3>)
-                            : reinterpret_cast<const void*>(&batch_rows_kernel<4>);
+    const void* fn = rows_fn(C, KQ);
     if (lds > 64 * 1024) {
       const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
@@ -231,14 +238,12 @@ hipError_t launch_batch_rounds(const BatchArgs& a, uint32_t C, bool rows, uint32
   return hipGetLastError();
 }
 
-uint32_t batch_resident_groups(uint32_t C, bool rows, uint32_t G, uint32_t threads, size_t lds,
-                               int device) {
+uint32_t batch_resident_groups(uint32_t C, uint32_t KQ, bool rows, uint32_t G, uint32_t threads,
+                               size_t lds, int device) {
   int per_cu = 0, cus = 0;
   hipError_t e;
   if (rows) {
-    const void* fn = C == 3 ? reinterpret_cast<const void*>(&batch_rows_kernel<3>)
-                            : reinterpret_cast<const void*>(&batch_rows_kernel<4>);
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, skew::kThreads, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rows_fn(C, KQ), skew::kThreads, lds);
   } else {
     e = C == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_rounds_kernel<3>, threads, lds)
                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_rounds_kernel<4>, threads, lds);

@@ -16,6 +16,7 @@
 // copy, keystream launches, rounds launches, error-flag read-back -- is
 // replayed from a HIP graph captured the first time.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -30,6 +31,13 @@ using namespace cv::rt;
 namespace {
 
 constexpr uint32_t kSpinLimit = 1u << 21;  // about two seconds of polling per barrier
+// Frame jobs are launched in classes: by channel count (3, 4) and by whether
+// the row-run kernel takes runs of 12 pixels per lane (W a multiple of 12)
+// or of 4.  Class index = (C == 4) * 2 + (W % 12 != 0).
+constexpr int kClasses = 4;
+int job_class(const cv::Geom& g) { return (g.C == 4 ? 2 : 0) + (g.W % 12 != 0 ? 1 : 0); }
+uint32_t class_C(int c) { return c >= 2 ? 4u : 3u; }
+uint32_t class_KQ(int c) { return (c & 1) ? 4u : 12u; }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -43,18 +51,18 @@ struct Signature {
   uint32_t* d_counters = nullptr;
   uint32_t n_chains[cv::kPrbgVariants] = {};
   size_t chain_off[cv::kPrbgVariants] = {};
-  uint32_t groups[2] = {0, 0};  // C = 3, C = 4
-  uint32_t G = 0, threads = 0;
-  bool rows[2] = {false, false};
-  size_t lds[2] = {0, 0};
-  size_t job_off[2] = {0, 0}, gj_off[2] = {0, 0}, go_off[2] = {0, 0};
+  uint32_t groups[kClasses] = {};  // per job class
+  uint32_t G = 0, threads = 0, tile_cap = 0;
+  bool rows[kClasses] = {};
+  size_t lds[kClasses] = {};
+  size_t job_off[kClasses] = {}, gj_off[kClasses] = {}, go_off[kClasses] = {};
   uint64_t scratch_stride = 0;
   bool operator==(const Signature& o) const {
     bool eq = blob_bytes == o.blob_bytes && d_blob == o.d_blob && d_ks == o.d_ks &&
               d_scratch == o.d_scratch && d_counters == o.d_counters && G == o.G &&
-              threads == o.threads && scratch_stride == o.scratch_stride;
+              threads == o.threads && tile_cap == o.tile_cap && scratch_stride == o.scratch_stride;
     for (int v = 0; v < cv::kPrbgVariants; v++) eq = eq && n_chains[v] == o.n_chains[v] && chain_off[v] == o.chain_off[v];
-    for (int c = 0; c < 2; c++)
+    for (int c = 0; c < kClasses; c++)
       eq = eq && groups[c] == o.groups[c] && rows[c] == o.rows[c] && lds[c] == o.lds[c] &&
            job_off[c] == o.job_off[c] &&
            gj_off[c] == o.gj_off[c] && go_off[c] == o.go_off[c];
@@ -83,7 +91,7 @@ struct Span {
 
 struct cv_batch {
   int device = 0;
-  cv_batch_shape shape{1024, 16, 0, 1};
+  cv_batch_shape shape{1024, 8, 0, 1, 0};
   size_t lds_max = 0;
   hipStream_t cap = nullptr;  // private stream that graphs are captured on
   std::array<Slot, 2> slot;
@@ -114,13 +122,13 @@ namespace {
 // ------------------------------------------------------------ the plan ---
 struct Plan {
   std::vector<cv::PlcmChain> chains[cv::kPrbgVariants];  // by generator variant
-  std::vector<cv::BatchJob> jobs[2];     // by C (3, 4); ks and gm hold offsets until fill_blob
-  std::vector<uint32_t> group_jobs[2], group_off[2];
+  std::vector<cv::BatchJob> jobs[kClasses];  // by job class; ks and gm hold offsets until fill_blob
+  std::vector<uint32_t> group_jobs[kClasses], group_off[kClasses];
   std::vector<uint32_t> gm;              // shift tables of every frame job
   uint64_t scratch_stride = 0;
-  uint32_t groups[2] = {0, 0};
-  bool rows[2] = {false, false};  // the row-run kernel (else the pixel-word one)
-  size_t lds[2] = {0, 0};
+  uint32_t groups[kClasses] = {};
+  bool rows[kClasses] = {};  // the row-run kernel (else the pixel-word one)
+  size_t lds[kClasses] = {};
   uint64_t steps = 0, frame_rounds = 0;
 };
 
@@ -197,20 +205,23 @@ cv_status plan_tick(const cv_batch* b, const std::vector<ChainJob>& cj,
   P.scratch_stride = align_up(pwf_max, 256);
   P.gm.resize(gm);
   gm = 0;
-  std::vector<std::pair<uint64_t, uint32_t>> order[2];  // (cost, job) per C
-  // the row-run kernel takes a channel count's jobs when it takes every one
-  bool rows_ok[2] = {threads == 1024, threads == 1024};
-  size_t lds_pw[2] = {0, 0}, lds_rows[2] = {0, 0};
+  std::vector<std::pair<uint64_t, uint32_t>> order[kClasses];  // (cost, job) per class
+  // the row-run kernel takes a class's jobs when it takes every one
+  bool rows_ok[kClasses];
+  for (bool& x : rows_ok) x = threads == 1024;
+  size_t lds_pw[kClasses] = {}, lds_rows[kClasses] = {};
   for (const FrameJob& f : fj) {
     const Geom& g = f.k->g;
     shift_table(g.H, g.W, f.s_c, P.gm.data() + gm);
-    const int ci = g.C == 4;
-    const uint32_t tile = pw_tile_rows(g, threads, b->lds_max);
+    const int ci = job_class(g);
+    // the LDS tiling: the largest tiles that fit, capped by the shape
+    const uint32_t cap = b->shape.tile_rows_max ? b->shape.tile_rows_max : 0xFFFFFFFFu;
+    const uint32_t tile = std::min(pw_tile_rows(g, threads, b->lds_max), cap);
     if (tile == 0) return fail(CV_E_INVAL, "frame too wide for the batch's workgroup size");
     lds_pw[ci] = std::max(lds_pw[ci], cv::round_pw_lds_bytes(g, tile));
-    const uint32_t te = cv::rounds_skew_tile_rows(g, b->lds_max);
-    const uint32_t td = cv::batch_unskew_tile_rows(g, b->lds_max);
-    rows_ok[ci] = rows_ok[ci] && g.W % 12 == 0 && te > 0 && td > 0;
+    const uint32_t te = std::min(cv::rounds_skew_tile_rows(g, b->lds_max), cap);
+    const uint32_t td = std::min(cv::batch_unskew_tile_rows(g, b->lds_max), cap);
+    rows_ok[ci] = rows_ok[ci] && te > 0 && td > 0;
     if (rows_ok[ci])
       lds_rows[ci] = std::max(lds_rows[ci], cv::batch_rows_lds_bytes(g, f.decrypt != 0, f.decrypt ? td : te));
     cv::BatchJob J{};
@@ -231,12 +242,13 @@ cv_status plan_tick(const cv_batch* b, const std::vector<ChainJob>& cj,
     P.frame_rounds += g.r;
     gm += g.H;
   }
-  // per channel count: longest job first onto the least loaded group
-  for (int ci = 0; ci < 2; ci++) {
+  // per job class: longest job first onto the least loaded group
+  for (int ci = 0; ci < kClasses; ci++) {
     if (P.jobs[ci].empty()) continue;
     P.rows[ci] = rows_ok[ci];
     P.lds[ci] = rows_ok[ci] ? lds_rows[ci] : lds_pw[ci];
-    const uint32_t cap = cv::batch_resident_groups(3 + ci, P.rows[ci], G, threads, P.lds[ci], b->device);
+    const uint32_t cap = cv::batch_resident_groups(class_C(ci), class_KQ(ci), P.rows[ci], G, threads,
+                                                   P.lds[ci], b->device);
     if (cap == 0) return fail(CV_E_INVAL, "batch launch shape does not fit on the device");
     uint32_t groups = std::min<uint64_t>(cap, P.jobs[ci].size());
     if (b->shape.max_groups) groups = std::min(groups, b->shape.max_groups);
@@ -289,7 +301,7 @@ void drop_graphs(cv_batch* b) {
 
 // Layout of the blob: chains (3 variants), jobs, group tables, shift tables.
 struct Layout {
-  size_t chain_off[cv::kPrbgVariants], job_off[2], gj_off[2], go_off[2], gm_off, bytes;
+  size_t chain_off[cv::kPrbgVariants], job_off[kClasses], gj_off[kClasses], go_off[kClasses], gm_off, bytes;
 };
 
 Layout layout(const Plan& P) {
@@ -299,7 +311,7 @@ Layout layout(const Plan& P) {
     L.chain_off[v] = o;
     o = align_up(o + P.chains[v].size() * sizeof(cv::PlcmChain), 16);
   }
-  for (int c = 0; c < 2; c++) {
+  for (int c = 0; c < kClasses; c++) {
     L.job_off[c] = o;
     o = align_up(o + P.jobs[c].size() * sizeof(cv::BatchJob), 16);
     L.gj_off[c] = o;
@@ -341,7 +353,7 @@ void fill_blob(const cv_batch* b, const Plan& P, const Layout& L, uint8_t* h,
     if (!P.chains[v].empty())
       memcpy(h + L.chain_off[v], P.chains[v].data(), P.chains[v].size() * sizeof(cv::PlcmChain));
   const uint8_t* d_gm = b->d_blob + L.gm_off;
-  for (int c = 0; c < 2; c++) {
+  for (int c = 0; c < kClasses; c++) {
     cv::BatchJob* J = (cv::BatchJob*)(h + L.job_off[c]);
     for (size_t q = 0; q < P.jobs[c].size(); q++) {
       J[q] = P.jobs[c][q];
@@ -367,7 +379,7 @@ Signature signature(const cv_batch* b, const Plan& P, const Layout& L, uint8_t* 
     s.n_chains[v] = (uint32_t)P.chains[v].size();
     s.chain_off[v] = L.chain_off[v];
   }
-  for (int c = 0; c < 2; c++) {
+  for (int c = 0; c < kClasses; c++) {
     s.groups[c] = P.groups[c];
     s.rows[c] = P.rows[c];
     s.lds[c] = P.lds[c];
@@ -377,6 +389,7 @@ Signature signature(const cv_batch* b, const Plan& P, const Layout& L, uint8_t* 
   }
   s.G = b->shape.group_wgs;
   s.threads = b->shape.threads;
+  s.tile_cap = b->shape.tile_rows_max;
   s.scratch_stride = P.scratch_stride;
   return s;
 }
@@ -419,7 +432,8 @@ cv_status enqueue_tick(cv_batch* b, const Plan& P, const Layout& L, const Slot& 
   CV_HIP(hipMemcpyAsync(b->d_blob, s.h_blob, L.bytes, hipMemcpyHostToDevice, st));
   bool has_chains = false;
   for (const auto& cs : P.chains) has_chains = has_chains || !cs.empty();
-  const bool has_jobs = !P.jobs[0].empty() || !P.jobs[1].empty();
+  bool has_jobs = false;
+  for (const auto& js : P.jobs) has_jobs = has_jobs || !js.empty();
   hipEvent_t ta = nullptr;
   if (timed && has_chains && (ta = pooled(b))) CV_HIP(hipEventRecord(ta, st));
   for (int v = 0; v < cv::kPrbgVariants; v++)
@@ -435,7 +449,7 @@ cv_status enqueue_tick(cv_batch* b, const Plan& P, const Layout& L, const Slot& 
   }
   ta = nullptr;
   if (timed && has_jobs && (ta = pooled(b))) CV_HIP(hipEventRecord(ta, st));
-  for (int c = 0; c < 2; c++) {
+  for (int c = 0; c < kClasses; c++) {
     if (P.jobs[c].empty()) continue;
     cv::BatchArgs a{};
     a.jobs = (const cv::BatchJob*)(b->d_blob + L.job_off[c]);
@@ -448,7 +462,7 @@ cv_status enqueue_tick(cv_batch* b, const Plan& P, const Layout& L, const Slot& 
     a.G = b->shape.group_wgs;
     a.groups = P.groups[c];
     a.spin_limit = kSpinLimit;
-    CV_HIP(cv::launch_batch_rounds(a, 3 + c, P.rows[c], b->shape.threads, P.lds[c], st));
+    CV_HIP(cv::launch_batch_rounds(a, class_C(c), class_KQ(c), P.rows[c], b->shape.threads, P.lds[c], st));
   }
   if (ta) {
     hipEvent_t tb = pooled(b);
@@ -486,7 +500,7 @@ cv_status prepare(cv_batch* b, const std::vector<ChainJob>& cj, const std::vecto
   cv_status s = plan_tick(b, cj, fj, P);
   if (s != CV_OK) return s;
   L = layout(P);
-  const uint32_t gmax = std::max(P.groups[0], P.groups[1]);
+  const uint32_t gmax = *std::max_element(P.groups, P.groups + kClasses);
   if ((s = grow(&b->d_blob, &b->blob_cap, L.bytes, "batch table")) != CV_OK) return s;
   if ((s = grow(&b->d_scratch, &b->scratch_cap, std::max<uint64_t>(2 * P.scratch_stride * gmax, 256),
                 "batch scratch")) != CV_OK)
@@ -616,8 +630,12 @@ cv_status batch_enqueue(cv_batch* b, const std::vector<ChainJob>& cj, const std:
   Layout L;
   cv_status s = prepare(b, cj, fj, P, L);
   if (s != CV_OK) return s;
-  b->info.last_jobs = (uint32_t)(P.jobs[0].size() + P.jobs[1].size());
-  b->info.last_groups = P.groups[0] + P.groups[1];
+  b->info.last_jobs = 0;
+  b->info.last_groups = 0;
+  for (int c = 0; c < kClasses; c++) {
+    b->info.last_jobs += (uint32_t)P.jobs[c].size();
+    b->info.last_groups += P.groups[c];
+  }
   b->info.last_chains = 0;
   for (const auto& cs : P.chains) b->info.last_chains += (uint32_t)cs.size();
   if (cj.empty() && fj.empty()) return CV_OK;
@@ -669,6 +687,34 @@ cv_status check_shape(const cv_batch_shape& s) {
   if (s.group_wgs < 1 || s.group_wgs > 64) return fail(CV_E_INVAL, "group_wgs must be in 1..64");
   if (s.use_graph > 1) return fail(CV_E_INVAL, "use_graph must be 0 or 1");
   return CV_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Shape class of a tick for the autotuner cache: the sorted multiset of its
+// batched items' (H, W, C, n, r, direction, frames), and the device's LDS.
+std::string tune_key(const cv_batch* b, const cv_batch_item* items, size_t n_items) {
+  std::vector<std::string> parts;
+  for (size_t i = 0; i < n_items; i++) {
+    const cv_batch_item& it = items[i];
+    if (it.n_frames == 0 || !item_eligible(b, it)) continue;
+    const Geom& g = it.key->g;
+    char buf[96];
+    snprintf(buf, sizeof buf, "%ux%ux%u/n%u/r%u/%c%u", g.H, g.W, g.C, g.n, g.r,
+             it.decrypt ? 'd' : 'e', it.n_frames);
+    parts.push_back(buf);
+  }
+  std::sort(parts.begin(), parts.end());
+  std::string k = "batch|lds" + std::to_string(b->lds_max);
+  for (size_t i = 0; i < parts.size();) {
+    size_t j = i;
+    while (j < parts.size() && parts[j] == parts[i]) j++;
+    k += "|" + std::to_string(j - i) + "*" + parts[i];
+    i = j;
+  }
+  return k;
 }
 
 }  // namespace
@@ -760,52 +806,107 @@ cv_status cv_batch_autotune(cv_batch* b, const cv_batch_item* items, size_t n_it
   if ((s = check_flag(b, false)) != CV_OK) return s;
   DeviceGuard dg(b->device);
   hipStream_t st = (hipStream_t)stream;
-  if ((s = order_after_last(b, st)) != CV_OK) return s;
   const cv_batch_shape keep = b->shape;
+  // the tick's shape class: its batched frame jobs' geometries and directions
+  const std::string key = tune_key(b, items, n_items);
+  std::map<std::string, int64_t> cached;
+  if (tune_lookup(key, &cached) && cached.count("threads") && cached.count("group_wgs") &&
+      cached.count("max_groups") && cached.count("tile_rows_max")) {
+    cv_batch_shape c = keep;
+    c.threads = (uint32_t)cached["threads"];
+    c.group_wgs = (uint32_t)cached["group_wgs"];
+    c.max_groups = (uint32_t)cached["max_groups"];
+    c.tile_rows_max = (uint32_t)cached["tile_rows_max"];
+    if (check_shape(c) == CV_OK) {
+      b->shape = c;
+      b->info.tune_cache_hits++;
+      if (best) *best = c;
+      return CV_OK;
+    }
+  }
+  if ((s = order_after_last(b, st)) != CV_OK) return s;
   const bool prof = b->profiling;
   b->profiling = true;  // time each rounds launch
   cv_batch_shape win = keep;
   double win_ms = -1.0;
-  const uint32_t threads_c[] = {512, 1024}, G_c[] = {2, 4, 8, 16, 32};
+  // candidates: the kernel (512 threads: pixel-word, 1024: row-run), G, the
+  // groups in flight (0 = all resident, else half the resident groups) and
+  // the LDS tiling (0 = the largest tiles, else half their rows)
+  const uint32_t threads_c[] = {512, 1024}, G_c[] = {4, 8, 16, 32};
   for (uint32_t th : threads_c) {
     for (uint32_t G : G_c) {
-      b->shape = keep;
-      b->shape.threads = th;
-      b->shape.group_wgs = G;
-      std::vector<ChainJob> cj;
-      std::vector<FrameJob> fj;
-      std::vector<size_t> fallback, eligible;
-      uint64_t ks = 0;
-      collect(b, items, n_items, cj, fj, fallback, eligible, ks);
-      if ((s = grow(&b->d_ks, &b->ks_cap, std::max<uint64_t>(ks, 16), "batch keystream")) != CV_OK)
-        break;
-      Plan P;
-      Layout L;
-      if ((s = prepare(b, {}, fj, P, L)) != CV_OK) break;
-      if (P.jobs[0].empty() && P.jobs[1].empty()) break;
-      Slot* sp = nullptr;
-      if ((s = next_slot(b, L.bytes, &sp)) != CV_OK) break;
-      Slot& sl = *sp;
-      fill_blob(b, P, L, sl.h_blob, b->d_ks);
-      if ((s = drain(b)) != CV_OK) break;
-      b->prof = cv_profile{};
-      for (int rep = 0; rep < 4 && s == CV_OK; rep++) s = enqueue_tick(b, P, L, sl, st, true, b->d_ks);
+      for (int half_groups = 0; half_groups < 2 && s == CV_OK; half_groups++) {
+        for (int half_tiles = 0; half_tiles < 2 && s == CV_OK; half_tiles++) {
+          b->shape = keep;
+          b->shape.threads = th;
+          b->shape.group_wgs = G;
+          b->shape.max_groups = 0;
+          b->shape.tile_rows_max = 0;
+          std::vector<ChainJob> cj;
+          std::vector<FrameJob> fj;
+          std::vector<size_t> fallback, eligible;
+          uint64_t ks = 0;
+          collect(b, items, n_items, cj, fj, fallback, eligible, ks);
+          if (fj.empty()) break;
+          if (half_tiles) {
+            // half the rows of the largest tile of any job
+            uint32_t rows = 0;
+            for (const FrameJob& f : fj) {
+              const Geom& g = f.k->g;
+              rows = std::max(rows, std::max(pw_tile_rows(g, th, b->lds_max),
+                                             std::max(cv::rounds_skew_tile_rows(g, b->lds_max),
+                                                      cv::batch_unskew_tile_rows(g, b->lds_max))));
+            }
+            if (rows < 2) continue;
+            b->shape.tile_rows_max = rows / 2;
+          }
+          if ((s = grow(&b->d_ks, &b->ks_cap, std::max<uint64_t>(ks, 16), "batch keystream")) != CV_OK)
+            break;
+          Plan P;
+          Layout L;
+          if ((s = prepare(b, {}, fj, P, L)) != CV_OK) {
+            // a shape this tick cannot use (too wide for the workgroup) is skipped
+            if (s == CV_E_INVAL) {
+              s = CV_OK;
+              continue;
+            }
+            break;
+          }
+          if (half_groups) {
+            const uint32_t gmax = *std::max_element(P.groups, P.groups + kClasses);
+            if (gmax < 16) continue;
+            b->shape.max_groups = gmax / 2 / 8 * 8;
+            Plan P2;
+            if ((s = prepare(b, {}, fj, P2, L)) != CV_OK) break;
+            P = std::move(P2);
+          }
+          Slot* sp = nullptr;
+          if ((s = next_slot(b, L.bytes, &sp)) != CV_OK) break;
+          Slot& sl = *sp;
+          fill_blob(b, P, L, sl.h_blob, b->d_ks);
+          if ((s = drain(b)) != CV_OK) break;
+          b->prof = cv_profile{};
+          for (int rep = 0; rep < 4 && s == CV_OK; rep++) s = enqueue_tick(b, P, L, sl, st, true, b->d_ks);
+          if (s != CV_OK) break;
+          CV_HIP(hipEventRecord(sl.copied, st));
+          sl.pending = true;
+          // the first launch warms up; the rest are timed
+          if (!b->spans.empty()) {
+            Span first = b->spans.front();
+            b->spans.erase(b->spans.begin());
+            if ((s = drain(b)) != CV_OK) break;
+            b->event_pool.push_back(first.a);
+            b->event_pool.push_back(first.b);
+          }
+          b->info.tune_shapes_timed++;
+          const double ms = b->prof.round_ms / std::max<uint64_t>(1, b->prof.round_launches);
+          if (win_ms < 0 || ms < win_ms) {
+            win_ms = ms;
+            win = b->shape;
+          }
+        }
+      }
       if (s != CV_OK) break;
-      CV_HIP(hipEventRecord(sl.copied, st));
-      sl.pending = true;
-      // the first launch warms up; the rest are timed
-      if (!b->spans.empty()) {
-        Span first = b->spans.front();
-        b->spans.erase(b->spans.begin());
-        if ((s = drain(b)) != CV_OK) break;
-        b->event_pool.push_back(first.a);
-        b->event_pool.push_back(first.b);
-      }
-      const double ms = b->prof.round_ms / std::max<uint64_t>(1, b->prof.round_launches);
-      if (win_ms < 0 || ms < win_ms) {
-        win_ms = ms;
-        win = b->shape;
-      }
     }
     if (s != CV_OK) break;
   }
@@ -819,6 +920,10 @@ cv_status cv_batch_autotune(cv_batch* b, const cv_batch_item* items, size_t n_it
   if (s != CV_OK) return s;
   if (s2 != CV_OK) return s2;
   if ((s = check_flag(b, true)) != CV_OK) return s;
+  if (win_ms >= 0)
+    (void)tune_store(key, {{"threads", b->shape.threads}, {"group_wgs", b->shape.group_wgs},
+                           {"max_groups", b->shape.max_groups},
+                           {"tile_rows_max", b->shape.tile_rows_max}});
   if (best) *best = b->shape;
   return CV_OK;
 }

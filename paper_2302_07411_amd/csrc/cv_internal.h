@@ -179,12 +179,14 @@ struct BatchArgs {
   uint32_t G, groups, spin_limit;
 };
 
-// rows = true: the row-run kernel (1024 threads; every job with W a multiple
-// of 12 and tile_enc, tile_dec > 0); false: the pixel-word kernel.
-hipError_t launch_batch_rounds(const BatchArgs& a, uint32_t C, bool rows, uint32_t threads,
-                               size_t lds, hipStream_t s);
-uint32_t batch_resident_groups(uint32_t C, bool rows, uint32_t G, uint32_t threads, size_t lds,
-                               int device);
+// rows = true: the row-run kernel (1024 threads; every job with tile_enc,
+// tile_dec > 0); false: the pixel-word kernel.
+// KQ: the row-run kernel's pixels per lane in the encryption diffusion (12
+// for frame widths that are multiples of 12, else 4).
+hipError_t launch_batch_rounds(const BatchArgs& a, uint32_t C, uint32_t KQ, bool rows,
+                               uint32_t threads, size_t lds, hipStream_t s);
+uint32_t batch_resident_groups(uint32_t C, uint32_t KQ, bool rows, uint32_t G, uint32_t threads,
+                               size_t lds, int device);
 // Row-run batch kernel: decryption tile rows for geometry g (0 = does not
 // fit) and the LDS a job needs in either direction.
 uint32_t batch_unskew_tile_rows(const Geom& g, size_t lds_max);

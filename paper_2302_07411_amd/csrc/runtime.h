@@ -1,6 +1,7 @@
 // Host-side runtime state of libchaosvid shared by the C-ABI translation
 // units (abi.cpp: keys; batch_host.cpp: multi-stream batches).
 #pragma once
+#include <map>
 #include <string>
 #include <vector>
 
@@ -185,6 +186,10 @@ struct FrameJob {
 // Every frame job must satisfy pw_eligible for the batch's shape.
 cv_status batch_enqueue(cv_batch* b, const std::vector<ChainJob>& cj, const std::vector<FrameJob>& fj,
                         uint8_t* ks_base, hipStream_t st);
+// Autotuner cache (tune_cache.cpp): the integer fields stored for a shape
+// class in the file named by CV_TUNE_CACHE; false when absent (or no file).
+bool tune_lookup(const std::string& key, std::map<std::string, int64_t>* fields);
+bool tune_store(const std::string& key, const std::map<std::string, int64_t>& fields);
 // Read-back of the batch's timeout flag as of its last completed tick.
 bool batch_flag_set(const cv_batch* b);
 

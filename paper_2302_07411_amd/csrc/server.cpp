@@ -271,7 +271,7 @@ hipError_t make_streams(cv_server* S, bool split) {
   int cus = 0;
   hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->device);
   if (e != hipSuccess) return e;
-  cv_batch_shape shape{kThreads, 8, 0, 0};
+  cv_batch_shape shape{kThreads, 8, 0, 0, 0};
   S->split = split && cus >= 64 && cus % 32 == 0;
   if (S->split) {
     std::vector<uint32_t> ks((cus + 31) / 32, 0), rd((cus + 31) / 32, 0);
