@@ -162,6 +162,18 @@ def bench_batched(B, torch, np, args):
     wall = time.perf_counter() - t0
     tick_ms = [ev[t].elapsed_time(ev[t + 1]) for t in range(ticks)]
     info = b.info()
+    # kernel times of a few more ticks, from the HIP events the batch records
+    # around its keystream and rounds launches on its stream
+    b.set_profiling(True)
+    prof_ticks = 3
+    for t in range(prof_ticks):
+        b.run(items((warm + ticks + t) % (ticks + warm)))
+    b.sync()
+    bprof = b.get_profile()
+    b.set_profiling(False)
+    rounds_ms = bprof["round_ms"] / max(1, bprof["round_launches"])
+    tick_bytes = sum((2 + R) * h * w * c for h, w, c, _ in specs)
+    rounds_gbs = tick_bytes / (rounds_ms * 1e-3) / 1e9
     # the plain path on the same streams: one call per stream and frame
     plain_keys = [B.Key(h, w, c, n, R, pm) for (h, w, c, n), pm in zip(specs, pms)]
     for k, s_, o in zip(plain_keys, srcs, outs):
@@ -184,6 +196,13 @@ def bench_batched(B, torch, np, args):
         "speedup_vs_plain": (frames / wall) / (64 * reps / plain_wall),
         "mb_per_s": sum(h * w * c for h, w, c, _ in specs) * ticks / wall / 1e6,
         "shape": shape, "graph_replays": info["graph_replays"],
+        "rounds_ms_per_tick": rounds_ms,
+        "keystream_ms_per_tick": bprof["prbg_ms"] / max(1, bprof["prbg_launches"]),
+        "rounds_roofline": {"bound": "hbm", "kernel": "batch_rows_kernel", "achieved": rounds_gbs,
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": rounds_gbs / HBM_PEAK_GBS,
+                            "per_launch": "one tick: 64 frames x (2+r)F bytes",
+                            "traffic": recorded_traffic("batch_rows_kernel")
+                            if shape["threads"] == 1024 else None},
         "oracle_sample_streams": len(sample), "oracle_mismatched_bytes": mism,
         "oracle_sample_s": oracle_s,
     }
@@ -566,8 +585,8 @@ def bench_quality(B, torch, np, args, src, dst, s_c, pm):
 def bench_decrypt(B, torch, src, s_c, pm, batch, reps=20):
     """Decryption rounds of one batch of the video on the fused path (the
     keystream generated beforehand, as for the rounds roofline), timed with
-    HIP events on the launch stream; the decrypted frames must equal the
-    plaintext byte for byte."""
+    the HIP events the library records around each rounds launch on its
+    stream; the decrypted frames must equal the plaintext byte for byte."""
     key = B.Key(H, W, C, N_SUB, R, pm)
     key.set_path(B.CV_PATH_FUSED)
     key.set_launch(batch_frames=batch)
@@ -577,18 +596,20 @@ def bench_decrypt(B, torch, src, s_c, pm, batch, reps=20):
     key.apply_rounds(False, src[:batch], enc, ks, s_c[:batch])
     key.apply_rounds(True, enc, dec, ks, s_c[:batch])  # warm-up
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
+    # HIP events the library records around each rounds launch on its stream
+    key.set_profiling(True)
     for _ in range(reps):
         key.apply_rounds(True, enc, dec, ks, s_c[:batch])
-    e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    prof = key.get_profile()
+    ms = prof["round_ms"] / max(1, prof["round_launches"])
     exact = bool(torch.equal(dec, src[:batch]))
     gbs = (2 + R) * F * batch / (ms * 1e-3) / 1e9
+    kernel = "rounds_unskew_kernel"  # fused decryption by row runs (every band one LDS tile here)
     return {"workload": f"{batch} frames of the {H}x{W}x{C} video, {R} rounds, keystream precomputed",
-            "kernel": "rounds_fused_kernel (decryption)", "launch_ms": ms, "gb_per_s": gbs,
+            "kernel": kernel, "launch_ms": ms, "gb_per_s": gbs,
             "frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "frames_per_s": batch / (ms * 1e-3),
+            "traffic": recorded_traffic(kernel) if batch == 48 else None,
             "round_trip_exact": exact}
 
 
