@@ -147,8 +147,8 @@ int cv_spec_version(void);
 /* Message of the last failed call on this thread ("" if none). */
 const char *cv_last_error(void);
 
-/* Set up the per-band generators of one video stream (Algorithm 2,
- * "Initialize PRBG_a^i with p_m^i"; Sec. 3, Eq. 5).
+/* Set up the per-band generators of one video stream (Algorithm 2: each
+ * subframe's generator starts from its record of P_m; Sec. 3, Eq. 5).
  *  geom      frame geometry; requires H,W,C,n,r >= 1, n <= H, every band at
  *            least 2 bytes, H*W*C < 2^32 per row block limits of uint32.
  *  map       CV_MAP_PLCM or CV_MAP_2DLASM.
@@ -294,8 +294,8 @@ cv_status cv_key_get_profile(cv_key *key, cv_profile *prof);
  * (Eq. 1) and diffusion (Eq. 3).
  *  in, out   device buffers of n_frames*H*W*C bytes, HWC frames back to
  *            back; must not overlap.
- *  s_c       host array of n_frames confusion seeds (Algorithm 1, "generate
- *            a confusion seed s_c"), each >= 1.
+ *  s_c       host array of n_frames confusion seeds (Algorithm 1 draws one
+ *            per frame), each >= 1.
  *  stream    hipStream_t the work is ordered on.
  * Advances the key by n_frames frames.  n_frames = 0 is a no-op.
  * Errors: CV_E_INVAL (NULL, overlap, s_c = 0), CV_E_NOMEM, CV_E_HIP. */
@@ -310,8 +310,8 @@ cv_status cv_decrypt_frames(cv_key *key, const uint8_t *in, uint8_t *out, const 
 
 /* Write the keystream of the next n_frames frames into ks (device, n_frames
  * * r*H*W*C bytes; per frame band i's r*S_i bytes start at byte
- * r*floor(i*H/n)*W*C) and advance the key (Algorithm 2, "Iterate PRBG_a^i,
- * generate enough iteration results; convert them into byte sequence B_i").
+ * r*floor(i*H/n)*W*C) and advance the key (Algorithm 2: each subframe's
+ * generator runs until the frame's bytes of that subframe exist).
  * Errors: CV_E_INVAL (NULL), CV_E_HIP. */
 cv_status cv_keystream_frames(cv_key *key, uint8_t *ks, size_t n_frames, void *stream);
 

@@ -240,8 +240,8 @@ int oracle_key_schedule(int is_lasm, const double *K, uint32_t n, double *pm,
 
 /* ------------------------------------------------------------ geometry --- */
 
-/* Algorithm 2 (startRow/endRow), generalised so that every row is covered
- * when n does not divide H. */
+/* Algorithm 2's band bounds (rows i*w/n up to (i+1)*w/n), generalised so
+ * that every row is covered when n does not divide H. */
 uint32_t oracle_band_lo(uint32_t H, uint32_t n, uint32_t i)
 {
     return (uint32_t)(((uint64_t)i * H) / n);
@@ -265,19 +265,27 @@ void oracle_gtable(uint32_t H, uint32_t s_c, int64_t *g)
 
 /* ----------------------------------------------------------- confusion --- */
 
-/* Eq. (1) as Algorithm 2 applies it: every source pixel (a,o) is written to
- * (alpha,beta) = ((a+o) mod H, (o+g[alpha]) mod W); the C bytes of a pixel
- * move together. */
-void oracle_confuse(const uint8_t *in, uint8_t *out, uint32_t H, uint32_t W,
-                    uint32_t C, const int64_t *g)
+/* Eq. (1) for the source pixels of rows [a_lo, a_hi): every pixel (a,o) is
+ * written to (alpha,beta) = ((a+o) mod H, (o+g[alpha]) mod W); the C bytes
+ * of a pixel move together.  (Algorithm 2 has each subframe's thread move the
+ * pixels of its own rows.) */
+void oracle_confuse_rows(const uint8_t *in, uint8_t *out, uint32_t H, uint32_t W,
+                         uint32_t C, const int64_t *g, uint32_t a_lo, uint32_t a_hi)
 {
-    for (uint32_t a = 0; a < H; a++)
+    for (uint32_t a = a_lo; a < a_hi; a++)
         for (uint32_t o = 0; o < W; o++) {
             int64_t alpha = mod_nonneg((int64_t)a + o, H);
             int64_t beta = mod_nonneg((int64_t)o + g[alpha], W);
             memcpy(out + ((uint64_t)alpha * W + beta) * C,
                    in + ((uint64_t)a * W + o) * C, C);
         }
+}
+
+/* Eq. (1) for the whole frame. */
+void oracle_confuse(const uint8_t *in, uint8_t *out, uint32_t H, uint32_t W,
+                    uint32_t C, const int64_t *g)
+{
+    oracle_confuse_rows(in, out, H, W, C, g, 0, H);
 }
 
 /* Eq. (2): pixel (alpha,beta) goes back to o=(beta-g[alpha]) mod W and
@@ -299,27 +307,34 @@ void oracle_unconfuse(const uint8_t *in, uint8_t *out, uint32_t H, uint32_t W,
 /* Keystream layout of one frame used by the oracle: the r*S_i bytes of band
  * i are stored from byte r*lo_i*W*C on (bands in order). */
 
-/* Eq. (3) for every band of the frame, round j: the first byte of band i is
- * chained to s_d, the last byte of band (i+1) mod n of the confused frame
- * (before diffusion); every other byte to the previous cipher byte. */
+/* Eq. (3) for band i of the frame, round j: its first byte is chained to
+ * s_d, the last byte of band (i+1) mod n of the confused frame (before
+ * diffusion); every other byte to the previous cipher byte. */
+void oracle_diffuse_band(const uint8_t *Y, uint8_t *Z, uint32_t H, uint32_t W,
+                         uint32_t C, uint32_t n, uint32_t r, uint32_t j,
+                         const uint8_t *ks, uint32_t i)
+{
+    uint64_t row = (uint64_t)W * C;
+    uint64_t lo = oracle_band_lo(H, n, i) * row;
+    uint64_t hi = oracle_band_lo(H, n, i + 1) * row;
+    uint64_t S = hi - lo;
+    uint64_t next_hi = oracle_band_lo(H, n, (i + 1) % n + 1) * row;
+    const uint8_t *b = ks + (uint64_t)r * lo + (uint64_t)j * S;
+    uint8_t prev = Y[next_hi - 1]; /* s_d */
+    for (uint64_t k = 0; k < S; k++) {
+        uint8_t sum = (uint8_t)(Y[lo + k] + b[k]);
+        Z[lo + k] = (uint8_t)(b[k] ^ sum ^ prev);
+        prev = Z[lo + k];
+    }
+}
+
+/* Eq. (3) for every band of the frame, round j. */
 void oracle_diffuse(const uint8_t *Y, uint8_t *Z, uint32_t H, uint32_t W,
                     uint32_t C, uint32_t n, uint32_t r, uint32_t j,
                     const uint8_t *ks)
 {
-    uint64_t row = (uint64_t)W * C;
-    for (uint32_t i = 0; i < n; i++) {
-        uint64_t lo = oracle_band_lo(H, n, i) * row;
-        uint64_t hi = oracle_band_lo(H, n, i + 1) * row;
-        uint64_t S = hi - lo;
-        uint64_t next_hi = oracle_band_lo(H, n, (i + 1) % n + 1) * row;
-        const uint8_t *b = ks + (uint64_t)r * lo + (uint64_t)j * S;
-        uint8_t prev = Y[next_hi - 1]; /* s_d */
-        for (uint64_t k = 0; k < S; k++) {
-            uint8_t sum = (uint8_t)(Y[lo + k] + b[k]);
-            Z[lo + k] = (uint8_t)(b[k] ^ sum ^ prev);
-            prev = Z[lo + k];
-        }
-    }
+    for (uint32_t i = 0; i < n; i++)
+        oracle_diffuse_band(Y, Z, H, W, C, n, r, j, ks, i);
 }
 
 /* Eq. (4): P = (b xor C xor C_prev) - b.  The seed of band i is recovered

@@ -7,7 +7,7 @@
 namespace cv {
 
 // Geometry of one video stream.  Band (subframe) i covers rows
-// [floor(i*H/n), floor((i+1)*H/n)) -- Algorithm 2's startRow/endRow,
+// [floor(i*H/n), floor((i+1)*H/n)) -- Algorithm 2's band bounds,
 // extended with floor so every row is covered when n does not divide H.
 struct Geom {
   uint32_t H, W, C, n, r;

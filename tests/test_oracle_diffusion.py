@@ -12,7 +12,7 @@ def _ints(tokens):
 
 def _band_bounds(orc, H, W, C, n):
     """Byte ranges of the n bands, from the definition of the split
-    (Algorithm 2, startRow = i*H/n, extended as floor(i*H/n) so that every
+    (Algorithm 2's band bounds i*H/n, extended as floor(i*H/n) so that every
     row is covered when n does not divide H), not from the oracle."""
     row = W * C
     return [((i * H // n) * row, ((i + 1) * H // n) * row) for i in range(n)]

@@ -133,8 +133,9 @@ def test_byte_generator_general_p(orc):
 
 
 def test_keystream_layout_and_continuation(orc):
-    """Per frame, band i gets r*S_i bytes (Algorithm 2: 'generate enough
-    iteration results'), bands in order; the chains carry across frames."""
+    """Per frame, band i gets r*S_i bytes (Algorithm 2 iterates each band's
+    generator until its bytes for the frame exist), bands in order; the
+    chains carry across frames."""
     from paper_2302_07411_amd.inputs import plcm_key
     H, W, C, n, r = 10, 6, 3, 3, 2          # bands of 3, 3, 4 rows
     pm = plcm_key(n, 77)
