@@ -40,7 +40,10 @@ Three more workloads are reported beside it:
   `served`: 256 live streams, Poisson arrivals at 24 frames/s each,
   480^2 ... 3840x2160, 20% decrypting, through the serving loop for
   --serve-seconds of wall time; per-frame latency from arrival to
-  completion, p50/p99 against the 41.7 ms deadline.
+  completion, p50/p99 against the 41.7 ms deadline; then the same streams
+  at 1.25x, 1.5x, ... the rate (--serve-capacity-seconds each) until p99
+  passes the deadline or the served rate falls behind the offered one
+  (`capacity`).
 
     python bench.py [--steps K] [--warmup W] [--batch B] [--cpu-frames N]
                     [--no-batched] [--no-served] [--serve-seconds S]
@@ -370,45 +373,55 @@ def bench_served(B, torch, np, args):
     sample = list(range(0, N, 20))  # about 5% of the streams: their first frame vs the oracle
     first = {i: torch.empty(specs[i][0] * specs[i][1] * 3, dtype=torch.uint8, device=dev)
              for i in sample}
-    seeds = [confusion_seeds(int(RATE * secs * 3) + 64, 9700 + i) for i in range(N)]
-    arrivals = poisson_arrivals(N, RATE, secs, 5006)
+    cap_factors = [f for f in (1.25, 1.5, 1.75, 2.0, 2.5, 3.0, 4.0) if args.serve_capacity_seconds > 0]
+    per_stream_max = RATE * secs * 3 + sum(RATE * f * args.serve_capacity_seconds * 3 for f in cap_factors)
+    seeds = [confusion_seeds(int(per_stream_max) + 64, 9700 + i) for i in range(N)]
     torch.cuda.synchronize()
     time.sleep(0.5)  # let the keystream rings fill
     nxt = [0] * N
-    tickets = []  # (stream, ticket, arrival, submit delay)
-    backlog = []
-    t0 = time.perf_counter()
-    k = 0
-    deferred = 0
-    while k < len(arrivals) or backlog:
-        now = time.perf_counter() - t0
-        while k < len(arrivals) and arrivals[k][0] <= now:
-            backlog.append(arrivals[k])
-            k += 1
-        keep = []
-        for (ta, i) in backlog:
-            t = nxt[i]
-            h, w, c, n, dec = specs[i]
-            src = cipher[(h, w)] if dec else plain[(h, w)]
-            out = first[i] if (t == 0 and i in first) else outs[i][t % Q]
-            tk = streams[i].try_submit(src, out, int(seeds[i][t]))
-            if tk is None:
-                keep.append((ta, i))
-                deferred += 1
-                continue
-            tickets.append((i, tk, ta, (time.perf_counter() - t0) - ta))
-            nxt[i] += 1
-        backlog = keep
-        if k < len(arrivals):
-            time.sleep(max(0.0, min(0.0005, arrivals[k][0] - (time.perf_counter() - t0))))
-        elif backlog:
-            time.sleep(0.0002)
-    srv.drain()
-    wall = time.perf_counter() - t0
-    lat = []
-    for i, tk, ta, delay in tickets:
-        done, l = streams[i].poll(tk)
-        lat.append(l + delay * 1e3)
+
+    def serve(rate, seconds, seed):
+        """Poisson arrivals at `rate` frames/s per stream for `seconds`;
+        every frame submitted when it arrives (or, with its stream's queue
+        full, as soon as a slot frees).  Latency = arrival to completion."""
+        arrivals = poisson_arrivals(N, rate, seconds, seed)
+        tickets = []  # (stream, ticket, arrival, submit delay)
+        backlog = []
+        t0 = time.perf_counter()
+        k = 0
+        deferred = 0
+        while k < len(arrivals) or backlog:
+            now = time.perf_counter() - t0
+            while k < len(arrivals) and arrivals[k][0] <= now:
+                backlog.append(arrivals[k])
+                k += 1
+            keep = []
+            for (ta, i) in backlog:
+                t = nxt[i]
+                h, w, c, n, dec = specs[i]
+                src = cipher[(h, w)] if dec else plain[(h, w)]
+                out = first[i] if (t == 0 and i in first) else outs[i][t % Q]
+                tk = streams[i].try_submit(src, out, int(seeds[i][t]))
+                if tk is None:
+                    keep.append((ta, i))
+                    deferred += 1
+                    continue
+                tickets.append((i, tk, ta, (time.perf_counter() - t0) - ta))
+                nxt[i] += 1
+            backlog = keep
+            if k < len(arrivals):
+                time.sleep(max(0.0, min(0.0005, arrivals[k][0] - (time.perf_counter() - t0))))
+            elif backlog:
+                time.sleep(0.0002)
+        srv.drain()
+        wall = time.perf_counter() - t0
+        lat = []
+        for i, tk, ta, delay in tickets:
+            done, l = streams[i].poll(tk)
+            lat.append(l + delay * 1e3)
+        return tickets, lat, wall, deferred, len(arrivals)
+
+    tickets, lat, wall, deferred, n_arrivals = serve(RATE, secs, 5006)
     stats = srv.stats()
     mism = 0
     t_or = time.perf_counter()
@@ -436,6 +449,24 @@ def bench_served(B, torch, np, args):
         late_mism += int(np.count_nonzero(got != want))
     mism += late_mism
     oracle_s = time.perf_counter() - t_or
+    # capacity at the real-time bound: the same streams at 1.5x, 2x, ... the
+    # rate, a short run each, until p99 exceeds the deadline or the served
+    # rate falls behind the offered one
+    capacity = []
+    for f in cap_factors:
+        tk_c, lat_c, wall_c, _, n_c = serve(RATE * f, args.serve_capacity_seconds, 5100 + int(10 * f))
+        lc = np.asarray(lat_c)
+        row = {"fps_per_stream": RATE * f, "offered_frames_per_s": n_c / args.serve_capacity_seconds,
+               "frames_per_s": len(tk_c) / wall_c, "latency_ms_p50": pct(lat_c, 50),
+               "latency_ms_p99": pct(lat_c, 99), "over_deadline": float(np.mean(lc > DEADLINE_MS))}
+        row["meets_deadline"] = bool(row["latency_ms_p99"] is not None and row["latency_ms_p99"] <= DEADLINE_MS
+                                     and row["frames_per_s"] >= 0.97 * row["offered_frames_per_s"])
+        capacity.append(row)
+        print(f"[bench] served capacity: {RATE * f:g} frames/s per stream, p99 "
+              f"{row['latency_ms_p99']:.1f} ms", file=sys.stderr, flush=True)
+        if not row["meets_deadline"]:
+            break
+    passing = [c for c in capacity if c["meets_deadline"]]
     # admission by device-memory budget: further 3840x2160 streams until the
     # server refuses one (after the measurement, so they do not disturb it)
     n4k = next((sp[3] for sp in specs if sp[:2] == (2160, 3840)), 32)
@@ -457,7 +488,7 @@ def bench_served(B, torch, np, args):
                     "{480^2, 576^2, 768^2, 1280x720, 1920x1080, 3840x2160}x3, n = smallest of "
                     "8/16/32/64 with bands <= 800 KB, 20% decrypting",
         "seconds": secs, "frames": len(tickets), "frames_per_s": len(tickets) / wall,
-        "offered_frames_per_s": len(arrivals) / secs,
+        "offered_frames_per_s": n_arrivals / secs,
         "latency_ms_p50": pct(lat, 50), "latency_ms_p99": pct(lat, 99),
         "latency_ms_max": float(lat_np.max()) if len(lat) else None,
         "over_deadline": float(np.mean(lat_np > DEADLINE_MS)) if len(lat) else None,
@@ -474,6 +505,13 @@ def bench_served(B, torch, np, args):
                                       for i in late],
         "oracle_last_frame_mismatched_bytes": late_mism,
         "oracle_sample_s": oracle_s,
+        "capacity": {"runs": capacity, "seconds_per_run": args.serve_capacity_seconds,
+                     "max_fps_per_stream_meeting_deadline":
+                         max([RATE] + [c["fps_per_stream"] for c in passing]) if capacity else None,
+                     "max_frames_per_s_meeting_deadline":
+                         max([len(tickets) / wall] + [c["frames_per_s"] for c in passing])
+                         if capacity else None,
+                     "rule": "p99 <= 41.7 ms and served >= 97% of offered"},
         "admission": {"workload_streams_admitted": N, "extra_3840x2160_admitted": extra,
                       "refused_next": refused, "hbm_budget_gb": adm["hbm_budget"] / 1e9,
                       "hbm_used_gb": adm["hbm_used"] / 1e9},
@@ -771,6 +809,8 @@ def main():
     ap.add_argument("--video480-frames", type=int, default=240,
                     help="frames of the 480x480x3 per-frame workload (0 = skip)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-capacity-seconds", type=float, default=3.0,
+                    help="seconds per run of the served capacity sweep (0 = skip)")
     ap.add_argument("--serve-ring", type=int, default=8,
                     help="keystream frames generated ahead per served stream")
     ap.add_argument("--serve-shared-cus", action="store_true",
