@@ -396,6 +396,18 @@ typedef struct {
                            unchanged; 0: launch kernel by kernel */
   uint32_t tile_rows_max; /* frame rows per LDS tile at most (the LDS tiling); 0 = as many
                            as fit */
+  uint32_t prefetch;    /* 1: once a tick's keystream is generated, generate the next tick's
+                           -- the same keys and frame counts, one tick on -- on a private
+                           stream while this tick's rounds run (on compute units the rounds
+                           leave free for it when the device is still busy with earlier
+                           ticks), from a copy of the keys' generator states made
+                           on the tick's stream (the keystream depends only on them,
+                           Algorithm 2).  The next cv_batch_run takes it when its batched
+                           items are the same keys (any order) at the frame index and frame
+                           count predicted, copying the advanced states into the keys on its
+                           stream; otherwise it generates its own keystream and the
+                           prefetched work is dropped.  The private stream never touches a
+                           key.  Ticks then go kernel by kernel, without graphs.  0: off */
 } cv_batch_shape;
 
 /* Counters of a batch object (host-side, no synchronisation). */
@@ -409,11 +421,14 @@ typedef struct {
   uint32_t last_fallback_items; /* items of the last tick that ran on their key's own path */
   uint32_t tune_cache_hits;     /* cv_batch_autotune calls answered from CV_TUNE_CACHE */
   uint32_t tune_shapes_timed;   /* launch shapes the autotuner timed */
+  uint32_t prefetch_hits;       /* ticks that took a prefetched keystream */
+  uint32_t prefetch_misses;     /* prefetched keystreams dropped (the next tick differed) */
 } cv_batch_info;
 
 /* Create a batch object on HIP device `device` (the keys of its items must
- * live there).  Default shape: 1024 threads, G = 16, resident capacity,
- * graphs on.  Errors: CV_E_INVAL (NULL, no such device), CV_E_NOMEM. */
+ * live there).  Default shape: 1024 threads, G = 8, resident capacity,
+ * graphs on, largest tiles, prefetch on.  Errors: CV_E_INVAL (NULL, no such
+ * device), CV_E_NOMEM. */
 cv_status cv_batch_create(int device, cv_batch **out);
 
 /* Release a batch object (synchronises its device).  NULL is ignored.  The
@@ -422,7 +437,8 @@ void cv_batch_free(cv_batch *batch);
 
 cv_status cv_batch_get_shape(const cv_batch *batch, cv_batch_shape *shape);
 
-/* CV_E_INVAL if threads or group_wgs is out of range or use_graph > 1. */
+/* CV_E_INVAL if threads or group_wgs is out of range or use_graph or
+ * prefetch > 1. */
 cv_status cv_batch_set_shape(cv_batch *batch, const cv_batch_shape *shape);
 
 /* Encrypt or decrypt one tick: every item's n_frames frames, with keystream

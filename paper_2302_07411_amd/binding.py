@@ -64,7 +64,7 @@ class CvBatchItem(ct.Structure):
 class CvBatchShape(ct.Structure):
     _fields_ = [("threads", ct.c_uint32), ("group_wgs", ct.c_uint32),
                 ("max_groups", ct.c_uint32), ("use_graph", ct.c_uint32),
-                ("tile_rows_max", ct.c_uint32)]
+                ("tile_rows_max", ct.c_uint32), ("prefetch", ct.c_uint32)]
 
 
 class CvBatchInfo(ct.Structure):
@@ -72,7 +72,8 @@ class CvBatchInfo(ct.Structure):
                 ("graph_replays", ct.c_uint64), ("last_jobs", ct.c_uint32),
                 ("last_groups", ct.c_uint32), ("last_chains", ct.c_uint32),
                 ("last_fallback_items", ct.c_uint32), ("tune_cache_hits", ct.c_uint32),
-                ("tune_shapes_timed", ct.c_uint32)]
+                ("tune_shapes_timed", ct.c_uint32), ("prefetch_hits", ct.c_uint32),
+                ("prefetch_misses", ct.c_uint32)]
 
 
 class CvServerStats(ct.Structure):

@@ -14,6 +14,7 @@
 #include <cmath>
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -708,7 +709,9 @@ cv_status cv_keysetup(const cv_geom* geom, cv_map map, const double* p_m, size_t
   const size_t lds_max = lds_limit(device);
   if (cv::round_lds_bytes(g, 1) > lds_max) return fail(CV_E_INVAL, "row too wide for LDS");
 
+  static std::atomic<uint64_t> serials{0};
   cv_key* k = new cv_key();
+  k->serial = ++serials;
   k->g = g;
   k->map = map;
   k->device = device;
@@ -831,6 +834,7 @@ cv_status cv_key_set_state(cv_key* k, const double* x, size_t n_doubles, uint64_
   if (s != CV_OK) return s;
   CV_HIP(hipMemcpy(k->d_state, x, n_doubles * sizeof(double), hipMemcpyHostToDevice));
   k->frame_index = frame_index;
+  k->state_epoch++;
   if (k->map == CV_MAP_PLCM) {
     bool fast = true;
     for (uint32_t i = 0; i < k->g.n; i++)

@@ -239,7 +239,7 @@ hipError_t launch_batch_rounds(const BatchArgs& a, uint32_t C, uint32_t KQ, bool
 }
 
 uint32_t batch_resident_groups(uint32_t C, uint32_t KQ, bool rows, uint32_t G, uint32_t threads,
-                               size_t lds, int device) {
+                               size_t lds, int device, uint32_t reserve_cus) {
   int per_cu = 0, cus = 0;
   hipError_t e;
   if (rows) {
@@ -250,7 +250,9 @@ uint32_t batch_resident_groups(uint32_t C, uint32_t KQ, bool rows, uint32_t G, u
   }
   if (e != hipSuccess || per_cu <= 0) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
-  const uint32_t per_xcd = (uint32_t)per_cu * (uint32_t)cus / 8;
+  const uint32_t cus_xcd = (uint32_t)cus / 8;
+  uint32_t per_xcd = (uint32_t)per_cu * (cus_xcd > reserve_cus ? cus_xcd - reserve_cus : 0);
+  if (per_xcd < G) per_xcd = (uint32_t)per_cu * cus_xcd;
   return (per_xcd / G) * 8;
 }
 

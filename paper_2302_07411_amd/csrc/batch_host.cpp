@@ -15,6 +15,20 @@
 // with one copy.  When the tick's structure repeats, the whole sequence --
 // copy, keystream launches, rounds launches, error-flag read-back -- is
 // replayed from a HIP graph captured the first time.
+//
+// Keystream prefetch (shape.prefetch): the keystream of a frame depends only
+// on its key's generator state (Algorithm 2), so once a tick's keystream is
+// generated (or adopted), the next tick's -- the same keys and frame counts,
+// one tick on -- is generated on a private stream into the other of two
+// keystream buffers while this tick's rounds run (on compute units that the
+// rounds launches leave free for it when ticks are queued back to back).  It advances a shadow copy of the keys'
+// generator states, made on the tick's stream right after the tick's
+// keystream, so the prefetch never touches a key; a next tick that matches
+// takes the keystream and copies the shadow states into the keys on its own
+// stream, in the same launch that starts the following prefetch's shadow.
+// A run of equal ticks thus costs max(keystream, rounds) per tick instead of
+// their sum.  A tick that does not match generates its own keystream into
+// the buffer the prefetch does not write, and the prefetched work is dropped.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -87,19 +101,59 @@ struct Span {
   uint64_t work;
 };
 
+// The keystream prefetch of one batch.  Generator states advance in one of
+// two shadow buffers, used in turn by successive prefetches; keystream goes
+// to the keystream buffer the tick does not use.
+struct Prefetch {
+  struct Entry {
+    const cv_key* k;
+    uint64_t serial, epoch, frame_index;  // the key as the next tick must find it
+    uint32_t n_frames;
+    uint64_t ks_off;     // its keystream in the prefetch's keystream buffer
+    uint64_t state_off;  // its generator states in the prefetch's shadow buffer (doubles)
+  };
+  hipStream_t s = nullptr;             // private stream (default priority)
+  hipEvent_t ks_ready = nullptr;       // tick's stream: keystream generated or adopted, states copied
+  hipEvent_t done[2] = {};             // per shadow buffer: the last prefetch using it is complete
+  bool used[2] = {};
+  hipEvent_t copied = nullptr;         // the chain-table copy has read h_table
+  bool copy_pending = false;
+  uint8_t* h_table = nullptr;          // pinned chain tables
+  size_t h_cap = 0;
+  uint8_t* d_table = nullptr;
+  size_t d_cap = 0;
+  uint8_t* d_shadow[2] = {};
+  size_t shadow_cap[2] = {};
+  std::vector<Entry> entries;
+  bool valid = false;  // entries describe the last prefetch launched
+  int target = -1;     // keystream buffer of the last prefetch launched (-1: none yet)
+  int shadow = -1;     // its shadow buffer
+};
+
+// The next prefetch, planned before the tick that launches it.
+struct NextPrefetch {
+  std::vector<Prefetch::Entry> entries;
+  std::vector<cv::PlcmChain> chains[cv::kPrbgVariants];
+  std::vector<cv::StateCopy> gather;  // generator states into the shadow buffer
+  int target = 0, shadow = 0;
+  uint64_t steps = 0;
+  uint32_t workgroups = 0;
+};
+
 }  // namespace
 
 struct cv_batch {
   int device = 0;
-  cv_batch_shape shape{1024, 8, 0, 1, 0};
+  cv_batch_shape shape{1024, 8, 0, 1, 0, 1};
   size_t lds_max = 0;
   hipStream_t cap = nullptr;  // private stream that graphs are captured on
   std::array<Slot, 2> slot;
   uint32_t turn = 0;
   uint8_t* d_blob = nullptr;
   size_t blob_cap = 0;
-  uint8_t* d_ks = nullptr;
-  size_t ks_cap = 0;
+  uint8_t* d_ks[2] = {};  // keystream buffers: a tick's and a prefetch's
+  size_t ks_cap[2] = {};
+  Prefetch pf;
   uint8_t* d_scratch = nullptr;
   size_t scratch_cap = 0;
   uint32_t* d_counters = nullptr;
@@ -125,6 +179,8 @@ struct Plan {
   std::vector<cv::BatchJob> jobs[kClasses];  // by job class; ks and gm hold offsets until fill_blob
   std::vector<uint32_t> group_jobs[kClasses], group_off[kClasses];
   std::vector<uint32_t> gm;              // shift tables of every frame job
+  std::vector<cv::StateCopy> copies;     // generator-state copies of the tick's hooks
+  uint32_t reserve_cus = 0;              // compute units per XCD the rounds leave free
   uint64_t scratch_stride = 0;
   uint32_t groups[kClasses] = {};
   bool rows[kClasses] = {};  // the row-run kernel (else the pixel-word one)
@@ -178,6 +234,14 @@ uint64_t job_cost(const cv_key* k, uint32_t G) {
   return (uint64_t)k->g.r * ((k->g.n + G - 1) / G) * k->max_band_rows * k->g.W;
 }
 
+// Longest chains first, so that a wavefront holds chains of similar length.
+void sort_chains(std::vector<cv::PlcmChain> (&chains)[cv::kPrbgVariants]) {
+  for (auto& cs : chains)
+    std::stable_sort(cs.begin(), cs.end(), [](const cv::PlcmChain& x, const cv::PlcmChain& y) {
+      return x.nbytes * x.frames > y.nbytes * y.frames;
+    });
+}
+
 // Tables of one tick: the chains of `cj` and the frame jobs of `fj`.
 cv_status plan_tick(const cv_batch* b, const std::vector<ChainJob>& cj,
                     const std::vector<FrameJob>& fj, Plan& P) {
@@ -193,10 +257,7 @@ cv_status plan_tick(const cv_batch* b, const std::vector<ChainJob>& cj,
     }
     P.steps += prbg_steps(c.k, c.frames);
   }
-  for (auto& cs : P.chains)
-    std::stable_sort(cs.begin(), cs.end(), [](const cv::PlcmChain& x, const cv::PlcmChain& y) {
-      return x.nbytes * x.frames > y.nbytes * y.frames;
-    });
+  sort_chains(P.chains);
   uint64_t gm = 0, pwf_max = 0;
   for (const FrameJob& f : fj) {
     gm += f.k->g.H;
@@ -248,7 +309,7 @@ cv_status plan_tick(const cv_batch* b, const std::vector<ChainJob>& cj,
     P.rows[ci] = rows_ok[ci];
     P.lds[ci] = rows_ok[ci] ? lds_rows[ci] : lds_pw[ci];
     const uint32_t cap = cv::batch_resident_groups(class_C(ci), class_KQ(ci), P.rows[ci], G, threads,
-                                                   P.lds[ci], b->device);
+                                                   P.lds[ci], b->device, P.reserve_cus);
     if (cap == 0) return fail(CV_E_INVAL, "batch launch shape does not fit on the device");
     uint32_t groups = std::min<uint64_t>(cap, P.jobs[ci].size());
     if (b->shape.max_groups) groups = std::min(groups, b->shape.max_groups);
@@ -301,7 +362,8 @@ void drop_graphs(cv_batch* b) {
 
 // Layout of the blob: chains (3 variants), jobs, group tables, shift tables.
 struct Layout {
-  size_t chain_off[cv::kPrbgVariants], job_off[kClasses], gj_off[kClasses], go_off[kClasses], gm_off, bytes;
+  size_t chain_off[cv::kPrbgVariants], job_off[kClasses], gj_off[kClasses], go_off[kClasses], gm_off,
+      copies_off, bytes;
 };
 
 Layout layout(const Plan& P) {
@@ -320,7 +382,9 @@ Layout layout(const Plan& P) {
     o = align_up(o + P.group_off[c].size() * 4, 16);
   }
   L.gm_off = o;
-  L.bytes = align_up(o + P.gm.size() * 4, 256);
+  o = align_up(o + P.gm.size() * 4, 16);
+  L.copies_off = o;
+  L.bytes = align_up(o + P.copies.size() * sizeof(cv::StateCopy), 256);
   return L;
 }
 
@@ -366,6 +430,7 @@ void fill_blob(const cv_batch* b, const Plan& P, const Layout& L, uint8_t* h,
       memcpy(h + L.go_off[c], P.group_off[c].data(), P.group_off[c].size() * 4);
   }
   if (!P.gm.empty()) memcpy(h + L.gm_off, P.gm.data(), P.gm.size() * 4);
+  if (!P.copies.empty()) memcpy(h + L.copies_off, P.copies.data(), P.copies.size() * sizeof(cv::StateCopy));
 }
 
 Signature signature(const cv_batch* b, const Plan& P, const Layout& L, uint8_t* ks_base) {
@@ -428,7 +493,7 @@ cv_status drain(cv_batch* b) {
 // Enqueue the tick (copy, launches, flag read-back) on stream st.  With
 // `timed`, every launch is bracketed by events (not allowed while capturing).
 cv_status enqueue_tick(cv_batch* b, const Plan& P, const Layout& L, const Slot& s, hipStream_t st,
-                       bool timed, uint8_t* ks_base) {
+                       bool timed, uint8_t* ks_base, const TickHooks* hooks = nullptr) {
   CV_HIP(hipMemcpyAsync(b->d_blob, s.h_blob, L.bytes, hipMemcpyHostToDevice, st));
   bool has_chains = false;
   for (const auto& cs : P.chains) has_chains = has_chains || !cs.empty();
@@ -446,6 +511,12 @@ cv_status enqueue_tick(cv_batch* b, const Plan& P, const Layout& L, const Slot& 
       CV_HIP(hipEventRecord(tb, st));
       b->spans.push_back({ta, tb, 0, P.steps});
     }
+  }
+  if (hooks) {
+    for (hipEvent_t e : hooks->waits) CV_HIP(hipStreamWaitEvent(st, e, 0));
+    CV_HIP(cv::launch_copy_states((const cv::StateCopy*)(b->d_blob + L.copies_off),
+                                  (uint32_t)P.copies.size(), st));
+    if (hooks->ks_ready) CV_HIP(hipEventRecord(hooks->ks_ready, st));
   }
   ta = nullptr;
   if (timed && has_jobs && (ta = pooled(b))) CV_HIP(hipEventRecord(ta, st));
@@ -496,7 +567,11 @@ cv_status check_flag(cv_batch* b, bool wait) {
 }
 
 cv_status prepare(cv_batch* b, const std::vector<ChainJob>& cj, const std::vector<FrameJob>& fj,
-                  Plan& P, Layout& L) {
+                  Plan& P, Layout& L, const TickHooks* hooks = nullptr) {
+  if (hooks) {
+    P.copies = hooks->copies;
+    P.reserve_cus = hooks->reserve_cus;
+  }
   cv_status s = plan_tick(b, cj, fj, P);
   if (s != CV_OK) return s;
   L = layout(P);
@@ -599,14 +674,170 @@ void collect(const cv_batch* b, const cv_batch_item* items, size_t n_items,
   }
 }
 
+// Grow keystream buffer `i`; a prefetch that wrote the old buffer is lost.
+cv_status grow_ks(cv_batch* b, int i, uint64_t bytes) {
+  const uint8_t* old = b->d_ks[i];
+  cv_status s = grow(&b->d_ks[i], &b->ks_cap[i], std::max<uint64_t>(bytes, 16), "batch keystream");
+  if (b->d_ks[i] != old && b->pf.target == i) b->pf.valid = false;
+  return s;
+}
+
+cv_status ensure_prefetch(cv_batch* b) {
+  Prefetch& pf = b->pf;
+  if (pf.s) return CV_OK;
+  hipError_t e = hipStreamCreateWithFlags(&pf.s, hipStreamNonBlocking);
+  for (hipEvent_t* ev : {&pf.ks_ready, &pf.done[0], &pf.done[1], &pf.copied})
+    if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+  if (e != hipSuccess) return hip_fail(e, "prefetch stream");
+  return CV_OK;
+}
+
+// Does the tick take the prefetched keystream?  Every batched item's key
+// must be one the prefetch covered, unchanged since (same key object, state
+// not set from outside, same frame index), with the frame count predicted,
+// and no key covered may be missing.  `prev` receives each item's entry.
+bool prefetch_matches(const cv_batch* b, const cv_batch_item* items,
+                      const std::vector<size_t>& eligible, std::vector<const Prefetch::Entry*>* prev) {
+  const Prefetch& pf = b->pf;
+  if (!pf.valid || pf.entries.size() != eligible.size()) return false;
+  std::map<const cv_key*, const Prefetch::Entry*> by_key;
+  for (const Prefetch::Entry& e : pf.entries) by_key[e.k] = &e;
+  prev->clear();
+  for (size_t i : eligible) {
+    const cv_batch_item& it = items[i];
+    const auto f = by_key.find(it.key);
+    if (f == by_key.end()) return false;
+    const Prefetch::Entry& e = *f->second;
+    if (e.serial != it.key->serial || e.epoch != it.key->state_epoch ||
+        e.frame_index != it.key->frame_index || e.n_frames != it.n_frames)
+      return false;
+    prev->push_back(&e);
+  }
+  return true;
+}
+
+// Plan the prefetch that follows this tick: the same items one tick on, into
+// keystream buffer `target`.  Its generator states start as copies made on
+// the tick's stream after the tick's keystream: from the keys, or on a tick
+// that takes a prefetch (`prev`), from that prefetch's shadow states, which
+// the same launch copies into the keys.  False when its memory cannot be had.
+bool plan_prefetch(cv_batch* b, const cv_batch_item* items, const std::vector<size_t>& eligible,
+                   const std::vector<const Prefetch::Entry*>* prev, int target, NextPrefetch& np) {
+  Prefetch& pf = b->pf;
+  np.target = target;
+  np.shadow = pf.shadow == 0 ? 1 : 0;
+  uint64_t ks = 0, states = 0;
+  for (size_t i : eligible) {
+    const cv_batch_item& it = items[i];
+    const cv_key* k = it.key;
+    np.entries.push_back({k, k->serial, k->state_epoch, k->frame_index + it.n_frames, it.n_frames, ks,
+                          states});
+    ks += it.n_frames * (uint64_t)k->g.r * k->F;
+    states += 2ull * k->g.n;
+  }
+  if (grow_ks(b, target, ks) != CV_OK ||
+      grow(&pf.d_shadow[np.shadow], &pf.shadow_cap[np.shadow], std::max<uint64_t>(states * 8, 256),
+           "prefetch states") != CV_OK)
+    return false;
+  double* sh = (double*)pf.d_shadow[np.shadow];
+  const double* from = prev ? (const double*)pf.d_shadow[pf.shadow] : nullptr;
+  for (size_t j = 0; j < np.entries.size(); j++) {
+    const Prefetch::Entry& e = np.entries[j];
+    const cv_key* k = e.k;
+    const uint64_t nd = 2ull * k->g.n;
+    np.gather.push_back({prev ? from + (*prev)[j]->state_off : k->d_state, sh + e.state_off, nd});
+    const int v = prbg_variant(k);
+    for (const cv::PlcmChain& c0 : k->h_chains) {
+      cv::PlcmChain ch = c0;
+      ch.state = sh + e.state_off + (c0.state - k->d_state);
+      ch.out_off = e.ks_off + c0.out_off;
+      ch.frames = e.n_frames;
+      np.chains[v].push_back(ch);
+    }
+    np.steps += prbg_steps(k, e.n_frames);
+  }
+  sort_chains(np.chains);
+  for (int v = 0; v < cv::kPrbgVariants; v++)
+    np.workgroups += cv::prbg_plcm_workgroups((uint32_t)np.chains[v].size(), v);
+  return true;
+}
+
+// Launch the planned prefetch on the prefetch stream: its chain tables go
+// up (after the previous prefetch, which read the same device table), then
+// its keystream launches wait for the tick's stream to have its keystream
+// and the shadow states (pf.ks_ready).
+cv_status launch_prefetch(cv_batch* b, NextPrefetch& np) {
+  Prefetch& pf = b->pf;
+  size_t chain_off[cv::kPrbgVariants], bytes = 0;
+  for (int v = 0; v < cv::kPrbgVariants; v++) {
+    chain_off[v] = bytes;
+    bytes += align_up(np.chains[v].size() * sizeof(cv::PlcmChain), 256);
+  }
+  if (pf.copy_pending) {  // the previous prefetch may still be copying from h_table
+    CV_HIP(hipEventSynchronize(pf.copied));
+    pf.copy_pending = false;
+  }
+  if (pf.h_cap < bytes) {
+    if (pf.h_table) (void)hipHostFree(pf.h_table);
+    pf.h_table = nullptr;
+    pf.h_cap = 0;
+    if (hipHostMalloc(&pf.h_table, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      pf.h_table = nullptr;
+      return CV_OK;  // no prefetch this time
+    }
+    pf.h_cap = bytes;
+  }
+  if (grow(&pf.d_table, &pf.d_cap, bytes, "prefetch tables") != CV_OK) return CV_OK;
+  for (int v = 0; v < cv::kPrbgVariants; v++)
+    if (!np.chains[v].empty())
+      memcpy(pf.h_table + chain_off[v], np.chains[v].data(), np.chains[v].size() * sizeof(cv::PlcmChain));
+  CV_HIP(hipMemcpyAsync(pf.d_table, pf.h_table, bytes, hipMemcpyHostToDevice, pf.s));
+  CV_HIP(hipEventRecord(pf.copied, pf.s));
+  pf.copy_pending = true;
+  CV_HIP(hipStreamWaitEvent(pf.s, pf.ks_ready, 0));
+  hipEvent_t ta = b->profiling ? pooled(b) : nullptr;
+  if (ta) CV_HIP(hipEventRecord(ta, pf.s));
+  for (int v = 0; v < cv::kPrbgVariants; v++)
+    if (!np.chains[v].empty())
+      CV_HIP(cv::launch_prbg_plcm((const cv::PlcmChain*)(pf.d_table + chain_off[v]),
+                                  (uint32_t)np.chains[v].size(), b->d_ks[np.target], 0, v, pf.s));
+  if (ta) {
+    hipEvent_t tb = pooled(b);
+    if (tb) {
+      CV_HIP(hipEventRecord(tb, pf.s));
+      b->spans.push_back({ta, tb, 0, np.steps});
+    } else {
+      b->event_pool.push_back(ta);
+    }
+  }
+  CV_HIP(hipEventRecord(pf.done[np.shadow], pf.s));
+  pf.used[np.shadow] = true;
+  pf.entries = std::move(np.entries);
+  pf.target = np.target;
+  pf.shadow = np.shadow;
+  pf.valid = true;
+  return CV_OK;
+}
+
 cv_status run_tick(cv_batch* b, const cv_batch_item* items, size_t n_items, hipStream_t st) {
   std::vector<ChainJob> cj;
   std::vector<FrameJob> fj;
   std::vector<size_t> fallback, eligible;
   uint64_t ks = 0;
   collect(b, items, n_items, cj, fj, fallback, eligible, ks);
-  cv_status s = grow(&b->d_ks, &b->ks_cap, std::max<uint64_t>(ks, 16), "batch keystream");
+  Prefetch& pf = b->pf;
+  std::vector<const Prefetch::Entry*> prev;
+  const bool hit = prefetch_matches(b, items, eligible, &prev);
+  if (pf.valid) (hit ? b->info.prefetch_hits : b->info.prefetch_misses)++;
+  // keystream buffer: the prefetched one, else one that no prefetch writes
+  const int buf = hit ? pf.target : (pf.target == 0 ? 1 : 0);
+  cv_status s = hit ? CV_OK : grow_ks(b, buf, ks);
   if (s != CV_OK) return s;
+  bool ahead = b->shape.prefetch && !eligible.empty();
+  if (ahead && (s = ensure_prefetch(b)) != CV_OK) return s;
+  NextPrefetch np;
+  ahead = ahead && plan_prefetch(b, items, eligible, hit ? &prev : nullptr, 1 - buf, np);
   if ((s = order_after_last(b, st)) != CV_OK) return s;
   for (size_t i : fallback) {
     const cv_batch_item& it = items[i];
@@ -614,9 +845,42 @@ cv_status run_tick(cv_batch* b, const cv_batch_item* items, size_t n_items, hipS
       return s;
   }
   b->info.last_fallback_items = (uint32_t)fallback.size();
-  if ((s = batch_enqueue(b, cj, fj, b->d_ks, st)) != CV_OK) return s;
+  TickHooks hooks;
+  if (hit) {
+    // the prefetched keystream, laid out item by item in the prefetch's
+    // order; its generator states become the keys' states
+    const double* sh = (const double*)pf.d_shadow[pf.shadow];
+    size_t q = 0;
+    for (size_t j = 0; j < eligible.size(); j++) {
+      const cv_batch_item& it = items[eligible[j]];
+      const uint64_t rF = (uint64_t)it.key->g.r * it.key->F;
+      for (uint32_t t = 0; t < it.n_frames; t++) fj[q++].ks_off = prev[j]->ks_off + t * rF;
+      hooks.copies.push_back({sh + prev[j]->state_off, it.key->d_state, 2ull * it.key->g.n});
+    }
+    hooks.waits.push_back(pf.done[pf.shadow]);
+    cj.clear();
+  }
+  if (ahead) {
+    // the next prefetch's shadow buffer is free once the last prefetch that used it is done
+    if (pf.used[np.shadow]) hooks.waits.push_back(pf.done[np.shadow]);
+    hooks.copies.insert(hooks.copies.end(), np.gather.begin(), np.gather.end());
+    hooks.ks_ready = pf.ks_ready;
+    // while earlier ticks are still running (ticks queued back to back), the
+    // prefetch is on the critical path: the rounds leave it compute units;
+    // after an idle device (ticks that arrive in real time) the rounds take
+    // them all and the prefetch catches up in the idle time after them
+    bool busy = false;
+    if (b->ran) {
+      busy = hipEventQuery(b->done) == hipErrorNotReady;
+      (void)hipGetLastError();
+    }
+    if (busy) hooks.reserve_cus = (np.workgroups + 7) / 8;
+  }
+  pf.valid = false;
+  const bool hooked = hit || ahead;
+  if ((s = batch_enqueue(b, cj, fj, b->d_ks[buf], st, hooked ? &hooks : nullptr)) != CV_OK) return s;
   for (size_t i : eligible) items[i].key->frame_index += items[i].n_frames;
-  return CV_OK;
+  return ahead ? launch_prefetch(b, np) : CV_OK;
 }
 
 }  // namespace
@@ -625,10 +889,10 @@ namespace cv {
 namespace rt {
 
 cv_status batch_enqueue(cv_batch* b, const std::vector<ChainJob>& cj, const std::vector<FrameJob>& fj,
-                        uint8_t* ks_base, hipStream_t st) {
+                        uint8_t* ks_base, hipStream_t st, const TickHooks* hooks) {
   Plan P;
   Layout L;
-  cv_status s = prepare(b, cj, fj, P, L);
+  cv_status s = prepare(b, cj, fj, P, L, hooks);
   if (s != CV_OK) return s;
   b->info.last_jobs = 0;
   b->info.last_groups = 0;
@@ -642,8 +906,8 @@ cv_status batch_enqueue(cv_batch* b, const std::vector<ChainJob>& cj, const std:
   Slot* sp = nullptr;
   if ((s = next_slot(b, L.bytes, &sp)) != CV_OK) return s;
   fill_blob(b, P, L, sp->h_blob, ks_base);
-  if (b->profiling || !b->shape.use_graph)
-    s = enqueue_tick(b, P, L, *sp, st, b->profiling, ks_base);
+  if (b->profiling || !b->shape.use_graph || hooks)
+    s = enqueue_tick(b, P, L, *sp, st, b->profiling, ks_base, hooks);
   else
     s = launch_graph(b, P, L, *sp, ks_base, st);
   if (s != CV_OK) return s;
@@ -671,7 +935,16 @@ void release(cv_batch* b) {
   }
   for (hipEvent_t e : b->event_pool) (void)hipEventDestroy(e);
   if (b->d_blob) (void)hipFree(b->d_blob);
-  if (b->d_ks) (void)hipFree(b->d_ks);
+  for (uint8_t* p : b->d_ks)
+    if (p) (void)hipFree(p);
+  Prefetch& pf = b->pf;
+  if (pf.h_table) (void)hipHostFree(pf.h_table);
+  if (pf.d_table) (void)hipFree(pf.d_table);
+  for (uint8_t* p : pf.d_shadow)
+    if (p) (void)hipFree(p);
+  for (hipEvent_t e : {pf.ks_ready, pf.done[0], pf.done[1], pf.copied})
+    if (e) (void)hipEventDestroy(e);
+  if (pf.s) (void)hipStreamDestroy(pf.s);
   if (b->d_scratch) (void)hipFree(b->d_scratch);
   if (b->d_counters) (void)hipFree(b->d_counters);
   if (b->d_err) (void)hipFree(b->d_err);
@@ -686,6 +959,7 @@ cv_status check_shape(const cv_batch_shape& s) {
     return fail(CV_E_INVAL, "threads must be a multiple of 64 in 256..1024");
   if (s.group_wgs < 1 || s.group_wgs > 64) return fail(CV_E_INVAL, "group_wgs must be in 1..64");
   if (s.use_graph > 1) return fail(CV_E_INVAL, "use_graph must be 0 or 1");
+  if (s.prefetch > 1) return fail(CV_E_INVAL, "prefetch must be 0 or 1");
   return CV_OK;
 }
 
@@ -829,6 +1103,7 @@ cv_status cv_batch_autotune(cv_batch* b, const cv_batch_item* items, size_t n_it
   b->profiling = true;  // time each rounds launch
   cv_batch_shape win = keep;
   double win_ms = -1.0;
+  const int kb = b->pf.target == 0 ? 1 : 0;  // a keystream buffer no prefetch writes
   // candidates: the kernel (512 threads: pixel-word, 1024: row-run), G, the
   // groups in flight (0 = all resident, else half the resident groups) and
   // the LDS tiling (0 = the largest tiles, else half their rows)
@@ -860,8 +1135,7 @@ cv_status cv_batch_autotune(cv_batch* b, const cv_batch_item* items, size_t n_it
             if (rows < 2) continue;
             b->shape.tile_rows_max = rows / 2;
           }
-          if ((s = grow(&b->d_ks, &b->ks_cap, std::max<uint64_t>(ks, 16), "batch keystream")) != CV_OK)
-            break;
+          if ((s = grow_ks(b, kb, ks)) != CV_OK) break;
           Plan P;
           Layout L;
           if ((s = prepare(b, {}, fj, P, L)) != CV_OK) {
@@ -883,10 +1157,10 @@ cv_status cv_batch_autotune(cv_batch* b, const cv_batch_item* items, size_t n_it
           Slot* sp = nullptr;
           if ((s = next_slot(b, L.bytes, &sp)) != CV_OK) break;
           Slot& sl = *sp;
-          fill_blob(b, P, L, sl.h_blob, b->d_ks);
+          fill_blob(b, P, L, sl.h_blob, b->d_ks[kb]);
           if ((s = drain(b)) != CV_OK) break;
           b->prof = cv_profile{};
-          for (int rep = 0; rep < 4 && s == CV_OK; rep++) s = enqueue_tick(b, P, L, sl, st, true, b->d_ks);
+          for (int rep = 0; rep < 4 && s == CV_OK; rep++) s = enqueue_tick(b, P, L, sl, st, true, b->d_ks[kb]);
           if (s != CV_OK) break;
           CV_HIP(hipEventRecord(sl.copied, st));
           sl.pending = true;

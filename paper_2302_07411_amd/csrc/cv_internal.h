@@ -74,6 +74,17 @@ constexpr int kPrbgVariants = 5;
 // (n_frames = 0: every chain generates its own `frames`).
 hipError_t launch_prbg_plcm(const PlcmChain* d_chains, uint32_t n_chains, uint8_t* ks_base,
                             uint32_t n_frames, int variant, hipStream_t s);
+// Workgroups of that launch.
+uint32_t prbg_plcm_workgroups(uint32_t n_chains, int variant);
+
+// Copy of `count` generator-state doubles from src to dst (device memory).
+struct StateCopy {
+  const double* src;
+  double* dst;
+  uint64_t count;
+};
+// One launch over n copies (a workgroup each).
+hipError_t launch_copy_states(const StateCopy* d_copies, uint32_t n, hipStream_t s);
 
 // Conditions under which the reciprocal division is exact for a whole orbit:
 // p >= 2^-64 and the current state x is 0 or >= 2^-800.
@@ -185,8 +196,11 @@ struct BatchArgs {
 // for frame widths that are multiples of 12, else 4).
 hipError_t launch_batch_rounds(const BatchArgs& a, uint32_t C, uint32_t KQ, bool rows,
                                uint32_t threads, size_t lds, hipStream_t s);
+// Groups of G workgroups that fit on the device at once, a multiple of 8
+// (one XCD each); with `reserve_cus`, on all but that many compute units of
+// every XCD, unless fewer than a group's worth would remain.
 uint32_t batch_resident_groups(uint32_t C, uint32_t KQ, bool rows, uint32_t G, uint32_t threads,
-                               size_t lds, int device);
+                               size_t lds, int device, uint32_t reserve_cus = 0);
 // Row-run batch kernel: decryption tile rows for geometry g (0 = does not
 // fit) and the LDS a job needs in either direction.
 uint32_t batch_unskew_tile_rows(const Geom& g, size_t lds_max);

@@ -568,7 +568,24 @@ __global__ __launch_bounds__((2 + kNV) * 64) void prbg_plcm_spec_kernel(
   }
 }
 
+// Generator states moved between a key and a batch's speculative copy of
+// them: workgroup q copies entry q.
+__global__ __launch_bounds__(64) void copy_states_kernel(const StateCopy* c, uint32_t n) {
+  const StateCopy e = c[blockIdx.x];
+  for (uint64_t i = threadIdx.x; i < e.count; i += 64) e.dst[i] = e.src[i];
+}
+
 }  // namespace
+
+hipError_t launch_copy_states(const StateCopy* d_copies, uint32_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_states_kernel, dim3(n), dim3(64), 0, s, d_copies, n);
+  return hipGetLastError();
+}
+
+uint32_t prbg_plcm_workgroups(uint32_t n_chains, int variant) {
+  return variant == PRBG_RECIP_PAIR ? (n_chains + 15) / 16 : (n_chains + 31) / 32;
+}
 
 hipError_t launch_prbg_plcm(const PlcmChain* d_chains, uint32_t n_chains, uint8_t* ks_base,
                             uint32_t n_frames, int variant, hipStream_t s) {

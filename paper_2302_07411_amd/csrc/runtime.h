@@ -19,6 +19,8 @@ struct cv_key {
   int path = CV_PATH_PLAIN;
   uint64_t F = 0;              // bytes per frame
   uint64_t frame_index = 0;    // frames processed so far
+  uint64_t serial = 0;         // unique per key in the process (never reused)
+  uint64_t state_epoch = 0;    // bumped whenever the generator state is set from outside
   std::vector<double> pm;      // the n key records as given
   double* d_state = nullptr;   // 2n: x of map 1, map 2 per band
   bool fast = false;           // every chain qualifies for the reciprocal division
@@ -183,9 +185,21 @@ struct FrameJob {
 };
 // Enqueue keystream generation for `cj` and the rounds of `fj` (whose
 // keystream is generated by this tick or was generated earlier) on st.
-// Every frame job must satisfy pw_eligible for the batch's shape.
+// Every frame job must satisfy pw_eligible for the batch's shape.  With
+// `hooks`, the work is launched kernel by kernel, and the hooks run on st
+// between the keystream launches and the rounds launches, in this order:
+// wait for each of `waits`, one launch of the state copies (sent with the
+// tick's tables), record `ks_ready` (each if present).  The rounds launches
+// then leave `reserve_cus` compute units of every XCD free (when at least a
+// group's worth remain).
+struct TickHooks {
+  std::vector<hipEvent_t> waits;
+  std::vector<cv::StateCopy> copies;
+  hipEvent_t ks_ready = nullptr;
+  uint32_t reserve_cus = 0;
+};
 cv_status batch_enqueue(cv_batch* b, const std::vector<ChainJob>& cj, const std::vector<FrameJob>& fj,
-                        uint8_t* ks_base, hipStream_t st);
+                        uint8_t* ks_base, hipStream_t st, const TickHooks* hooks = nullptr);
 // Autotuner cache (tune_cache.cpp): the integer fields stored for a shape
 // class in the file named by CV_TUNE_CACHE; false when absent (or no file).
 bool tune_lookup(const std::string& key, std::map<std::string, int64_t>* fields);

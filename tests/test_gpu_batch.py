@@ -85,17 +85,18 @@ def _streams(B, specs=STREAMS):
     return [Stream(B, i, s, decrypt=i % 3 == 2) for i, s in enumerate(specs)]
 
 
-@pytest.mark.parametrize("use_graph", [1, 0])
-def test_batch_ticks_match_oracle(B, use_graph):
+@pytest.mark.parametrize("use_graph,prefetch", [(1, 0), (0, 0), (1, 1), (0, 1)])
+def test_batch_ticks_match_oracle(B, use_graph, prefetch):
     """Three ticks of ten streams (mixed sizes, n, frame counts, directions,
     two on their key's own path, one on the IEEE-division generator): every
     tick's bytes equal the oracle's; the structure repeats, so ticks 2 and
-    3 replay the graph captured by tick 1."""
+    3 replay the graph captured by tick 1 -- or, with the keystream
+    prefetch, take the keystream generated behind the tick before."""
     streams = _streams(B)
     b = B.Batch()
-    b.set_shape(use_graph=use_graph)
+    b.set_shape(use_graph=use_graph, prefetch=prefetch)
     for t in range(3):
-        print(f"[case] batch tick {t} use_graph={use_graph}", flush=True)
+        print(f"[case] batch tick {t} use_graph={use_graph} prefetch={prefetch}", flush=True)
         parts = [s.tick(t) for s in streams]
         items = [p[0] for p in parts]
         b.run(items)
@@ -107,10 +108,15 @@ def test_batch_ticks_match_oracle(B, use_graph):
         assert info["last_jobs"] == sum(s.T for s in streams if s.name not in ("b-odd", "b-gray"))
     info = b.info()
     assert info["ticks"] == 3
-    if use_graph:
+    if prefetch:  # ticks go kernel by kernel
+        assert info["graph_captures"] == 0
+        assert info["prefetch_hits"] == 2 and info["prefetch_misses"] == 0
+    elif use_graph:
         assert info["graph_captures"] == 2 and info["graph_replays"] == 1  # two staging slots
     else:
         assert info["graph_captures"] == 0
+    if not prefetch:
+        assert info["prefetch_hits"] == 0 and info["prefetch_misses"] == 0
     for s in streams:
         x, fi = s.key.get_state()
         assert fi == 3 * s.T
@@ -145,6 +151,7 @@ def test_batch_round_trip_and_changing_structure(B):
     advance its key."""
     specs = [s for s in STREAMS if s[3] in (3, 4) and s[2] % 16 == 0]
     b = B.Batch()
+    b.set_shape(prefetch=0)
     enc_keys, dec_keys, data = [], [], []
     for i, (name, H, W, C, n, r, T) in enumerate(specs):
         pm = _pm(i, n, name)
@@ -176,6 +183,100 @@ def test_batch_round_trip_and_changing_structure(B):
     want = ref.encrypt(data[0][0], data[0][1])
     assert np.array_equal(_host(out0, (T, H, W, C)), want)
     assert b.info()["graph_captures"] == 3
+    b.close()
+
+
+def test_batch_prefetch_hits_and_misses(B):
+    """The keystream prefetch is taken only by a tick that it predicted, and
+    every tick matches the oracle either way: same items in another order
+    (taken), a stream switching direction (taken: encryption and decryption
+    use the same keystream), a key used on its own between ticks, a key's
+    state set from outside (even to the value it had), a changed frame count
+    and a dropped stream (all dropped); keys end in the oracle's state."""
+    specs = [s for s in STREAMS if s[3] in (3, 4) and s[2] % 16 == 0][:5]
+    specs.append(STREAMS[7])  # b-odd: on its key's own path, never prefetched
+    streams = _streams(B, specs)
+    b = B.Batch()
+    assert b.get_shape()["prefetch"] == 1
+    hits = misses = 0
+
+    def tick(label, active, taken, T=None, reverse=False):
+        nonlocal hits, misses
+        print(f"[case] batch prefetch {label}", flush=True)
+        parts = []
+        for s in active:
+            if T is not None:
+                s.T = T
+            parts.append(s.tick(100 + len(label)))
+        items = [p[0] for p in parts]
+        order = list(reversed(range(len(items)))) if reverse else list(range(len(items)))
+        b.run([items[j] for j in order])
+        b.sync()
+        _check_tick(items, [p[1] for p in parts], [p[2] for p in parts], label)
+        hits += taken is True
+        misses += taken is False
+        info = b.info()
+        assert (info["prefetch_hits"], info["prefetch_misses"]) == (hits, misses), label
+
+    tick("first", streams, None)
+    tick("reordered", streams, True, reverse=True)
+    streams[1].decrypt = not streams[1].decrypt
+    tick("direction", streams, True)
+    # a key used on its own between ticks
+    s0 = streams[0]
+    f = uniform_frames(s0.H, s0.W, s0.C, 1, 4242)
+    sc = confusion_seeds(1, 4243)
+    want = s0.ref.encrypt(f, sc)
+    src = _dev(f)
+    dst = torch.empty_like(src)
+    s0.key.encrypt(src, dst, sc)
+    assert np.array_equal(_host(dst, want.shape), want)
+    tick("solo use", streams, False)
+    tick("after solo", streams, True)
+    # state set from outside to the value it already had
+    x, fi = streams[2].key.get_state()
+    streams[2].key.set_state(x, fi)
+    tick("state set", streams, False)
+    # state set to other values
+    x, fi = streams[2].key.get_state()
+    xs = np.ascontiguousarray(x * np.array([0.5, 0.25]))
+    streams[2].key.set_state(xs, fi)
+    streams[2].ref.x1 = xs[:, 0].copy()
+    streams[2].ref.x2 = xs[:, 1].copy()
+    tick("state changed", streams, False)
+    tick("frames changed", streams, False, T=1)
+    tick("dropped", streams[1:], False)
+    tick("steady", streams[1:], True)
+    for s in streams:
+        x, _ = s.key.get_state()
+        assert np.array_equal(x[:, 0], s.ref.x1) and np.array_equal(x[:, 1], s.ref.x2), s.name
+    b.close()
+
+
+def test_batch_prefetch_queued_ticks(B):
+    """Ticks enqueued back to back without waiting (the prefetch of one tick
+    running beside the next tick's rounds, and the host ahead of the device),
+    then one wait: every tick's bytes equal the oracle's, every tick after
+    the first takes the prefetch, and the keys end in the oracle's state."""
+    streams = _streams(B)
+    b = B.Batch()
+    runs = []
+    print("[case] batch prefetch queued ticks", flush=True)
+    for t in range(5):
+        parts = [s.tick(t) for s in streams]
+        items = [p[0] for p in parts]
+        b.run(items)
+        runs.append(parts)
+    b.sync()
+    for t, parts in enumerate(runs):
+        _check_tick([p[0] for p in parts], [p[1] for p in parts], [p[2] for p in parts],
+                    f"queued tick {t}")
+    info = b.info()
+    assert info["prefetch_hits"] == 4 and info["prefetch_misses"] == 0
+    for s in streams:
+        x, fi = s.key.get_state()
+        assert fi == 5 * s.T
+        assert np.array_equal(x[:, 0], s.ref.x1) and np.array_equal(x[:, 1], s.ref.x2)
     b.close()
 
 
