@@ -39,7 +39,7 @@ Three more workloads are reported beside it:
   oracle.
   `served`: 256 live streams, Poisson arrivals at 24 frames/s each,
   480^2 ... 3840x2160, 20% decrypting, through the serving loop for
-  --serve-seconds of wall time; per-frame latency from arrival to
+  --serve-seconds (60) of wall time; per-frame latency from arrival to
   completion, p50/p99 against the 41.7 ms deadline; then the same streams
   at 1.25x, 1.5x, ... the rate (--serve-capacity-seconds each) until p99
   passes the deadline or the served rate falls behind the offered one
@@ -429,6 +429,14 @@ def bench_served(B, torch, np, args):
     sample = list(range(0, N, 20))  # about 5% of the streams: their first frame vs the oracle
     first = {i: torch.empty(specs[i][0] * specs[i][1] * 3, dtype=torch.uint8, device=dev)
              for i in sample}
+    # frame LATE_K of one encrypting and one decrypting 480^2 stream (long after
+    # their keystream rings wrapped, in ticks shared with every other stream)
+    # is kept for a check against the oracle run over the stream's frames 0..LATE_K
+    LATE_K = 240
+    late = [next((i for i in range(N) if specs[i][:2] == (480, 480) and specs[i][4] == d), None)
+            for d in (False, True)]
+    late = [i for i in late if i is not None]
+    late_out = {i: torch.empty(480 * 480 * 3, dtype=torch.uint8, device=dev) for i in late}
     cap_factors = [f for f in (1.25, 1.5, 1.75, 2.0, 2.5, 3.0, 4.0) if args.serve_capacity_seconds > 0]
     per_stream_max = RATE * secs * 3 + sum(RATE * f * args.serve_capacity_seconds * 3 for f in cap_factors)
     seeds = [confusion_seeds(int(per_stream_max) + 64, 9700 + i) for i in range(N)]
@@ -456,7 +464,8 @@ def bench_served(B, torch, np, args):
                 t = nxt[i]
                 h, w, c, n, dec = specs[i]
                 src = cipher[(h, w)] if dec else plain[(h, w)]
-                out = first[i] if (t == 0 and i in first) else outs[i][t % Q]
+                out = (first[i] if (t == 0 and i in first) else
+                       late_out[i] if (t == LATE_K and i in late_out) else outs[i][t % Q])
                 tk = streams[i].try_submit(src, out, int(seeds[i][t]))
                 if tk is None:
                     keep.append((ta, i))
@@ -487,21 +496,20 @@ def bench_served(B, torch, np, args):
         ref = oracle.PlcmKey(h, w, c, n, R, pms[i])
         want = (ref.decrypt if dec else ref.encrypt)(src, seeds[i][:1])
         mism += int(np.count_nonzero(first[i].cpu().numpy().reshape(want.shape) != want))
-    # the last frame of one encrypting and one decrypting 480^2 stream (after
-    # their keystream rings wrapped, in ticks shared with every other stream)
-    # against the oracle run over all of the stream's frames
-    late = [next((i for i in range(N) if specs[i][:2] == (480, 480) and specs[i][4] == d
-                  and nxt[i] > 1), None) for d in (False, True)]
-    late = [i for i in late if i is not None]
-    late_mism = 0
+    # frame LATE_K of the late-check streams (or their last frame, on a short
+    # run) against the oracle run over all of the stream's frames up to it
+    late = [i for i in late if nxt[i] > 1]
+    late_t, late_mism = {}, 0
     for i in late:
         h, w, c, n, dec = specs[i]
-        t_last = nxt[i] - 1
+        t_chk = LATE_K if nxt[i] > LATE_K else nxt[i] - 1
+        late_t[i] = t_chk
         src = (cipher if dec else plain)[(h, w)].cpu().numpy().reshape(1, h, w, c)
         ref = oracle.PlcmKey(h, w, c, n, R, pms[i])
-        want = (ref.decrypt if dec else ref.encrypt)(np.repeat(src, t_last + 1, axis=0),
-                                                     seeds[i][:t_last + 1])[-1]
-        got = outs[i][t_last % Q].cpu().numpy().reshape(want.shape)
+        want = (ref.decrypt if dec else ref.encrypt)(np.repeat(src, t_chk + 1, axis=0),
+                                                     seeds[i][:t_chk + 1])[-1]
+        buf = late_out[i] if t_chk == LATE_K else outs[i][t_chk % Q]
+        got = buf.cpu().numpy().reshape(want.shape)
         late_mism += int(np.count_nonzero(got != want))
     mism += late_mism
     oracle_s = time.perf_counter() - t_or
@@ -557,9 +565,9 @@ def bench_served(B, torch, np, args):
         "decrypt_streams": sum(1 for s in specs if s[4]),
         "split_cus": bool(stats["split_cus"]), "ring_frames": args.serve_ring, "queue_frames": Q,
         "oracle_sample_streams": len(sample), "oracle_mismatched_bytes": mism,
-        "oracle_last_frame_streams": [{"stream": i, "frames": nxt[i], "decrypt": specs[i][4]}
-                                      for i in late],
-        "oracle_last_frame_mismatched_bytes": late_mism,
+        "oracle_late_frame_streams": [{"stream": i, "frame": late_t[i], "frames": nxt[i],
+                                       "decrypt": specs[i][4]} for i in late],
+        "oracle_late_frame_mismatched_bytes": late_mism,
         "oracle_sample_s": oracle_s,
         "capacity": {"runs": capacity, "seconds_per_run": args.serve_capacity_seconds,
                      "max_fps_per_stream_meeting_deadline":
@@ -866,7 +874,7 @@ def main():
     ap.add_argument("--lasm-frames", type=int, default=13)
     ap.add_argument("--video480-frames", type=int, default=240,
                     help="frames of the 480x480x3 per-frame workload (0 = skip)")
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-capacity-seconds", type=float, default=3.0,
                     help="seconds per run of the served capacity sweep (0 = skip)")
     ap.add_argument("--serve-ring", type=int, default=8,

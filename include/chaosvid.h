@@ -389,8 +389,14 @@ typedef struct {
                            whole source-row runs, decryption in one pass per tile) when
                            every one of them has tiles that fit the LDS; otherwise, and
                            with fewer threads, on the pixel-word kernel */
-  uint32_t group_wgs;   /* G, workgroups per frame job: 1..64 */
-  uint32_t max_groups;  /* frame jobs in flight at once; 0 = as many as can be resident */
+  uint32_t group_wgs;   /* G, workgroups per frame job: 1..64.  With max_groups = 0 the
+                           planner may also form larger groups (multiples of G, up to the
+                           workgroups of one XCD) for frames with more than G subframes,
+                           when that shortens the tick by its cost model (rounds x
+                           ceil(n / group size) x band rows x W per job, longest job first
+                           onto the group where it finishes first) */
+  uint32_t max_groups;  /* frame jobs in flight at once, in groups of exactly G; 0 = as many
+                           as can be resident */
   uint32_t use_graph;   /* 1: capture a tick in a HIP graph and replay it while the tick's
                            structure (items' geometries, frame counts and launch sizes) is
                            unchanged; 0: launch kernel by kernel */

@@ -3,11 +3,13 @@
 // Eq. (1)-(4), Algorithm 1's round loop), on gfx950.
 //
 // Work is a list of jobs, one per (stream, frame).  A persistent grid is cut
-// into groups of G workgroups that share an XCD; a group takes its jobs one
-// after the other (the host assigns jobs to groups longest first), and for
-// each job and round its workgroup w handles bands w, w+G, w+2G, ... of that
-// job's frame -- so streams with 8, 16 or 32 subframes run side by side in
-// one grid.  Bands are exchanged through the group's pixel-word scratch with
+// into groups of workgroups that share an XCD (a table gives each workgroup
+// its group, its index w in it and the group's size G; sizes may differ, so
+// that a frame with many subframes can get a larger group); a group takes
+// its jobs one after the other (the host assigns jobs to groups longest
+// first), and for each job and round its workgroup w handles bands w, w+G,
+// w+2G, ... of that job's frame -- so streams with 8, 16 or 32 subframes run
+// side by side in one grid.  Bands are exchanged through the group's pixel-word scratch with
 // the same XCD-local group barrier as the single-stream fused kernel.  Jobs
 // must share C (3 or 4); every frame width is a multiple of 16 and every
 // buffer 16-byte aligned (the host sends other streams down the per-key
@@ -29,9 +31,9 @@ template <uint32_t C>
 __global__ __launch_bounds__(kMaxThreads) void batch_rounds_kernel(BatchArgs A) {
   extern __shared__ __align__(16) uint32_t tile_lds[];
   __shared__ uint32_t scan_sh[kMaxThreads / 64];
-  const uint32_t i = blockIdx.x, xcd = i % 8, idx = i / 8;
-  const uint32_t group = xcd + 8 * (idx / A.G), w = idx % A.G;
-  if (group >= A.groups) return;
+  const uint32_t sl = A.slots[blockIdx.x];
+  if (sl == kIdleSlot) return;
+  const uint32_t group = sl & 0xFFFu, w = (sl >> 12) & 0x3FFu, G = sl >> 22;
   uint32_t* ctr = A.counters + 32 * group;
   check_group_xcc(ctr + 1, A.err);
   uint8_t* buf[2] = {A.scratch + (uint64_t)group * 2 * A.scratch_stride,
@@ -53,7 +55,7 @@ __global__ __launch_bounds__(kMaxThreads) void batch_rounds_kernel(BatchArgs A) 
       v.dst = last ? J.out : buf[s & 1];
       if (!J.decrypt) {
         const uint32_t j = s;
-        for (uint32_t band = w; band < g.n; band += A.G) {
+        for (uint32_t band = w; band < g.n; band += G) {
           const uint32_t lo = (uint32_t)band_lo(g.H, g.n, band), hi = (uint32_t)band_lo(g.H, g.n, band + 1);
           uint32_t carry = first ? enc_seed<C, true>(v, g, band) : enc_seed<C, false>(v, g, band);
           for (uint32_t t0 = lo; t0 < hi; t0 += J.tile_rows) {
@@ -71,7 +73,7 @@ __global__ __launch_bounds__(kMaxThreads) void batch_rounds_kernel(BatchArgs A) 
           if (first) dec_seeds<C, true>(v, g, j, blo, seed);
           else dec_seeds<C, false>(v, g, j, blo, seed);
         }
-        for (uint32_t band = w; band < g.n; band += A.G) {
+        for (uint32_t band = w; band < g.n; band += G) {
           const uint32_t lo = (uint32_t)band_lo(g.H, g.n, band), hi = (uint32_t)band_lo(g.H, g.n, band + 1);
           for (uint32_t t0 = lo; t0 < hi; t0 += J.tile_rows) {
             const uint32_t R = min(J.tile_rows, hi - t0);
@@ -83,7 +85,7 @@ __global__ __launch_bounds__(kMaxThreads) void batch_rounds_kernel(BatchArgs A) 
         }
       }
       nbar++;
-      if (!group_barrier(ctr, nbar * A.G, A.spin_limit, A.err)) return;
+      if (!group_barrier(ctr, nbar * G, A.spin_limit, A.err)) return;
     }
   }
 }
@@ -132,9 +134,9 @@ template <uint32_t C, uint32_t KQ>
 __global__ __launch_bounds__(skew::kThreads) void batch_rows_kernel(BatchArgs A) {
   extern __shared__ __align__(16) uint32_t lds[];
   __shared__ uint32_t wsum[skew::kWaves];
-  const uint32_t i = blockIdx.x, xcd = i % 8, idx = i / 8;
-  const uint32_t group = xcd + 8 * (idx / A.G), w = idx % A.G;
-  if (group >= A.groups) return;
+  const uint32_t sl = A.slots[blockIdx.x];
+  if (sl == kIdleSlot) return;
+  const uint32_t group = sl & 0xFFFu, w = (sl >> 12) & 0x3FFu, G = sl >> 22;
   uint32_t* ctr = A.counters + 32 * group;
   check_group_xcc(ctr + 1, A.err);
   uint8_t* buf[2] = {A.scratch + (uint64_t)group * 2 * A.scratch_stride,
@@ -162,7 +164,7 @@ __global__ __launch_bounds__(skew::kThreads) void batch_rows_kernel(BatchArgs A)
       v.src_last = first ? J.in_last : buf[(s + 1) & 1] + pwf - 4;
       v.dst = last ? J.out : buf[s & 1];
       if (!J.decrypt) {
-        for (uint32_t band = w; band < g.n; band += A.G) {
+        for (uint32_t band = w; band < g.n; band += G) {
           const uint32_t lo = (uint32_t)band_lo(g.H, g.n, band), hi = (uint32_t)band_lo(g.H, g.n, band + 1);
           const int64_t seed_at = (int64_t)enc_seed_index(v, g, band);
           uint32_t carry = 0;
@@ -178,7 +180,7 @@ __global__ __launch_bounds__(skew::kThreads) void batch_rows_kernel(BatchArgs A)
         const uint32_t j = g.r - 1 - s;
         if (first) dec_seeds<C, true>(v, g, j, blo, seed);
         else dec_seeds<C, false>(v, g, j, blo, seed);
-        for (uint32_t band = w; band < g.n; band += A.G) {
+        for (uint32_t band = w; band < g.n; band += G) {
           const uint32_t lo = blo[band], hi = blo[band + 1];
           for (uint32_t t0 = lo; t0 < hi; t0 += J.tile_dec) {
             const uint32_t R = min(J.tile_dec, hi - t0);
@@ -196,7 +198,7 @@ __global__ __launch_bounds__(skew::kThreads) void batch_rows_kernel(BatchArgs A)
         }
       }
       nbar++;
-      if (!group_barrier(ctr, nbar * A.G, A.spin_limit, A.err)) return;
+      if (!group_barrier(ctr, nbar * G, A.spin_limit, A.err)) return;
     }
   }
 }
@@ -220,7 +222,7 @@ static const void* rows_fn(uint32_t C, uint32_t KQ) {
 hipError_t launch_batch_rounds(const BatchArgs& a, uint32_t C, uint32_t KQ, bool rows,
                                uint32_t threads, size_t lds, hipStream_t s) {
   hipLaunchKernelGGL(reset_batch_groups, dim3(1), dim3(256), 0, s, a.counters, a.groups);
-  const uint32_t slots = ((a.groups + 7) / 8) * 8 * a.G;
+  const uint32_t slots = a.n_slots;
   if (rows) {
     const void* fn = rows_fn(C, KQ);
     if (lds > 64 * 1024) {
@@ -238,8 +240,8 @@ hipError_t launch_batch_rounds(const BatchArgs& a, uint32_t C, uint32_t KQ, bool
   return hipGetLastError();
 }
 
-uint32_t batch_resident_groups(uint32_t C, uint32_t KQ, bool rows, uint32_t G, uint32_t threads,
-                               size_t lds, int device, uint32_t reserve_cus) {
+uint32_t batch_resident_slots(uint32_t C, uint32_t KQ, bool rows, uint32_t threads, size_t lds,
+                              int device, uint32_t reserve_cus, uint32_t min_wgs) {
   int per_cu = 0, cus = 0;
   hipError_t e;
   if (rows) {
@@ -252,8 +254,8 @@ uint32_t batch_resident_groups(uint32_t C, uint32_t KQ, bool rows, uint32_t G, u
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
   const uint32_t cus_xcd = (uint32_t)cus / 8;
   uint32_t per_xcd = (uint32_t)per_cu * (cus_xcd > reserve_cus ? cus_xcd - reserve_cus : 0);
-  if (per_xcd < G) per_xcd = (uint32_t)per_cu * cus_xcd;
-  return (per_xcd / G) * 8;
+  if (per_xcd < min_wgs) per_xcd = (uint32_t)per_cu * cus_xcd;
+  return per_xcd;
 }
 
 size_t batch_rows_lds_bytes(const Geom& g, bool decrypt, uint32_t tile_rows) {

@@ -66,10 +66,11 @@ struct Signature {
   uint32_t n_chains[cv::kPrbgVariants] = {};
   size_t chain_off[cv::kPrbgVariants] = {};
   uint32_t groups[kClasses] = {};  // per job class
+  uint32_t n_slots[kClasses] = {};
   uint32_t G = 0, threads = 0, tile_cap = 0;
   bool rows[kClasses] = {};
   size_t lds[kClasses] = {};
-  size_t job_off[kClasses] = {}, gj_off[kClasses] = {}, go_off[kClasses] = {};
+  size_t job_off[kClasses] = {}, gj_off[kClasses] = {}, go_off[kClasses] = {}, sl_off[kClasses] = {};
   uint64_t scratch_stride = 0;
   bool operator==(const Signature& o) const {
     bool eq = blob_bytes == o.blob_bytes && d_blob == o.d_blob && d_ks == o.d_ks &&
@@ -77,9 +78,9 @@ struct Signature {
               threads == o.threads && tile_cap == o.tile_cap && scratch_stride == o.scratch_stride;
     for (int v = 0; v < cv::kPrbgVariants; v++) eq = eq && n_chains[v] == o.n_chains[v] && chain_off[v] == o.chain_off[v];
     for (int c = 0; c < kClasses; c++)
-      eq = eq && groups[c] == o.groups[c] && rows[c] == o.rows[c] && lds[c] == o.lds[c] &&
-           job_off[c] == o.job_off[c] &&
-           gj_off[c] == o.gj_off[c] && go_off[c] == o.go_off[c];
+      eq = eq && groups[c] == o.groups[c] && n_slots[c] == o.n_slots[c] && rows[c] == o.rows[c] &&
+           lds[c] == o.lds[c] && job_off[c] == o.job_off[c] && gj_off[c] == o.gj_off[c] &&
+           go_off[c] == o.go_off[c] && sl_off[c] == o.sl_off[c];
     return eq;
   }
 };
@@ -151,6 +152,7 @@ struct cv_batch {
   uint32_t turn = 0;
   uint8_t* d_blob = nullptr;
   size_t blob_cap = 0;
+  uint32_t reserve_cus = 0;  // compute units per XCD the rounds launches leave to others
   uint8_t* d_ks[2] = {};  // keystream buffers: a tick's and a prefetch's
   size_t ks_cap[2] = {};
   Prefetch pf;
@@ -183,6 +185,7 @@ struct Plan {
   uint32_t reserve_cus = 0;              // compute units per XCD the rounds leave free
   uint64_t scratch_stride = 0;
   uint32_t groups[kClasses] = {};
+  std::vector<uint32_t> slots[kClasses];  // per workgroup of the launch (cv::batch_slot)
   bool rows[kClasses] = {};  // the row-run kernel (else the pixel-word one)
   size_t lds[kClasses] = {};
   uint64_t steps = 0, frame_rounds = 0;
@@ -228,10 +231,62 @@ cv_status check_items(const cv_batch* b, const cv_batch_item* items, size_t n_it
   return CV_OK;
 }
 
-// Work of one job on the critical path of its group: r rounds, each
-// ceil(n/G) bands of at most max_band_rows rows per workgroup.
-uint64_t job_cost(const cv_key* k, uint32_t G) {
-  return (uint64_t)k->g.r * ((k->g.n + G - 1) / G) * k->max_band_rows * k->g.W;
+// A job as the planner sees it: work of one band-round (r rounds of at most
+// max_band_rows rows of W pixels) and its band count.
+struct JobLoad {
+  uint64_t unit;
+  uint32_t n, job;
+  // on the critical path of a group of G: r rounds of ceil(n/G) bands
+  uint64_t cost(uint32_t G) const { return unit * ((n + G - 1) / G); }
+};
+
+// One group of a launch: its XCD, its first slot there and its size.
+struct GroupDesc {
+  uint32_t xcd, first, G;
+};
+
+// Groups of the XCDs' `slots` workgroups each: `nb` groups of size B spread
+// over the XCDs (at most slots/B on one), every other slot in groups of G0;
+// listed XCD by XCD in turn, so that consecutive groups sit on different XCDs.
+std::vector<GroupDesc> partition(uint32_t slots, uint32_t G0, uint32_t nb, uint32_t B) {
+  std::vector<GroupDesc> per[8];
+  for (uint32_t x = 0; x < 8; x++) {
+    uint32_t s = 0;
+    for (uint32_t q = x; q < nb && s + B <= slots; q += 8, s += B) per[x].push_back({x, s, B});
+    for (; s + G0 <= slots; s += G0) per[x].push_back({x, s, G0});
+  }
+  std::vector<GroupDesc> out;
+  for (size_t k = 0;; k++) {
+    const size_t before = out.size();
+    for (uint32_t x = 0; x < 8; x++)
+      if (k < per[x].size()) out.push_back(per[x][k]);
+    if (out.size() == before) break;
+  }
+  return out;
+}
+
+// Longest job first onto the group where it would finish first; returns the
+// largest group load and each job's group in `where`.
+uint64_t place(const std::vector<JobLoad>& order, const std::vector<GroupDesc>& groups,
+               std::vector<uint32_t>* where) {
+  std::vector<uint64_t> load(groups.size(), 0);
+  uint64_t span = 0;
+  if (where) where->assign(order.size(), 0);
+  for (size_t j = 0; j < order.size(); j++) {
+    size_t best = 0;
+    uint64_t best_end = ~0ull;
+    for (size_t q = 0; q < groups.size(); q++) {
+      const uint64_t end = load[q] + order[j].cost(groups[q].G);
+      if (end < best_end) {
+        best_end = end;
+        best = q;
+      }
+    }
+    load[best] = best_end;
+    span = std::max(span, best_end);
+    if (where) (*where)[j] = (uint32_t)best;
+  }
+  return span;
 }
 
 // Longest chains first, so that a wavefront holds chains of similar length.
@@ -266,7 +321,7 @@ cv_status plan_tick(const cv_batch* b, const std::vector<ChainJob>& cj,
   P.scratch_stride = align_up(pwf_max, 256);
   P.gm.resize(gm);
   gm = 0;
-  std::vector<std::pair<uint64_t, uint32_t>> order[kClasses];  // (cost, job) per class
+  std::vector<JobLoad> order[kClasses];  // per class
   // the row-run kernel takes a class's jobs when it takes every one
   bool rows_ok[kClasses];
   for (bool& x : rows_ok) x = threads == 1024;
@@ -298,39 +353,64 @@ cv_status plan_tick(const cv_batch* b, const std::vector<ChainJob>& cj,
     J.tile_rows = tile;
     J.tile_enc = te;
     J.tile_dec = td;
-    order[ci].push_back({job_cost(f.k, G), (uint32_t)P.jobs[ci].size()});
+    order[ci].push_back({(uint64_t)g.r * f.k->max_band_rows * g.W, g.n, (uint32_t)P.jobs[ci].size()});
     P.jobs[ci].push_back(J);
     P.frame_rounds += g.r;
     gm += g.H;
   }
-  // per job class: longest job first onto the least loaded group
+  // per job class: the groups (sizes chosen for the tick's jobs) and the
+  // jobs on them, longest first onto the group where each finishes first
   for (int ci = 0; ci < kClasses; ci++) {
     if (P.jobs[ci].empty()) continue;
     P.rows[ci] = rows_ok[ci];
     P.lds[ci] = rows_ok[ci] ? lds_rows[ci] : lds_pw[ci];
-    const uint32_t cap = cv::batch_resident_groups(class_C(ci), class_KQ(ci), P.rows[ci], G, threads,
-                                                   P.lds[ci], b->device, P.reserve_cus);
-    if (cap == 0) return fail(CV_E_INVAL, "batch launch shape does not fit on the device");
-    uint32_t groups = std::min<uint64_t>(cap, P.jobs[ci].size());
-    if (b->shape.max_groups) groups = std::min(groups, b->shape.max_groups);
-    std::stable_sort(order[ci].begin(), order[ci].end(),
-                     [](const auto& x, const auto& y) { return x.first > y.first; });
-    std::vector<std::vector<uint32_t>> per(groups);
-    std::vector<std::pair<uint64_t, uint32_t>> heap;  // (load, group), min-heap
-    for (uint32_t q = 0; q < groups; q++) heap.push_back({0, q});
-    auto later = [](const auto& x, const auto& y) { return x > y; };
-    for (const auto& o : order[ci]) {
-      std::pop_heap(heap.begin(), heap.end(), later);
-      heap.back().first += o.first;
-      per[heap.back().second].push_back(o.second);
-      std::push_heap(heap.begin(), heap.end(), later);
+    const uint32_t slots = cv::batch_resident_slots(class_C(ci), class_KQ(ci), P.rows[ci], threads,
+                                                    P.lds[ci], b->device, P.reserve_cus, G);
+    if (slots < G) return fail(CV_E_INVAL, "batch launch shape does not fit on the device");
+    std::vector<JobLoad>& ord = order[ci];
+    std::stable_sort(ord.begin(), ord.end(),
+                     [G](const JobLoad& x, const JobLoad& y) { return x.cost(G) > y.cost(G); });
+    std::vector<GroupDesc> groups = partition(slots, G, 0, G);
+    if (b->shape.max_groups) {
+      // fixed shape: groups of G only, at most max_groups of them
+      groups.resize(std::min<size_t>(groups.size(), b->shape.max_groups));
+    } else {
+      // larger groups for jobs with more bands than G, when that shortens the tick
+      uint32_t wide = 0;
+      for (const JobLoad& o : ord) wide += o.n > G;
+      uint64_t best = place(ord, groups, nullptr);
+      for (uint32_t B = 2 * G; B <= slots && wide; B += G) {
+        for (uint32_t nb = 1; nb <= std::min(wide, 8 * (slots / B)); nb++) {
+          std::vector<GroupDesc> cand = partition(slots, G, nb, B);
+          const uint64_t span = place(ord, cand, nullptr);
+          if (span < best) {
+            best = span;
+            groups = std::move(cand);
+          }
+        }
+      }
     }
+    std::vector<uint32_t> where;
+    place(ord, groups, &where);
+    // groups that received jobs, renumbered in order
+    std::vector<std::vector<uint32_t>> per(groups.size());
+    for (size_t q = 0; q < ord.size(); q++) per[where[q]].push_back(ord[q].job);
+    std::vector<uint32_t> id(groups.size(), cv::kIdleSlot);
+    uint32_t used = 0;
     P.group_off[ci].push_back(0);
-    for (auto& v : per) {
-      P.group_jobs[ci].insert(P.group_jobs[ci].end(), v.begin(), v.end());
+    for (size_t q = 0; q < groups.size(); q++) {
+      if (per[q].empty()) continue;
+      id[q] = used++;
+      P.group_jobs[ci].insert(P.group_jobs[ci].end(), per[q].begin(), per[q].end());
       P.group_off[ci].push_back((uint32_t)P.group_jobs[ci].size());
     }
-    P.groups[ci] = groups;
+    P.groups[ci] = used;
+    P.slots[ci].assign(8 * slots, cv::kIdleSlot);
+    for (size_t q = 0; q < groups.size(); q++) {
+      if (id[q] == cv::kIdleSlot) continue;
+      for (uint32_t w = 0; w < groups[q].G; w++)
+        P.slots[ci][8 * (groups[q].first + w) + groups[q].xcd] = cv::batch_slot(id[q], w, groups[q].G);
+    }
   }
   return CV_OK;
 }
@@ -362,8 +442,8 @@ void drop_graphs(cv_batch* b) {
 
 // Layout of the blob: chains (3 variants), jobs, group tables, shift tables.
 struct Layout {
-  size_t chain_off[cv::kPrbgVariants], job_off[kClasses], gj_off[kClasses], go_off[kClasses], gm_off,
-      copies_off, bytes;
+  size_t chain_off[cv::kPrbgVariants], job_off[kClasses], gj_off[kClasses], go_off[kClasses],
+      sl_off[kClasses], gm_off, copies_off, bytes;
 };
 
 Layout layout(const Plan& P) {
@@ -380,6 +460,8 @@ Layout layout(const Plan& P) {
     o = align_up(o + P.group_jobs[c].size() * 4, 16);
     L.go_off[c] = o;
     o = align_up(o + P.group_off[c].size() * 4, 16);
+    L.sl_off[c] = o;
+    o = align_up(o + P.slots[c].size() * 4, 16);
   }
   L.gm_off = o;
   o = align_up(o + P.gm.size() * 4, 16);
@@ -428,6 +510,7 @@ void fill_blob(const cv_batch* b, const Plan& P, const Layout& L, uint8_t* h,
       memcpy(h + L.gj_off[c], P.group_jobs[c].data(), P.group_jobs[c].size() * 4);
     if (!P.group_off[c].empty())
       memcpy(h + L.go_off[c], P.group_off[c].data(), P.group_off[c].size() * 4);
+    if (!P.slots[c].empty()) memcpy(h + L.sl_off[c], P.slots[c].data(), P.slots[c].size() * 4);
   }
   if (!P.gm.empty()) memcpy(h + L.gm_off, P.gm.data(), P.gm.size() * 4);
   if (!P.copies.empty()) memcpy(h + L.copies_off, P.copies.data(), P.copies.size() * sizeof(cv::StateCopy));
@@ -446,6 +529,8 @@ Signature signature(const cv_batch* b, const Plan& P, const Layout& L, uint8_t* 
   }
   for (int c = 0; c < kClasses; c++) {
     s.groups[c] = P.groups[c];
+    s.n_slots[c] = (uint32_t)P.slots[c].size();
+    s.sl_off[c] = L.sl_off[c];
     s.rows[c] = P.rows[c];
     s.lds[c] = P.lds[c];
     s.job_off[c] = L.job_off[c];
@@ -526,11 +611,12 @@ cv_status enqueue_tick(cv_batch* b, const Plan& P, const Layout& L, const Slot& 
     a.jobs = (const cv::BatchJob*)(b->d_blob + L.job_off[c]);
     a.group_jobs = (const uint32_t*)(b->d_blob + L.gj_off[c]);
     a.group_off = (const uint32_t*)(b->d_blob + L.go_off[c]);
+    a.slots = (const uint32_t*)(b->d_blob + L.sl_off[c]);
+    a.n_slots = (uint32_t)P.slots[c].size();
     a.scratch = b->d_scratch;
     a.scratch_stride = P.scratch_stride;
     a.counters = b->d_counters;
     a.err = b->d_err;
-    a.G = b->shape.group_wgs;
     a.groups = P.groups[c];
     a.spin_limit = kSpinLimit;
     CV_HIP(cv::launch_batch_rounds(a, class_C(c), class_KQ(c), P.rows[c], b->shape.threads, P.lds[c], st));
@@ -568,10 +654,8 @@ cv_status check_flag(cv_batch* b, bool wait) {
 
 cv_status prepare(cv_batch* b, const std::vector<ChainJob>& cj, const std::vector<FrameJob>& fj,
                   Plan& P, Layout& L, const TickHooks* hooks = nullptr) {
-  if (hooks) {
-    P.copies = hooks->copies;
-    P.reserve_cus = hooks->reserve_cus;
-  }
+  if (hooks) P.copies = hooks->copies;
+  P.reserve_cus = std::max(b->reserve_cus, hooks ? hooks->reserve_cus : 0u);
   cv_status s = plan_tick(b, cj, fj, P);
   if (s != CV_OK) return s;
   L = layout(P);
@@ -917,6 +1001,8 @@ cv_status batch_enqueue(cv_batch* b, const std::vector<ChainJob>& cj, const std:
 }
 
 bool batch_flag_set(const cv_batch* b) { return b->failed || *b->h_err != 0; }
+
+void batch_set_reserve(cv_batch* b, uint32_t cus_per_xcd) { b->reserve_cus = cus_per_xcd; }
 
 }  // namespace rt
 }  // namespace cv

@@ -179,15 +179,24 @@ struct BatchJob {
   uint32_t tile_dec;        // row-run kernel: decryption tile rows (batch_unskew_tile_rows)
 };
 
+// Workgroup slot of a batch launch: group | member << 12 | group size << 22
+// (groups < 4096, sizes < 1024); kIdleSlot for a workgroup without a group.
+// Workgroup i runs on XCD i % 8, so a group's slots all have one i % 8.
+constexpr uint32_t kIdleSlot = 0xFFFFFFFFu;
+__host__ __device__ inline uint32_t batch_slot(uint32_t group, uint32_t w, uint32_t G) {
+  return group | (w << 12) | (G << 22);
+}
+
 struct BatchArgs {
   const BatchJob* jobs;
   const uint32_t* group_jobs;  // job indices, group after group
   const uint32_t* group_off;   // groups + 1 offsets into group_jobs
+  const uint32_t* slots;       // n_slots entries, one per workgroup (batch_slot)
   uint8_t* scratch;            // per group two pixel-word frames of scratch_stride bytes
   uint64_t scratch_stride;
   uint32_t* counters;          // 128 bytes per group
   uint32_t* err;
-  uint32_t G, groups, spin_limit;
+  uint32_t n_slots, groups, spin_limit;
 };
 
 // rows = true: the row-run kernel (1024 threads; every job with tile_enc,
@@ -196,11 +205,11 @@ struct BatchArgs {
 // for frame widths that are multiples of 12, else 4).
 hipError_t launch_batch_rounds(const BatchArgs& a, uint32_t C, uint32_t KQ, bool rows,
                                uint32_t threads, size_t lds, hipStream_t s);
-// Groups of G workgroups that fit on the device at once, a multiple of 8
-// (one XCD each); with `reserve_cus`, on all but that many compute units of
-// every XCD, unless fewer than a group's worth would remain.
-uint32_t batch_resident_groups(uint32_t C, uint32_t KQ, bool rows, uint32_t G, uint32_t threads,
-                               size_t lds, int device, uint32_t reserve_cus = 0);
+// Workgroups per XCD that fit on the device at once; with `reserve_cus`, on
+// all but that many compute units of every XCD, unless fewer than `min_wgs`
+// would remain.
+uint32_t batch_resident_slots(uint32_t C, uint32_t KQ, bool rows, uint32_t threads, size_t lds,
+                              int device, uint32_t reserve_cus = 0, uint32_t min_wgs = 1);
 // Row-run batch kernel: decryption tile rows for geometry g (0 = does not
 // fit) and the LDS a job needs in either direction.
 uint32_t batch_unskew_tile_rows(const Geom& g, size_t lds_max);

@@ -200,6 +200,9 @@ struct TickHooks {
 };
 cv_status batch_enqueue(cv_batch* b, const std::vector<ChainJob>& cj, const std::vector<FrameJob>& fj,
                         uint8_t* ks_base, hipStream_t st, const TickHooks* hooks = nullptr);
+// Compute units of every XCD that the batch's rounds launches leave free
+// (for work on other streams restricted to them).
+void batch_set_reserve(cv_batch* b, uint32_t cus_per_xcd);
 // Autotuner cache (tune_cache.cpp): the integer fields stored for a shape
 // class in the file named by CV_TUNE_CACHE; false when absent (or no file).
 bool tune_lookup(const std::string& key, std::map<std::string, int64_t>* fields);

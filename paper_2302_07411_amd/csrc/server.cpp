@@ -284,9 +284,6 @@ hipError_t make_streams(cv_server* S, bool split) {
       if (S->s_rounds) (void)hipStreamDestroy(S->s_rounds);
       S->s_ks = S->s_rounds = nullptr;
       S->split = false;
-    } else {
-      // one 1024-thread workgroup per CU: groups of 8 on the rounds CUs of each XCD
-      shape.max_groups = 8 * ((uint32_t)(cus * 3 / 4) / 8 / shape.group_wgs);
     }
   }
   if (!S->split) {
@@ -295,6 +292,8 @@ hipError_t make_streams(cv_server* S, bool split) {
   }
   (void)cv_batch_set_shape(S->rb, &shape);
   (void)cv_batch_set_shape(S->kb, &shape);
+  // with the split, the rounds launches are sized for the CUs their stream may use
+  batch_set_reserve(S->rb, S->split ? (uint32_t)cus / 32 : 0);
   return e;
 }
 
