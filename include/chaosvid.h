@@ -429,6 +429,7 @@ typedef struct {
   uint32_t tune_shapes_timed;   /* launch shapes the autotuner timed */
   uint32_t prefetch_hits;       /* ticks that took a prefetched keystream */
   uint32_t prefetch_misses;     /* prefetched keystreams dropped (the next tick differed) */
+  uint32_t last_wide_groups;    /* groups of the last tick larger than group_wgs */
 } cv_batch_info;
 
 /* Create a batch object on HIP device `device` (the keys of its items must

@@ -73,7 +73,7 @@ class CvBatchInfo(ct.Structure):
                 ("last_groups", ct.c_uint32), ("last_chains", ct.c_uint32),
                 ("last_fallback_items", ct.c_uint32), ("tune_cache_hits", ct.c_uint32),
                 ("tune_shapes_timed", ct.c_uint32), ("prefetch_hits", ct.c_uint32),
-                ("prefetch_misses", ct.c_uint32)]
+                ("prefetch_misses", ct.c_uint32), ("last_wide_groups", ct.c_uint32)]
 
 
 class CvServerStats(ct.Structure):

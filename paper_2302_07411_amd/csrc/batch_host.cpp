@@ -185,6 +185,7 @@ struct Plan {
   uint32_t reserve_cus = 0;              // compute units per XCD the rounds leave free
   uint64_t scratch_stride = 0;
   uint32_t groups[kClasses] = {};
+  uint32_t wide[kClasses] = {};           // groups larger than the shape's G
   std::vector<uint32_t> slots[kClasses];  // per workgroup of the launch (cv::batch_slot)
   bool rows[kClasses] = {};  // the row-run kernel (else the pixel-word one)
   size_t lds[kClasses] = {};
@@ -401,6 +402,7 @@ cv_status plan_tick(const cv_batch* b, const std::vector<ChainJob>& cj,
     for (size_t q = 0; q < groups.size(); q++) {
       if (per[q].empty()) continue;
       id[q] = used++;
+      P.wide[ci] += groups[q].G > G;
       P.group_jobs[ci].insert(P.group_jobs[ci].end(), per[q].begin(), per[q].end());
       P.group_off[ci].push_back((uint32_t)P.group_jobs[ci].size());
     }
@@ -980,9 +982,11 @@ cv_status batch_enqueue(cv_batch* b, const std::vector<ChainJob>& cj, const std:
   if (s != CV_OK) return s;
   b->info.last_jobs = 0;
   b->info.last_groups = 0;
+  b->info.last_wide_groups = 0;
   for (int c = 0; c < kClasses; c++) {
     b->info.last_jobs += (uint32_t)P.jobs[c].size();
     b->info.last_groups += P.groups[c];
+    b->info.last_wide_groups += P.wide[c];
   }
   b->info.last_chains = 0;
   for (const auto& cs : P.chains) b->info.last_chains += (uint32_t)cs.size();

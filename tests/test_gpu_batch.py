@@ -280,6 +280,28 @@ def test_batch_prefetch_queued_ticks(B):
     b.close()
 
 
+@pytest.mark.parametrize("max_groups", [0, 8])
+def test_batch_wide_groups(B, max_groups):
+    """Frames with many subframes next to small ones: the planner gives them
+    groups larger than G (unless max_groups fixes groups of G), and every
+    stream's bytes equal the oracle's either way."""
+    specs = ([("w-n32", 256, 256, 3, 32, 5, 1)] * 6 + [("w-n64", 192, 160, 3, 64, 3, 1)] * 2
+             + [("w-small", 32, 48, 3, 4, 5, 2)] * 12)
+    streams = _streams(B, specs)
+    b = B.Batch()
+    b.set_shape(group_wgs=8, max_groups=max_groups, prefetch=0)
+    for t in range(2):
+        print(f"[case] batch wide groups max_groups={max_groups} tick {t}", flush=True)
+        parts = [s.tick(t) for s in streams]
+        items = [p[0] for p in parts]
+        b.run(items)
+        b.sync()
+        _check_tick(items, [p[1] for p in parts], [p[2] for p in parts], f"wide tick {t}")
+        wide = b.info()["last_wide_groups"]
+        assert (wide > 0) if max_groups == 0 else (wide == 0)
+    b.close()
+
+
 def test_batch_full_size_streams(B):
     """Eight streams at real sizes in one tick -- 768x768x3 with 16
     subframes, 480x480x3 with 8, 1024x1024x3 with 32 -- against solo
