@@ -138,7 +138,17 @@ typedef struct {
                               launches, error read-back), captured the first time a buffer
                               set (in, out, frame count, direction) is seen; up to 16 graphs
                               are kept, the least recently used dropped.  0: every kernel
-                              launched on its own.  Ignored while profiling is on. */
+                              launched on its own.  Ignored while profiling is on, and with
+                              lookahead. */
+  uint32_t lookahead;      /* 1 (PLCM keys; ignored for 2DLASM keys): after each internal
+                              batch of T frames, generate the next T frames' keystream on a
+                              private stream from a copy of the generator states made on the
+                              call's stream (the keystream depends only on them, Algorithm 2),
+                              so that a call arriving later finds it ready and costs only its
+                              rounds.  The next batch takes it when it starts at the predicted
+                              frame with the same T and the state was not set in between;
+                              otherwise it is dropped.  The private stream never touches the
+                              key's state.  Costs two keystream buffers of T frames.  0: off */
 } cv_launch;
 
 /* Version of the cipher readings above (CV_SPEC_VERSION). */
@@ -256,6 +266,11 @@ cv_status cv_key_autotune(cv_key *key, int decrypt, uint32_t n_frames, void *str
 /* Graphs captured and replayed by the key's calls since its set-up
  * (cv_launch.use_graph).  Errors: CV_E_INVAL (NULL). */
 cv_status cv_key_graph_counts(const cv_key *key, uint64_t *captures, uint64_t *replays);
+
+/* Internal batches that took the lookahead's keystream, and lookaheads
+ * dropped because the next batch differed (cv_launch.lookahead).  Errors:
+ * CV_E_INVAL (NULL). */
+cv_status cv_key_lookahead_counts(const cv_key *key, uint64_t *hits, uint64_t *misses);
 
 /* Choose the round implementation (CV_PATH_*).  CV_E_INVAL if unknown. */
 cv_status cv_key_set_path(cv_key *key, int path);

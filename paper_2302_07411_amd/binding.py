@@ -32,7 +32,7 @@ EXPORTS = (
     "cv_server_get_stats", "cv_stream_open", "cv_stream_submit", "cv_stream_poll",
     "cv_stream_close", "cv_cr_sin", "cv_key_schedule", "cv_sin_stage1", "cv_key_sync",
     "cv_key_set_spin_limit", "cv_apply_rounds_noalloc", "cv_key_graph_counts",
-    "cv_key_autotune",
+    "cv_key_autotune", "cv_key_lookahead_counts",
 )
 
 
@@ -46,7 +46,7 @@ class CvLaunch(ct.Structure):
                 ("tile_rows_enc", ct.c_uint32), ("tile_rows_dec", ct.c_uint32),
                 ("prbg_variant", ct.c_uint32), ("round_variant", ct.c_uint32),
                 ("tile_rows_pw", ct.c_uint32), ("fused_groups", ct.c_uint32),
-                ("use_graph", ct.c_uint32)]
+                ("use_graph", ct.c_uint32), ("lookahead", ct.c_uint32)]
 
 
 class CvProfile(ct.Structure):
@@ -128,6 +128,8 @@ def load() -> ct.CDLL:
     L.cv_key_autotune.argtypes = [vp, ct.c_int, ct.c_uint32, vp, ct.POINTER(CvLaunch),
                                   ct.POINTER(ct.c_int)]
     L.cv_key_graph_counts.argtypes = [vp, ct.POINTER(ct.c_uint64), ct.POINTER(ct.c_uint64)]
+    L.cv_key_lookahead_counts.restype = ct.c_int
+    L.cv_key_lookahead_counts.argtypes = [vp, ct.POINTER(ct.c_uint64), ct.POINTER(ct.c_uint64)]
     for name in ("cv_encrypt_frames", "cv_decrypt_frames"):
         f = getattr(L, name)
         f.restype = ct.c_int
@@ -338,6 +340,12 @@ class Key:
         c, r = ct.c_uint64(), ct.c_uint64()
         _check(load().cv_key_graph_counts(self._h, ct.byref(c), ct.byref(r)))
         return c.value, r.value
+
+    def lookahead_counts(self):
+        """(hits, misses) of the key's keystream lookahead (cv_launch.lookahead)."""
+        h, m = ct.c_uint64(), ct.c_uint64()
+        _check(load().cv_key_lookahead_counts(self._h, ct.byref(h), ct.byref(m)))
+        return h.value, m.value
 
     def set_path(self, path: int):
         _check(load().cv_key_set_path(self._h, path))

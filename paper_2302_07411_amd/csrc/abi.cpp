@@ -558,6 +558,96 @@ cv_status crypt_batch_graph(cv_key* k, bool decrypt, const uint8_t* in, uint8_t*
   return CV_OK;
 }
 
+// ------------------------------------------------ keystream lookahead ---
+hipError_t copy_sync(void* dst, const void* src, size_t bytes, hipMemcpyKind kind);
+
+// Stream, events, shadow states and the chain tables that point at them.
+cv_status ensure_ahead(cv_key* k) {
+  cv_key::Ahead& a = k->ahead;
+  if (a.s) return CV_OK;
+  hipError_t e = hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking);
+  for (hipEvent_t* ev : {&a.ks_ready, &a.done[0], &a.done[1]})
+    if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+  const size_t nd = 2ull * k->g.n;
+  for (int i = 0; i < 2 && e == hipSuccess; i++) {
+    e = hipMalloc(&a.d_shadow[i], nd * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&a.d_chains[i], k->h_chains.size() * sizeof(cv::PlcmChain));
+    if (e != hipSuccess) break;
+    std::vector<cv::PlcmChain> ch = k->h_chains;
+    for (cv::PlcmChain& c : ch) c.state = a.d_shadow[i] + (c.state - k->d_state);
+    e = copy_sync(a.d_chains[i], ch.data(), ch.size() * sizeof(cv::PlcmChain), hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(e == hipErrorOutOfMemory ? CV_E_NOMEM : CV_E_HIP, "lookahead set-up failed");
+  }
+  return CV_OK;
+}
+
+// Keystream buffer i of at least `bytes`; a lookahead that wrote the old one is lost.
+cv_status ahead_buffer(cv_key* k, int i, size_t bytes) {
+  cv_key::Ahead& a = k->ahead;
+  if (a.ks_cap[i] >= bytes) return CV_OK;
+  CV_HIP(hipDeviceSynchronize());  // the old buffer may still be in use
+  if (a.d_ks[i]) (void)hipFree(a.d_ks[i]);
+  a.d_ks[i] = nullptr;
+  a.ks_cap[i] = 0;
+  if (a.target == i) a.valid = false;
+  if (hipMalloc(&a.d_ks[i], bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    a.d_ks[i] = nullptr;
+    return fail(CV_E_NOMEM, "lookahead keystream allocation failed");
+  }
+  a.ks_cap[i] = bytes;
+  return CV_OK;
+}
+
+// One internal batch of T frames with the lookahead: the keystream taken
+// from the last lookahead when it predicted this batch (its shadow states
+// become the key's), else generated on st; then the shadow copy for the next
+// batch is made on st, the rounds run on st, and the next batch's keystream
+// is generated on the private stream into the other buffer.
+cv_status crypt_batch_ahead(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
+                            const uint32_t* s_c, uint32_t T, hipStream_t st) {
+  cv_key::Ahead& a = k->ahead;
+  cv_status s = ensure_ahead(k);
+  if (s != CV_OK) return s;
+  const bool hit = a.valid && a.frame_index == k->frame_index && a.T == T && a.epoch == k->state_epoch;
+  if (a.valid) (hit ? k->ahead_hits : k->ahead_misses)++;
+  a.valid = false;
+  const int buf = hit ? a.target : (a.target == 0 ? 1 : 0), nsh = a.shadow == 0 ? 1 : 0;
+  const size_t bytes = (size_t)T * k->g.r * k->F, states = 2ull * k->g.n * sizeof(double);
+  if ((s = ahead_buffer(k, buf, bytes)) != CV_OK) return s;
+  if ((s = ahead_buffer(k, 1 - buf, bytes)) != CV_OK) return s;
+  if ((s = upload_shift_tables(k, s_c, T, st)) != CV_OK) return s;
+  if (hit) {
+    CV_HIP(hipStreamWaitEvent(st, a.done[a.shadow], 0));
+    CV_HIP(hipMemcpyAsync(k->d_state, a.d_shadow[a.shadow], states, hipMemcpyDeviceToDevice, st));
+  } else if ((s = launch_keystream(k, a.d_ks[buf], T, st)) != CV_OK) {
+    return s;
+  }
+  if (a.used[nsh]) CV_HIP(hipStreamWaitEvent(st, a.done[nsh], 0));
+  CV_HIP(hipMemcpyAsync(a.d_shadow[nsh], k->d_state, states, hipMemcpyDeviceToDevice, st));
+  CV_HIP(hipEventRecord(a.ks_ready, st));
+  if ((s = run_rounds(k, decrypt, in, out, a.d_ks[buf], T, st)) != CV_OK) return s;
+  k->frame_index += T;
+  CV_HIP(hipStreamWaitEvent(a.s, a.ks_ready, 0));
+  {
+    Timed tm(k, a.s);
+    CV_HIP(cv::launch_prbg_plcm(a.d_chains[nsh], k->g.n, a.d_ks[1 - buf], T, prbg_variant(k), a.s));
+    tm.end(0, prbg_steps(k, T));
+  }
+  CV_HIP(hipEventRecord(a.done[nsh], a.s));
+  a.used[nsh] = true;
+  a.target = 1 - buf;
+  a.shadow = nsh;
+  a.frame_index = k->frame_index;
+  a.epoch = k->state_epoch;
+  a.T = T;
+  a.valid = true;
+  return CV_OK;
+}
+
 cv_status crypt_frames(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
                        const uint32_t* s_c, size_t n, void* stream) {
   cv_status s = check_frames_args(k, in, out, s_c, n);
@@ -567,9 +657,16 @@ cv_status crypt_frames(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
   hipStream_t st = (hipStream_t)stream;
   const size_t B = std::min<size_t>(n, k->batch_frames);
   if ((s = ensure_workspace(k, B)) != CV_OK) return s;
-  const bool graph = k->use_graph && !k->profiling;
+  const bool ahead = k->lookahead && k->map == CV_MAP_PLCM;
+  const bool graph = k->use_graph && !k->profiling && !ahead;
   for (size_t f0 = 0; f0 < n; f0 += B) {
     const uint32_t T = (uint32_t)std::min(B, n - f0);
+    if (ahead) {
+      if ((s = crypt_batch_ahead(k, decrypt, in + f0 * k->F, out + f0 * k->F, s_c + f0, T, st)) !=
+          CV_OK)
+        return s;
+      continue;  // the batch advanced frame_index
+    }
     if (graph) {
       if ((s = crypt_batch_graph(k, decrypt, in + f0 * k->F, out + f0 * k->F, s_c + f0, T, st)) !=
           CV_OK)
@@ -806,6 +903,15 @@ void cv_key_free(cv_key* k) {
   if (k->d_chains) (void)hipFree(k->d_chains);
   if (k->d_lchains) (void)hipFree(k->d_lchains);
   if (k->gm_done) (void)hipEventDestroy(k->gm_done);
+  cv_key::Ahead& a = k->ahead;
+  for (int i = 0; i < 2; i++) {
+    if (a.d_shadow[i]) (void)hipFree(a.d_shadow[i]);
+    if (a.d_chains[i]) (void)hipFree(a.d_chains[i]);
+    if (a.d_ks[i]) (void)hipFree(a.d_ks[i]);
+    if (a.done[i]) (void)hipEventDestroy(a.done[i]);
+  }
+  if (a.ks_ready) (void)hipEventDestroy(a.ks_ready);
+  if (a.s) (void)hipStreamDestroy(a.s);
   delete k;
 }
 
@@ -875,6 +981,7 @@ cv_status cv_key_get_launch(const cv_key* k, cv_launch* l) {
   l->tile_rows_pw = k->tile_pw;
   l->fused_groups = k->fused_groups;
   l->use_graph = k->use_graph ? 1u : 0u;
+  l->lookahead = k->lookahead ? 1u : 0u;
   return CV_OK;
 }
 
@@ -998,12 +1105,20 @@ cv_status cv_key_graph_counts(const cv_key* k, uint64_t* captures, uint64_t* rep
   return CV_OK;
 }
 
+cv_status cv_key_lookahead_counts(const cv_key* k, uint64_t* hits, uint64_t* misses) {
+  if (!k || !hits || !misses) return fail(CV_E_INVAL, "NULL argument");
+  *hits = k->ahead_hits;
+  *misses = k->ahead_misses;
+  return CV_OK;
+}
+
 cv_status cv_key_set_launch(cv_key* k, const cv_launch* l) {
   if (!k || !l) return fail(CV_E_INVAL, "NULL argument");
   if (l->batch_frames == 0) return fail(CV_E_INVAL, "batch_frames must be >= 1");
   if (l->prbg_variant > 5) return fail(CV_E_INVAL, "prbg_variant must be 0..5");
   if (l->round_variant > 3) return fail(CV_E_INVAL, "round_variant must be 0..3");
   if (l->use_graph > 1) return fail(CV_E_INVAL, "use_graph must be 0 or 1");
+  if (l->lookahead > 1) return fail(CV_E_INVAL, "lookahead must be 0 or 1");
   const uint32_t tp = pw_tile_limit(k->g, l->threads, l->tile_rows_pw);
   if (tp == 0 && (k->g.C == 3 || k->g.C == 4))
     return fail(CV_E_INVAL, "tile_rows_pw must be >= 1 (and the frame not too wide for threads)");
@@ -1025,6 +1140,7 @@ cv_status cv_key_set_launch(cv_key* k, const cv_launch* l) {
   k->round_variant = l->round_variant;
   k->tile_pw = tp;
   k->use_graph = l->use_graph != 0;
+  k->lookahead = l->lookahead != 0;
   drop_graphs(k);
   // the fused workspace depends on the shape: drop it and size it anew
   if (k->d_fscratch) {

@@ -80,6 +80,27 @@ struct cv_key {
   static constexpr size_t kMaxGraphs = 16;
   std::vector<GraphEntry> graphs;
   uint64_t graph_clock = 0, graph_captures = 0, graph_replays = 0;
+  // keystream lookahead (cv_launch.lookahead, PLCM keys): after each batch of
+  // T frames, the next T frames' keystream is generated on a private stream
+  // from a shadow copy of the generator states (two copies and two keystream
+  // buffers, used in turn); the next batch takes it when it starts at the
+  // predicted frame with the same T and the state was not set in between
+  bool lookahead = false;
+  struct Ahead {
+    hipStream_t s = nullptr;           // private stream (default priority)
+    hipEvent_t ks_ready = nullptr;     // call's stream: keystream ready, shadow states copied
+    hipEvent_t done[2] = {};           // per shadow copy: the last lookahead using it is complete
+    bool used[2] = {};
+    double* d_shadow[2] = {};
+    cv::PlcmChain* d_chains[2] = {};   // the key's chains with their states in shadow 0 / 1
+    uint8_t* d_ks[2] = {};
+    size_t ks_cap[2] = {};
+    bool valid = false;                // the fields below describe the last lookahead launched
+    int target = -1, shadow = -1;      // its keystream buffer and shadow copy
+    uint64_t frame_index = 0, epoch = 0;
+    uint32_t T = 0;
+  } ahead;
+  uint64_t ahead_hits = 0, ahead_misses = 0;
   // event profiling
   bool profiling = false;
   struct Span {
