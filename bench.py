@@ -316,6 +316,48 @@ def bench_graph_frames(B, torch, np, src, s_c, pm, path, frames):
     return res
 
 
+def bench_paced_frames(B, torch, np, src, s_c, pm, path, frames):
+    """One 768x768x3 frame per call with the frames arriving at 24 per second
+    (each call made 1/24 s after the previous one), with and without the
+    key's keystream lookahead (cv_launch.lookahead): latency from call to
+    completion.  With the lookahead the next frame's keystream is generated
+    in the idle time between frames, so a call costs its rounds; without it,
+    its keystream and its rounds.  The two keys' outputs must be identical.
+    Calls go to a stream of their own and are waited for on it (the lookahead
+    runs on the key's private stream, which the call does not wait for)."""
+    dev = src.device
+    stream = torch.cuda.Stream()
+    res = {"workload": f"one {H}x{W}x{C} frame per call, {N_SUB} subframes, {R} rounds, "
+                       f"{frames} frames arriving at 24 per second, "
+                       f"{'fused' if path == B.CV_PATH_FUSED else 'plain'} round path"}
+    outs = {}
+    for mode in ("lookahead", "no_lookahead"):
+        k = B.Key(H, W, C, N_SUB, R, pm)
+        k.set_path(path)
+        k.set_launch(lookahead=1 if mode == "lookahead" else 0)
+        out = torch.empty((frames + 1, F), dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        k.encrypt(src[0], out[0], s_c[0:1], stream=stream)  # warm-up: workspace, first lookahead
+        torch.cuda.synchronize()
+        lat, due = [], time.perf_counter()
+        for t in range(1, frames + 1):
+            due += 1.0 / 24
+            while time.perf_counter() < due:
+                time.sleep(0.0005)
+            t0 = time.perf_counter()
+            k.encrypt(src[t], out[t], s_c[t:t + 1], stream=stream)
+            stream.synchronize()
+            lat.append((time.perf_counter() - t0) * 1e3)
+        torch.cuda.synchronize()
+        outs[mode] = out
+        hits, misses = k.lookahead_counts()
+        res[mode] = {"latency_ms_p50": pct(lat, 50), "latency_ms_p99": pct(lat, 99),
+                     "lookahead_hits": hits, "lookahead_misses": misses}
+    res["identical_output"] = bool(torch.equal(outs["lookahead"], outs["no_lookahead"]))
+    res["deadline_ms"] = DEADLINE_MS
+    return res
+
+
 def bench_video480(B, torch, np, args):
     """The 480x480x3 video (240 frames, 8 subframes, 5 rounds, one key) on
     the plain per-frame path: one cv_encrypt_frames call per frame with one
@@ -965,6 +1007,11 @@ def main():
     if args.latency_frames > 0 and total >= 4 + 2 * args.latency_frames:
         print("[bench] per-frame launches vs graph replay", file=sys.stderr, flush=True)
         graph_frames = bench_graph_frames(B, torch, np, src, s_c, pm, path, args.latency_frames)
+    paced_frames = None
+    if args.latency_frames > 0 and total >= 1 + args.latency_frames:
+        print("[bench] per-frame calls at 24 frames/s, keystream lookahead on and off",
+              file=sys.stderr, flush=True)
+        paced_frames = bench_paced_frames(B, torch, np, src, s_c, pm, path, args.latency_frames)
 
     cpu = cpu_baseline(src, dst, s_c, min(args.cpu_frames, total), pm) if args.cpu_frames > 0 else None
 
@@ -1017,7 +1064,12 @@ def main():
         "gb_per_s": fps * (2 + R) * F / 1e9,
         "pixels_per_s": fps * H * W,
         "latency_ms": {"plain_p50": pct(lat, 50), "plain_p99": pct(lat, 99),
-                       "plain": f"one {H}x{W}x{C} frame per call, waited for (call to completion)",
+                       "plain": f"one {H}x{W}x{C} frame per call, waited for (call to completion), "
+                                "calls back to back",
+                       "plain_paced_p50": paced_frames["lookahead"]["latency_ms_p50"] if paced_frames else None,
+                       "plain_paced_p99": paced_frames["lookahead"]["latency_ms_p99"] if paced_frames else None,
+                       "plain_paced": f"one {H}x{W}x{C} frame per call arriving at 24 frames/s, key "
+                                      "keystream lookahead on, call to completion",
                        "batched_p50": None, "batched_p99": None,
                        "batched": "one tick of the 64-stream batched workload (one frame of "
                                   "every stream per tick) arriving at 24 ticks/s, call to "
@@ -1031,6 +1083,7 @@ def main():
         "roofline_prbg": roof_prbg,
         "cpu_baseline": cpu,
         "per_frame_graph": graph_frames,
+        "per_frame_paced": paced_frames,
     }
     bad = cpu is not None and cpu["parity_mismatched_bytes"]
     bad = bad or (graph_frames is not None and not graph_frames["identical_output"])
