@@ -566,7 +566,7 @@ cv_status ensure_ahead(cv_key* k) {
   cv_key::Ahead& a = k->ahead;
   if (a.s) return CV_OK;
   hipError_t e = hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking);
-  for (hipEvent_t* ev : {&a.ks_ready, &a.done[0], &a.done[1]})
+  for (hipEvent_t* ev : {&a.ks_ready, &a.done[0], &a.done[1], &a.last})
     if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
   const size_t nd = 2ull * k->g.n;
   for (int i = 0; i < 2 && e == hipSuccess; i++) {
@@ -619,6 +619,9 @@ cv_status crypt_batch_ahead(cv_key* k, bool decrypt, const uint8_t* in, uint8_t*
   const size_t bytes = (size_t)T * k->g.r * k->F, states = 2ull * k->g.n * sizeof(double);
   if ((s = ahead_buffer(k, buf, bytes)) != CV_OK) return s;
   if ((s = ahead_buffer(k, 1 - buf, bytes)) != CV_OK) return s;
+  // a call on another stream than the last one starts after the last one's
+  // work there (which reads the buffers and shadow copies reused below)
+  if (a.has_last && a.last_stream != st) CV_HIP(hipStreamWaitEvent(st, a.last, 0));
   if ((s = upload_shift_tables(k, s_c, T, st)) != CV_OK) return s;
   if (hit) {
     CV_HIP(hipStreamWaitEvent(st, a.done[a.shadow], 0));
@@ -631,6 +634,9 @@ cv_status crypt_batch_ahead(cv_key* k, bool decrypt, const uint8_t* in, uint8_t*
   CV_HIP(hipEventRecord(a.ks_ready, st));
   if ((s = run_rounds(k, decrypt, in, out, a.d_ks[buf], T, st)) != CV_OK) return s;
   k->frame_index += T;
+  CV_HIP(hipEventRecord(a.last, st));
+  a.last_stream = st;
+  a.has_last = true;
   CV_HIP(hipStreamWaitEvent(a.s, a.ks_ready, 0));
   {
     Timed tm(k, a.s);
@@ -911,6 +917,7 @@ void cv_key_free(cv_key* k) {
     if (a.done[i]) (void)hipEventDestroy(a.done[i]);
   }
   if (a.ks_ready) (void)hipEventDestroy(a.ks_ready);
+  if (a.last) (void)hipEventDestroy(a.last);
   if (a.s) (void)hipStreamDestroy(a.s);
   delete k;
 }

@@ -90,6 +90,9 @@ struct cv_key {
     hipStream_t s = nullptr;           // private stream (default priority)
     hipEvent_t ks_ready = nullptr;     // call's stream: keystream ready, shadow states copied
     hipEvent_t done[2] = {};           // per shadow copy: the last lookahead using it is complete
+    hipEvent_t last = nullptr;         // end of the last batch's work on its call's stream
+    hipStream_t last_stream = nullptr;
+    bool has_last = false;
     bool used[2] = {};
     double* d_shadow[2] = {};
     cv::PlcmChain* d_chains[2] = {};   // the key's chains with their states in shadow 0 / 1

@@ -4,8 +4,9 @@ from a copy of the generator states.  Frames encrypted or decrypted one call
 at a time must equal the oracle frame by frame, whether a call takes the
 lookahead or not: calls arriving after the lookahead finished, calls queued
 back to back, calls that change the frame count, a keystream call or a state
-set between calls, calls of several internal batches, both round paths, and
-a 2DLASM key (for which the option is ignored)."""
+set between calls, calls of several internal batches, calls on two streams
+in turn, both round paths, and a 2DLASM key (for which the option is
+ignored)."""
 import numpy as np
 import pytest
 
@@ -52,8 +53,6 @@ def test_lookahead_calls_match_oracle(B, path, decrypt):
     plan = [(1, True, None), (1, True, None), (1, False, None), (1, False, None),
             (2, True, None), (2, False, None), (5, True, None), (1, True, "keystream"),
             (1, True, None), (1, True, "set_state"), (1, True, None), (3, False, None)]
-    seed = 0
-    hits_expected = 0
     for i, (T, wait, event) in enumerate(plan):
         if event == "keystream":  # the key advances outside the calls: the lookahead is dropped
             ks = torch.empty(r * H * W * C, dtype=torch.uint8, device="cuda:0")
@@ -76,7 +75,6 @@ def test_lookahead_calls_match_oracle(B, path, decrypt):
         call(src, dst, s_c)
         got = _host(dst, want.shape)
         assert np.array_equal(got, want), f"call {i}: {np.count_nonzero(got != want)} bytes differ"
-        seed += 1
     hits, misses = k.lookahead_counts()
     # batches (of at most 2 frames) that found the lookahead of the batch before:
     # call 1, 2, 3 (T=1 after T=1); call 4's batch of 2 after T=1 misses; call 5 hits;
@@ -116,6 +114,34 @@ def test_lookahead_round_trip_and_off_equal(B):
     assert on.lookahead_counts() == (T - 1, 0)
     for k in (on, off, dec):
         k.close()
+
+
+def test_lookahead_calls_on_alternating_streams(B):
+    """Calls queued without waiting on two streams in turn: each call starts
+    after the last one's work, whatever stream it was on, and every frame
+    equals the oracle's."""
+    H, W, C, n, r, T = 64, 96, 3, 8, 5, 8
+    pm = plcm_key(n, 7800)
+    frames = uniform_frames(H, W, C, T, 7801)
+    s_c = confusion_seeds(T, 7802)
+    want = oracle.PlcmKey(H, W, C, n, r, pm).encrypt(frames, s_c)
+    k = B.Key(H, W, C, n, r, pm)
+    k.set_path(B.CV_PATH_FUSED)
+    k.set_launch(lookahead=1)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    src = _dev(frames)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    F = H * W * C
+    print("[case] lookahead alternating streams", flush=True)
+    for t in range(T):
+        sl = slice(t * F, (t + 1) * F)
+        k.encrypt(src[sl], dst[sl], s_c[t:t + 1], stream=streams[t % 2])
+    torch.cuda.synchronize()
+    got = dst.cpu().numpy().reshape(want.shape)
+    assert np.array_equal(got, want), f"{np.count_nonzero(got != want)} bytes differ"
+    assert k.lookahead_counts() == (T - 1, 0)
+    k.close()
 
 
 def test_lookahead_ignored_for_2dlasm(B):
