@@ -573,11 +573,11 @@ def bench_served(B, torch, np, args):
         if not row["meets_deadline"]:
             break
     passing = [c for c in capacity if c["meets_deadline"]]
-    # admission by device-memory budget: further 3840x2160 streams until the
-    # server refuses one (after the measurement, so they do not disturb it)
+    # admission by the device's free memory: further 3840x2160 streams until
+    # the server refuses one (after the measurement, so they do not disturb it)
     n4k = next((sp[3] for sp in specs if sp[:2] == (2160, 3840)), 32)
     extra, refused = 0, False
-    while extra < 256:
+    while extra < 1024:
         try:
             srv.open(2160, 3840, 3, n4k, R, plcm_key(n4k, 9900 + extra))
         except B.CvError as e:

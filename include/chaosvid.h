@@ -518,10 +518,15 @@ cv_status cv_batch_get_profile(cv_batch *batch, cv_profile *prof);
 typedef struct cv_server cv_server;
 typedef struct cv_stream cv_stream;
 
-/* Start a server on `device` with `hbm_budget` bytes of device memory for
- * keystream rings (0 = a quarter of the free memory).  Ring depth 3
- * frames and 8 queued frames per stream unless cv_server_tune says
- * otherwise.  Errors: CV_E_INVAL (NULL, no such device), CV_E_NOMEM. */
+/* Start a server on `device`.  hbm_budget > 0: that many bytes of device
+ * memory for keystream rings, allocated now; a stream is admitted while
+ * they hold its ring.  hbm_budget = 0: rings are allocated as streams open,
+ * in chunks of at least 4 GiB, and a stream is admitted while the device's
+ * free memory at that moment, less a reserve of a sixteenth of the total,
+ * holds its ring (cv_server_stats.hbm_budget then reports the chunks taken
+ * so far).  Ring depth 3 frames and 8 queued frames per stream unless
+ * cv_server_tune says otherwise.  Errors: CV_E_INVAL (NULL, no such
+ * device), CV_E_NOMEM. */
 cv_status cv_server_create(int device, size_t hbm_budget, cv_server **out);
 
 /* Ring depth (keystream frames generated ahead, >= 1) and queue depth
@@ -548,7 +553,8 @@ typedef struct {
   uint64_t keystream_frames;    /* stream-frames of keystream generated */
   uint32_t open_streams;
   uint32_t split_cus;           /* 1 if keystream and rounds run on disjoint CUs */
-  uint64_t hbm_used, hbm_budget; /* keystream ring bytes in use / allowed */
+  uint64_t hbm_used, hbm_budget; /* keystream ring bytes in use / held (the fixed budget, or
+                                    the chunks taken so far when it grows) */
   double keystream_ms;          /* summed launch-to-completion time of keystream launches */
   double rounds_ms;             /* summed launch-to-completion time of rounds ticks */
   uint64_t starved_frames;      /* frames that waited in the queue for their keystream */

@@ -505,7 +505,7 @@ void fill_blob(const cv_batch* b, const Plan& P, const Layout& L, uint8_t* h,
     cv::BatchJob* J = (cv::BatchJob*)(h + L.job_off[c]);
     for (size_t q = 0; q < P.jobs[c].size(); q++) {
       J[q] = P.jobs[c][q];
-      J[q].ks = ks_base + (uintptr_t)P.jobs[c][q].ks;
+      J[q].ks = (const uint8_t*)((uintptr_t)ks_base + (uintptr_t)P.jobs[c][q].ks);
       J[q].gm = (const uint32_t*)(d_gm + (uintptr_t)P.jobs[c][q].gm);
     }
     if (!P.group_jobs[c].empty())

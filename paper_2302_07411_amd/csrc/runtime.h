@@ -209,6 +209,8 @@ struct FrameJob {
 };
 // Enqueue keystream generation for `cj` and the rounds of `fj` (whose
 // keystream is generated by this tick or was generated earlier) on st.
+// Keystream offsets (ChainJob.ks_off, FrameJob.ks_off) count from ks_base;
+// with a null ks_base they are device addresses.
 // Every frame job must satisfy pw_eligible for the batch's shape.  With
 // `hooks`, the work is launched kernel by kernel, and the hooks run on st
 // between the keystream launches and the rounds launches, in this order:

@@ -90,6 +90,60 @@ class Arena {
   std::map<size_t, size_t> free_;  // offset -> bytes
 };
 
+// Device memory for keystream rings: chunks from hipMalloc, each split by
+// its own Arena.  Rings are handed out as device addresses.
+class Pool {
+ public:
+  ~Pool() {
+    for (Chunk& c : chunks_) (void)hipFree(c.mem);
+  }
+  // Device memory of `bytes` (a multiple of 256), or null.
+  static uint8_t* allocate(size_t bytes) {
+    uint8_t* mem = nullptr;
+    if (bytes == 0 || hipMalloc(&mem, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return mem;
+  }
+  // Take `mem` (from allocate) as a new chunk.
+  void add(uint8_t* mem, size_t bytes) {
+    chunks_.push_back({mem, Arena()});
+    chunks_.back().sub.reset(bytes);
+  }
+  uint8_t* alloc(size_t n) {
+    for (Chunk& c : chunks_) {
+      const size_t off = c.sub.alloc(n);
+      if (off != SIZE_MAX) return c.mem + off;
+    }
+    return nullptr;
+  }
+  void release(uint8_t* p, size_t n) {
+    for (Chunk& c : chunks_)
+      if (p >= c.mem && p < c.mem + c.sub.cap()) {
+        c.sub.release((size_t)(p - c.mem), n);
+        return;
+      }
+  }
+  size_t used() const {
+    size_t u = 0;
+    for (const Chunk& c : chunks_) u += c.sub.used();
+    return u;
+  }
+  size_t cap() const {
+    size_t t = 0;
+    for (const Chunk& c : chunks_) t += c.sub.cap();
+    return t;
+  }
+
+ private:
+  struct Chunk {
+    uint8_t* mem;
+    Arena sub;
+  };
+  std::vector<Chunk> chunks_;
+};
+
 struct Pending {
   uint64_t ticket;
   const uint8_t* in;
@@ -121,7 +175,8 @@ struct cv_stream {
   uint32_t Q = 0;             // queue depth (frames in flight)
   uint64_t rF = 0;            // keystream bytes per frame
   uint64_t steps_per_frame = 0;  // longest chain's steps per frame
-  size_t ring_off = 0, ring_bytes = 0;
+  uint8_t* ring = nullptr;    // keystream ring: D frames of rF bytes
+  size_t ring_bytes = 0;
   bool pw = false;            // geometry takes the batched kernels
   // counters (server mutex)
   uint64_t submitted = 0;     // tickets issued
@@ -141,8 +196,8 @@ struct cv_server {
   size_t lds_max = 0;
   uint32_t ring_frames = 3, queue_frames = 8;
   bool split = false;      // keystream and rounds on disjoint compute units
-  uint8_t* arena_mem = nullptr;
-  Arena arena;
+  Pool pool;                 // keystream rings
+  bool grow = false;         // budget 0: the pool grows while the device has free memory
   cv_batch* rb = nullptr;  // rounds ticks
   cv_batch* kb = nullptr;  // keystream launches
   hipStream_t s_rounds = nullptr, s_ks = nullptr;
@@ -203,7 +258,8 @@ void plan_keystream(cv_server* S, std::vector<ChainJob>& cj, std::vector<LasmJob
     const uint64_t contiguous = st->D - st->ks_issued % st->D;  // no wrap within a launch
     const uint64_t share = std::max<uint64_t>(1, longest / std::max<uint64_t>(1, st->steps_per_frame));
     const uint32_t k = (uint32_t)std::min({free, contiguous, share});
-    const uint64_t off = st->ring_off + (st->ks_issued % st->D) * st->rF;
+    // keystream addresses are absolute (the launches get a null base)
+    const uint64_t off = (uint64_t)(uintptr_t)st->ring + (st->ks_issued % st->D) * st->rF;
     if (st->key->map == CV_MAP_PLCM)
       cj.push_back({st->key, off, 0, k});
     else
@@ -227,7 +283,7 @@ void plan_rounds(cv_server* S, std::vector<FrameJob>& fj, std::vector<Pending>& 
       const Pending p = st->queue.front();
       st->queue.pop_front();
       const cv_key* k = st->key;
-      const uint64_t ks_off = st->ring_off + (p.ticket % st->D) * st->rF;
+      const uint64_t ks_off = (uint64_t)(uintptr_t)st->ring + (p.ticket % st->D) * st->rF;
       if (st->pw && pw_eligible(k, p.in, p.out, kThreads, S->lds_max)) {
         fj.push_back({k, p.in, p.out, p.in + k->F - 4, ks_off, p.s_c, (uint32_t)st->decrypt});
       } else {
@@ -249,11 +305,27 @@ cv_status run_solo(cv_server* S, const std::vector<Pending>& solo,
     cv_status s = ensure_workspace(st->key, 1);
     if (s == CV_OK) s = upload_shift_tables(st->key, &p.s_c, 1, S->s_rounds);
     if (s == CV_OK)
-      s = run_rounds(st->key, st->decrypt, p.in, p.out,
-                     S->arena_mem + st->ring_off + (p.ticket % st->D) * st->rF, 1, S->s_rounds);
+      s = run_rounds(st->key, st->decrypt, p.in, p.out, st->ring + (p.ticket % st->D) * st->rF, 1,
+                     S->s_rounds);
     if (s != CV_OK) return s;
   }
   return CV_OK;
+}
+
+// Budget 0: admission by the device's free memory now.  A new chunk of at
+// least 4 GiB (or the ring) is allocated while the free memory, less a
+// reserve of a sixteenth of the total for other allocations, holds it.
+// Called without the server mutex; returns the chunk (null if none) and its size.
+uint8_t* new_chunk(size_t ring_bytes, size_t* bytes) {
+  size_t free_b = 0, total = 0;
+  if (hipMemGetInfo(&free_b, &total) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  const size_t reserve = total / 16, need = (ring_bytes + 255) / 256 * 256;
+  if (free_b < reserve + need) return nullptr;
+  *bytes = std::min(free_b - reserve, std::max<size_t>(need, 4ull << 30)) / 256 * 256;
+  return Pool::allocate(*bytes);
 }
 
 // Release a stream's ring (mutex held) and then, with the mutex released,
@@ -298,7 +370,7 @@ hipError_t make_streams(cv_server* S, bool split) {
 }
 
 void free_stream(cv_server* S, cv_stream* st, std::unique_lock<std::mutex>* lk) {
-  S->arena.release(st->ring_off, st->ring_bytes);
+  S->pool.release(st->ring, st->ring_bytes);
   if (lk) lk->unlock();
   cv_key_free(st->key);
   delete st;
@@ -367,7 +439,7 @@ void worker_main(cv_server* S) {
         t.batched = !fj.empty();
         lk.unlock();
         cv_status s = run_solo(S, solo, solo_st);
-        if (s == CV_OK && !fj.empty()) s = batch_enqueue(S->rb, {}, fj, S->arena_mem, S->s_rounds);
+        if (s == CV_OK && !fj.empty()) s = batch_enqueue(S->rb, {}, fj, nullptr, S->s_rounds);
         std::string msg = s != CV_OK ? cv_last_error() : "";
         hipError_t e = t.ev ? hipEventRecord(t.ev, S->s_rounds) : hipErrorOutOfMemory;
         lk.lock();
@@ -390,10 +462,10 @@ void worker_main(cv_server* S) {
         for (auto& l : lj) frames += l.frames;
         S->ks_launch_t = Clock::now();
         lk.unlock();
-        cv_status s = cj.empty() ? CV_OK : batch_enqueue(S->kb, cj, {}, S->arena_mem, S->s_ks);
+        cv_status s = cj.empty() ? CV_OK : batch_enqueue(S->kb, cj, {}, nullptr, S->s_ks);
         for (const LasmJob& l : lj) {
           if (s != CV_OK) break;
-          if (cv::launch_prbg_lasm(l.k->d_lchains, l.k->g.n, S->arena_mem + l.ks_off, l.frames, 0,
+          if (cv::launch_prbg_lasm(l.k->d_lchains, l.k->g.n, (uint8_t*)(uintptr_t)l.ks_off, l.frames, 0,
                                    l.k->d_err, S->s_ks) != hipSuccess ||
               hipMemcpyAsync(l.k->h_err, l.k->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost,
                              S->s_ks) != hipSuccess)
@@ -456,7 +528,7 @@ void destroy(cv_server* S) {
   cv_batch_free(S->kb);
   if (S->s_rounds) (void)hipStreamDestroy(S->s_rounds);
   if (S->s_ks) (void)hipStreamDestroy(S->s_ks);
-  if (S->arena_mem) (void)hipFree(S->arena_mem);
+
   delete S;
 }
 
@@ -471,14 +543,11 @@ cv_status cv_server_create(int device, size_t hbm_budget, cv_server** out) {
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
     return fail(CV_E_INVAL, "no such HIP device");
   DeviceGuard dg(device);
-  if (hbm_budget == 0) {
-    size_t free_b = 0, total = 0;
-    CV_HIP(hipMemGetInfo(&free_b, &total));
-    hbm_budget = free_b / 4;
-  }
+  const bool grow = hbm_budget == 0;
   hbm_budget = hbm_budget / 256 * 256;
-  if (hbm_budget == 0) return fail(CV_E_INVAL, "hbm_budget below 256 bytes");
+  if (!grow && hbm_budget == 0) return fail(CV_E_INVAL, "hbm_budget below 256 bytes");
   cv_server* S = new cv_server();
+  S->grow = grow;
   S->device = device;
   S->lds_max = lds_limit(device);
   cv_status s = cv_batch_create(device, &S->rb);
@@ -494,13 +563,15 @@ cv_status cv_server_create(int device, size_t hbm_budget, cv_server** out) {
     destroy(S);
     return hip_fail(e, "cv_server_create");
   }
-  if (hipMalloc(&S->arena_mem, hbm_budget) != hipSuccess) {
-    (void)hipGetLastError();
-    destroy(S);
-    return fail(CV_E_NOMEM, "keystream arena allocation failed");
+  if (!grow) {
+    uint8_t* mem = Pool::allocate(hbm_budget);
+    if (!mem) {
+      destroy(S);
+      return fail(CV_E_NOMEM, "keystream arena allocation failed");
+    }
+    S->pool.add(mem, hbm_budget);
   }
-  S->arena.reset(hbm_budget);
-  S->stats.hbm_budget = hbm_budget;
+  S->stats.hbm_budget = S->pool.cap();
   S->worker = std::thread(worker_main, S);
   *out = S;
   return CV_OK;
@@ -554,7 +625,7 @@ cv_status cv_server_get_stats(cv_server* S, cv_server_stats* stats) {
   *stats = S->stats;
   stats->open_streams = (uint32_t)S->streams.size();
   stats->split_cus = S->split;
-  stats->hbm_used = S->arena.used();
+  stats->hbm_used = S->pool.used();
   return CV_OK;
 }
 
@@ -576,18 +647,33 @@ cv_status cv_stream_open(cv_server* S, const cv_geom* geom, cv_map map, const do
   st->pw = (k->g.C == 3 || k->g.C == 4) && k->g.W % 16 == 0;
   st->lat.assign(kLatencyLog, -1.0);
   {
-    std::lock_guard<std::mutex> g(S->mu);
+    std::unique_lock<std::mutex> lk(S->mu);
     if ((s = server_error(S)) == CV_OK) {
       st->D = S->ring_frames;
       st->Q = S->queue_frames;
       st->ring_bytes = st->D * st->rF;
       if (S->streams.size() >= kMaxStreams) {
         s = fail(CV_E_AGAIN, "too many open streams");
-      } else if ((st->ring_off = S->arena.alloc(st->ring_bytes)) == SIZE_MAX) {
-        s = fail(CV_E_AGAIN, "the server's device-memory budget cannot hold this stream's "
-                             "keystream ring now");
       } else {
-        S->streams.push_back(st);
+        st->ring = S->pool.alloc(st->ring_bytes);
+        if (!st->ring && S->grow) {
+          lk.unlock();  // allocate without holding up the worker
+          size_t bytes = 0;
+          uint8_t* mem = new_chunk(st->ring_bytes, &bytes);
+          lk.lock();
+          if (mem) {
+            S->pool.add(mem, bytes);
+            S->stats.hbm_budget = S->pool.cap();
+          }
+          st->ring = S->pool.alloc(st->ring_bytes);
+        }
+        if (!st->ring)
+          s = fail(CV_E_AGAIN, S->grow ? "the device's free memory (less a reserve of 1/16 of it) "
+                                         "cannot hold this stream's keystream ring now"
+                                       : "the server's device-memory budget cannot hold this "
+                                         "stream's keystream ring now");
+        else
+          S->streams.push_back(st);
       }
     }
   }

@@ -44,8 +44,13 @@ def _wait(stream, ticket, timeout=20.0):
         time.sleep(0.0005)
 
 
-def test_served_streams_match_oracle(B):
-    srv = B.Server(hbm_budget=256 << 20, ring_frames=2, queue_frames=3)
+@pytest.mark.parametrize("budget", [256 << 20, 0])
+def test_served_streams_match_oracle(B, budget):
+    """Interleaved submission to streams of mixed sizes and directions equals
+    the oracle frame by frame; with a fixed device-memory budget, and with
+    budget 0 (rings allocated as streams open, by the free memory)."""
+    srv = B.Server(hbm_budget=budget, ring_frames=2, queue_frames=3)
+    assert srv.stats()["hbm_budget"] == budget
     cases = []
     for i, (name, H, W, C, n, r, T, dec) in enumerate(SERVED):
         pm = plcm_key(n, 5100 + i)
@@ -59,7 +64,9 @@ def test_served_streams_match_oracle(B):
         out = [torch.empty_like(x) for x in src]
         cases.append(dict(name=name, st=st, src=src, out=out, s_c=s_c, want=want,
                           next=0, tickets=[]))
-    print("[case] served streams, interleaved submission", flush=True)
+    if budget == 0:  # one chunk of at least 4 GiB holds every ring
+        assert srv.stats()["hbm_budget"] >= 4 << 30
+    print(f"[case] served streams, interleaved submission, budget {budget}", flush=True)
     torch.cuda.synchronize()
     # round-robin submission, retrying streams whose queue is full
     pending = True
