@@ -53,7 +53,7 @@
 // verifier wavefronts recompute the block's steps from the checkpoints with
 // the same operations, check every step against its predecessor (the
 // remainder by one FMA and one Markstein correction must give the value
-// back, see plcm_wrong) and the producer's checkpoints against their own
+// back, see plcm_wrong_yg) and the producer's checkpoints against their own
 // values; an emitter wavefront turns verified blocks into bytes.  On a
 // mismatch every wavefront takes a repair branch: the producer recomputes
 // the failed block and the one after it with the correctly rounded fast path
@@ -146,48 +146,6 @@ __device__ __forceinline__ double plcm_two(double x, double p, double zp, double
   asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(lo) : "v"(m), "v"(__double2loint(q1)), "v"(__double2loint(q2)));
   asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(hi) : "v"(m), "v"(__double2hiint(q1)), "v"(__double2hiint(q2)));
   return __hiloint2double((int)hi, (int)lo);
-}
-
-// Whether `cur` differs from the correctly rounded Eq. (5) step from `x`
-// (fast-path domain).  For each piece, the remainder num - cur*den by one FMA
-// and one Markstein correction cur + rem*RN(1/den): if cur is within one ulp
-// of num/den the remainder is exact and the correction is RN(num/den), so it
-// equals cur exactly when cur is right; if cur is further away, the
-// correction moves it by more than half an ulp.  Either way a wrong cur is
-// never accepted.  (The selected piece's comparison decides.)
-__device__ __forceinline__ bool plcm_wrong(double x, double cur, double p, double h, double ip,
-                                           double ih) {
-  const double y = vmin(x, 1.0 - x);
-  const double g = y - p;
-  const double r1 = __builtin_fma(-cur, p, y), r2 = __builtin_fma(-cur, h, g);
-  double c1 = __builtin_fma(r1, ip, cur), c2 = __builtin_fma(r2, ih, cur);
-  // both candidates in registers here: keeps the select branch-free, so the
-  // checks of a block overlap instead of running one masked branch at a time
-  asm volatile("" : "+v"(c1), "+v"(c2));
-  return (y < p ? c1 : c2) != cur;
-}
-
-// A verifier's step: plcm_two from x (the same operations, so the same value)
-// followed by plcm_wrong's check of that value, sharing the fold and the
-// piece test.  The asm statements here are not volatile, so the compiler may
-// move a step's check past the next steps and fill the chain's latency with
-// it.  `flip` (testing only) flips the last bit of the value before the check.
-__device__ __forceinline__ double plcm_two_checked(double x, double p, double h, double zp,
-                                                   double lp, double zh, double lh, bool flip,
-                                                   bool& wrong) {
-  double y;
-  asm("v_min_f64 %0, %1, %2" : "=v"(y) : "v"(x), "v"(1.0 - x));
-  const double g = y - p;
-  const bool first = y < p;
-  const double q1 = __builtin_fma(zp, y, lp * y);
-  const double q2 = __builtin_fma(zh, g, lh * g);
-  double cur = first ? q1 : q2;
-  if (flip) cur = __longlong_as_double(__double_as_longlong(cur) ^ 1);
-  double c1 = __builtin_fma(__builtin_fma(-cur, p, y), zp, cur);
-  double c2 = __builtin_fma(__builtin_fma(-cur, h, g), zh, cur);
-  asm("" : "+v"(c1), "+v"(c2));
-  wrong = (first ? c1 : c2) != cur;
-  return cur;
 }
 
 // Division variants of the generator (identical bytes).
@@ -368,7 +326,7 @@ __global__ __launch_bounds__(128) void prbg_plcm_kernel(const PlcmChain* __restr
 // keeps only kNV checkpoints per block (the value after the last step of each
 // verifier's segment); verifier v recomputes its segment from the preceding
 // checkpoint with the same two-operation step (bit-identical), writes the
-// values to the ring, checks every step (plcm_wrong's test, reusing the fold)
+// values to the ring, checks every step (plcm_wrong_yg, reusing the fold)
 // and that its last value equals the producer's checkpoint, which catches a
 // producer that diverged anywhere in the segment.  Iteration b: the producer
 // runs block b, the verifiers block b-1, the emitter block b-2; a barrier;
@@ -398,7 +356,14 @@ __device__ __forceinline__ double plcm_two_yg(double x, double p, double zp, dou
   return y < p ? q1 : q2;
 }
 
-// plcm_wrong's test with the fold of the step's input given.
+// Whether `cur` differs from the correctly rounded Eq. (5) step whose input
+// folds to y (g = y - p), in the fast-path domain.  For each piece, the
+// remainder num - cur*den by one FMA and one Markstein correction
+// cur + rem*RN(1/den): if cur is within one ulp of num/den the remainder is
+// exact and the correction is RN(num/den), so it equals cur exactly when cur
+// is right; if cur is further away, the correction moves it by more than
+// half an ulp.  Either way a wrong cur is never accepted.  (The selected
+// piece's comparison decides.)
 __device__ __forceinline__ bool plcm_wrong_yg(double y, double g, double cur, double p, double h,
                                               double ip, double ih) {
   double c1 = __builtin_fma(__builtin_fma(-cur, p, y), ip, cur);
