@@ -30,6 +30,40 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+STRUCTS = {  # header typedef -> binding class
+    "cv_geom": "CvGeom", "cv_launch": "CvLaunch", "cv_profile": "CvProfile",
+    "cv_batch_item": "CvBatchItem", "cv_batch_shape": "CvBatchShape", "cv_batch_info": "CvBatchInfo",
+    "cv_server_stats": "CvServerStats",
+}
+
+
+def test_struct_layouts_match_the_binding(tmp_path):
+    """Every struct the binding marshals has the header's size and field
+    offsets (a C program built with gcc against include/chaosvid.h prints
+    them)."""
+    import subprocess
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "chaosvid.h"', "int main(void) {"]
+    for c_name, py_name in STRUCTS.items():
+        cls = getattr(binding, py_name)
+        lines.append(f'  printf("{c_name} size %zu\\n", sizeof({c_name}));')
+        for field, _ in cls._fields_:
+            c_field = "in" if field == "in_" else field
+            lines.append(f'  printf("{c_name}.{field} %zu\\n", offsetof({c_name}, {c_field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = dict(line.rsplit(" ", 1) for line in out if line)
+    for c_name, py_name in STRUCTS.items():
+        cls = getattr(binding, py_name)
+        assert int(got[f"{c_name} size"]) == ct.sizeof(cls), c_name
+        for field, _ in cls._fields_:
+            assert int(got[f"{c_name}.{field}"]) == getattr(cls, field).offset, f"{c_name}.{field}"
+
+
 def test_spec_version():
     assert binding.load().cv_spec_version() == 1
 
