@@ -171,8 +171,14 @@ __global__ __launch_bounds__(skew::kThreads) void batch_rows_kernel(BatchArgs A)
           for (uint32_t t0 = lo; t0 < hi; t0 += J.tile_enc) {
             const uint32_t R = min(J.tile_enc, hi - t0);
             const int64_t sa = t0 == lo ? seed_at : -1;
-            carry = full ? enc_rows_tile<C, KQ, true>(first, last, v, g, s, lo, hi, t0, R, carry, sa, lds, wsum)
-                         : enc_rows_tile<C, KQ, false>(first, last, v, g, s, lo, hi, t0, R, carry, sa, lds, wsum);
+            // KQ = 0: runs of 12 or of 4 pixels, by the job's width
+            constexpr uint32_t kq12 = KQ == 0 ? 12u : KQ, kq4 = KQ == 0 ? 4u : KQ;
+            if (KQ == 0 ? g.W % 12 == 0 : true)
+              carry = full ? enc_rows_tile<C, kq12, true>(first, last, v, g, s, lo, hi, t0, R, carry, sa, lds, wsum)
+                           : enc_rows_tile<C, kq12, false>(first, last, v, g, s, lo, hi, t0, R, carry, sa, lds, wsum);
+            else
+              carry = full ? enc_rows_tile<C, kq4, true>(first, last, v, g, s, lo, hi, t0, R, carry, sa, lds, wsum)
+                           : enc_rows_tile<C, kq4, false>(first, last, v, g, s, lo, hi, t0, R, carry, sa, lds, wsum);
             __syncthreads();  // the next tile's gather overwrites the LDS tile and wsum
           }
         }
@@ -213,6 +219,8 @@ __global__ void reset_batch_groups(uint32_t* p, uint32_t groups) {
 }  // namespace
 
 static const void* rows_fn(uint32_t C, uint32_t KQ) {
+  if (KQ == 0) return C == 3 ? reinterpret_cast<const void*>(&batch_rows_kernel<3, 0>)
+                             : reinterpret_cast<const void*>(&batch_rows_kernel<4, 0>);
   if (C == 3) return KQ == 12 ? reinterpret_cast<const void*>(&batch_rows_kernel<3, 12>)
                               : reinterpret_cast<const void*>(&batch_rows_kernel<3, 4>);
   return KQ == 12 ? reinterpret_cast<const void*>(&batch_rows_kernel<4, 12>)

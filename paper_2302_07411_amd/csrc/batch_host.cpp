@@ -47,11 +47,14 @@ namespace {
 constexpr uint32_t kSpinLimit = 1u << 21;  // about two seconds of polling per barrier
 // Frame jobs are launched in classes: by channel count (3, 4) and by whether
 // the row-run kernel takes runs of 12 pixels per lane (W a multiple of 12)
-// or of 4.  Class index = (C == 4) * 2 + (W % 12 != 0).
-constexpr int kClasses = 4;
+// or of 4 -- class (C == 4) * 2 + (W % 12 != 0) -- except that a tick with
+// jobs of both widths for one channel count launches them together, in
+// class 4 + (C == 4), on the kernel that picks the run length per job (one
+// launch instead of two: groups freed by one kind take jobs of the other).
+constexpr int kClasses = 6;
 int job_class(const cv::Geom& g) { return (g.C == 4 ? 2 : 0) + (g.W % 12 != 0 ? 1 : 0); }
-uint32_t class_C(int c) { return c >= 2 ? 4u : 3u; }
-uint32_t class_KQ(int c) { return (c & 1) ? 4u : 12u; }
+uint32_t class_C(int c) { return c >= 4 ? (c == 5 ? 4u : 3u) : (c >= 2 ? 4u : 3u); }
+uint32_t class_KQ(int c) { return c >= 4 ? 0u : (c & 1) ? 4u : 12u; }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -323,6 +326,14 @@ cv_status plan_tick(const cv_batch* b, const std::vector<ChainJob>& cj,
   P.gm.resize(gm);
   gm = 0;
   std::vector<JobLoad> order[kClasses];  // per class
+  // both widths of one channel count in this tick: one launch for them
+  bool kind[kClasses] = {};
+  for (const FrameJob& f : fj) kind[job_class(f.k->g)] = true;
+  const bool merge[2] = {kind[0] && kind[1], kind[2] && kind[3]};
+  auto class_of = [&](const Geom& g) {
+    const int c = job_class(g);
+    return merge[c / 2] ? 4 + c / 2 : c;
+  };
   // the row-run kernel takes a class's jobs when it takes every one
   bool rows_ok[kClasses];
   for (bool& x : rows_ok) x = threads == 1024;
@@ -330,7 +341,7 @@ cv_status plan_tick(const cv_batch* b, const std::vector<ChainJob>& cj,
   for (const FrameJob& f : fj) {
     const Geom& g = f.k->g;
     shift_table(g.H, g.W, f.s_c, P.gm.data() + gm);
-    const int ci = job_class(g);
+    const int ci = class_of(g);
     // the LDS tiling: the largest tiles that fit, capped by the shape
     const uint32_t cap = b->shape.tile_rows_max ? b->shape.tile_rows_max : 0xFFFFFFFFu;
     const uint32_t tile = std::min(pw_tile_rows(g, threads, b->lds_max), cap);

@@ -202,7 +202,8 @@ struct BatchArgs {
 // rows = true: the row-run kernel (1024 threads; every job with tile_enc,
 // tile_dec > 0); false: the pixel-word kernel.
 // KQ: the row-run kernel's pixels per lane in the encryption diffusion (12
-// for frame widths that are multiples of 12, else 4).
+// for frame widths that are multiples of 12, else 4; 0: either, by each
+// job's width, for a launch that holds both kinds).
 hipError_t launch_batch_rounds(const BatchArgs& a, uint32_t C, uint32_t KQ, bool rows,
                                uint32_t threads, size_t lds, hipStream_t s);
 // Workgroups per XCD that fit on the device at once; with `reserve_cus`, on
