@@ -461,7 +461,8 @@ def bench_served(B, torch, np, args):
         plain[(h, w)] = CorrelatedVideo(h, w, 3, 9000 + j).frames_torch(0, 1, dev).reshape(-1)
         cipher[(h, w)] = torch.empty_like(plain[(h, w)])
         B.Key(h, w, 3, n, R, plcm_key(n, 9100 + j)).encrypt(plain[(h, w)], cipher[(h, w)], [1])
-    srv = B.Server(ring_frames=args.serve_ring, queue_frames=Q, split_cus=not args.serve_shared_cus)
+    srv = B.Server(ring_frames=args.serve_ring, queue_frames=Q,
+                   split_cus=0 if args.serve_shared_cus else args.serve_split)
     streams, outs, pms, first_out = [], [], [], []
     for i, (h, w, c, n, dec) in enumerate(specs):
         pm = plcm_key(n, 9500 + i)
@@ -605,7 +606,7 @@ def bench_served(B, torch, np, args):
         "frames_waiting_for_keystream": stats["starved_frames"],
         "keystream_ring_gb": stats["hbm_used"] / 1e9,
         "decrypt_streams": sum(1 for s in specs if s[4]),
-        "split_cus": bool(stats["split_cus"]), "ring_frames": args.serve_ring, "queue_frames": Q,
+        "split_cus": int(stats["split_cus"]), "ring_frames": args.serve_ring, "queue_frames": Q,
         "oracle_sample_streams": len(sample), "oracle_mismatched_bytes": mism,
         "oracle_late_frame_streams": [{"stream": i, "frame": late_t[i], "frames": nxt[i],
                                        "decrypt": specs[i][4]} for i in late],
@@ -921,6 +922,8 @@ def main():
                     help="seconds per run of the served capacity sweep (0 = skip)")
     ap.add_argument("--serve-ring", type=int, default=8,
                     help="keystream frames generated ahead per served stream")
+    ap.add_argument("--serve-split", type=int, default=1, choices=[1, 2, 3],
+                    help="quarters of every XCD's compute units for served keystream generation")
     ap.add_argument("--serve-shared-cus", action="store_true",
                     help="serve without splitting the CUs between keystream and rounds")
     ap.add_argument("--path", choices=["plain", "fused"], default="fused",

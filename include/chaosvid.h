@@ -531,10 +531,11 @@ cv_status cv_server_create(int device, size_t hbm_budget, cv_server **out);
 
 /* Ring depth (keystream frames generated ahead, >= 1) and queue depth
  * (frames a stream may have submitted and not finished, >= 1) for streams
- * opened after the call; split_cus = 1 (the default) runs keystream
- * generation on a quarter of the compute units of every XCD and the rounds
- * on the rest, 0 lets both use every CU.  CV_E_INVAL if a depth is 0 or
- * above 64; CV_E_STATE if split_cus changes while streams are open. */
+ * opened after the call.  split_cus = q in 1..3 runs keystream generation
+ * on q quarters of the compute units of every XCD and the rounds on the
+ * rest (1, a quarter, is the default); 0 lets both use every CU.
+ * CV_E_INVAL if a depth is 0 or above 64 or split_cus is outside 0..3;
+ * CV_E_STATE if split_cus changes while streams are open. */
 cv_status cv_server_tune(cv_server *server, uint32_t ring_frames, uint32_t queue_frames,
                          int split_cus);
 
@@ -552,7 +553,8 @@ typedef struct {
   uint64_t keystream_launches;  /* keystream generation launches */
   uint64_t keystream_frames;    /* stream-frames of keystream generated */
   uint32_t open_streams;
-  uint32_t split_cus;           /* 1 if keystream and rounds run on disjoint CUs */
+  uint32_t split_cus;           /* quarters of every XCD's CUs that keystream generation
+                                    runs on, apart from the rounds (0: CUs shared) */
   uint64_t hbm_used, hbm_budget; /* keystream ring bytes in use / held (the fixed budget, or
                                     the chunks taken so far when it grows) */
   double keystream_ms;          /* summed launch-to-completion time of keystream launches */

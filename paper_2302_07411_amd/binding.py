@@ -448,13 +448,13 @@ class Server:
     rounds ticks by a worker thread, keystream generated ahead."""
 
     def __init__(self, device: int = 0, hbm_budget: int = 0, ring_frames: int = None,
-                 queue_frames: int = None, split_cus: bool = True):
+                 queue_frames: int = None, split_cus: int = 1):
         h = ct.c_void_p()
         _check(load().cv_server_create(device, hbm_budget, ct.byref(h)))
         self._h = h
         self._streams = []
         _check(load().cv_server_tune(self._h, ring_frames or 3, queue_frames or 8,
-                                     int(bool(split_cus))))
+                                     int(split_cus)))
 
     def open(self, H, W, C, n, r, pm, decrypt: bool = False,
              map: int = CV_MAP_PLCM) -> "ServerStream":

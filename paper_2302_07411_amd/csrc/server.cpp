@@ -195,7 +195,7 @@ struct cv_server {
   int device = 0;
   size_t lds_max = 0;
   uint32_t ring_frames = 3, queue_frames = 8;
-  bool split = false;      // keystream and rounds on disjoint compute units
+  uint32_t split = 0;      // quarters of every XCD's CUs for the keystream (0: shared CUs)
   Pool pool;                 // keystream rings
   bool grow = false;         // budget 0: the pool grows while the device has free memory
   cv_batch* rb = nullptr;  // rounds ticks
@@ -330,13 +330,13 @@ uint8_t* new_chunk(size_t ring_bytes, size_t* bytes) {
 
 // Release a stream's ring (mutex held) and then, with the mutex released,
 // its key.
-// The server's two HIP streams.  With `split`, the keystream stream may use a
-// quarter of the compute units of every XCD (mask bits i with (i/8) % 4 == 0:
-// eight CUs per XCD whether consecutive mask bits walk the CUs of one XCD or
-// alternate between XCDs) and the rounds stream the rest, so that neither
-// kernel slows the other's wavefronts; the rounds launch is then sized for
-// the CUs it has.
-hipError_t make_streams(cv_server* S, bool split) {
+// The server's two HIP streams.  With `quarters` = q in 1..3, the keystream
+// stream may use q quarters of the compute units of every XCD (mask bits i
+// with (i/8) % 4 < q: 8q CUs per XCD whether consecutive mask bits walk the
+// CUs of one XCD or alternate between XCDs) and the rounds stream the rest,
+// so that neither kernel slows the other's wavefronts; the rounds launch is
+// then sized for the CUs it has.  q = 0: both streams use every CU.
+hipError_t make_streams(cv_server* S, uint32_t quarters) {
   if (S->s_rounds) (void)hipStreamDestroy(S->s_rounds);
   if (S->s_ks) (void)hipStreamDestroy(S->s_ks);
   S->s_rounds = S->s_ks = nullptr;
@@ -344,10 +344,10 @@ hipError_t make_streams(cv_server* S, bool split) {
   hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->device);
   if (e != hipSuccess) return e;
   cv_batch_shape shape{kThreads, 8, 0, 0, 0};
-  S->split = split && cus >= 64 && cus % 32 == 0;
+  S->split = cus >= 64 && cus % 32 == 0 ? std::min<uint32_t>(quarters, 3) : 0;
   if (S->split) {
     std::vector<uint32_t> ks((cus + 31) / 32, 0), rd((cus + 31) / 32, 0);
-    for (int i = 0; i < cus; i++) ((i / 8) % 4 == 0 ? ks : rd)[i / 32] |= 1u << (i % 32);
+    for (int i = 0; i < cus; i++) ((uint32_t)(i / 8) % 4 < S->split ? ks : rd)[i / 32] |= 1u << (i % 32);
     e = hipExtStreamCreateWithCUMask(&S->s_ks, (uint32_t)ks.size(), ks.data());
     if (e == hipSuccess) e = hipExtStreamCreateWithCUMask(&S->s_rounds, (uint32_t)rd.size(), rd.data());
     if (e != hipSuccess) {  // masks not supported here: share the CUs
@@ -355,7 +355,7 @@ hipError_t make_streams(cv_server* S, bool split) {
       if (S->s_ks) (void)hipStreamDestroy(S->s_ks);
       if (S->s_rounds) (void)hipStreamDestroy(S->s_rounds);
       S->s_ks = S->s_rounds = nullptr;
-      S->split = false;
+      S->split = 0;
     }
   }
   if (!S->split) {
@@ -365,7 +365,7 @@ hipError_t make_streams(cv_server* S, bool split) {
   (void)cv_batch_set_shape(S->rb, &shape);
   (void)cv_batch_set_shape(S->kb, &shape);
   // with the split, the rounds launches are sized for the CUs their stream may use
-  batch_set_reserve(S->rb, S->split ? (uint32_t)cus / 32 : 0);
+  batch_set_reserve(S->rb, S->split * (uint32_t)cus / 32);
   return e;
 }
 
@@ -557,7 +557,7 @@ cv_status cv_server_create(int device, size_t hbm_budget, cv_server** out) {
     return s;
   }
   // ticks change shape every time: launch kernel by kernel, groups of 8
-  hipError_t e = make_streams(S, true);
+  hipError_t e = make_streams(S, 1);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ks_ev, hipEventDisableTiming);
   if (e != hipSuccess) {
     destroy(S);
@@ -582,15 +582,15 @@ cv_status cv_server_tune(cv_server* S, uint32_t ring_frames, uint32_t queue_fram
   if (!S) return fail(CV_E_INVAL, "server is NULL");
   if (ring_frames < 1 || ring_frames > 64 || queue_frames < 1 || queue_frames > 64)
     return fail(CV_E_INVAL, "ring_frames and queue_frames must be in 1..64");
-  if (split_cus != 0 && split_cus != 1) return fail(CV_E_INVAL, "split_cus must be 0 or 1");
+  if (split_cus < 0 || split_cus > 3) return fail(CV_E_INVAL, "split_cus must be in 0..3");
   std::lock_guard<std::mutex> g(S->mu);
-  if (split_cus != (int)S->split) {
+  if ((uint32_t)split_cus != S->split) {
     if (!S->streams.empty() || S->ks_busy || !S->ticks.empty())
       return fail(CV_E_STATE, "the compute-unit split can change only with no stream open");
     DeviceGuard dg(S->device);
     (void)hipStreamSynchronize(S->s_ks);
     (void)hipStreamSynchronize(S->s_rounds);
-    hipError_t e = make_streams(S, split_cus != 0);
+    hipError_t e = make_streams(S, (uint32_t)split_cus);
     if (e != hipSuccess) {
       set_error(S, CV_E_HIP, "stream creation failed");
       return hip_fail(e, "cv_server_tune");

@@ -44,13 +44,15 @@ def _wait(stream, ticket, timeout=20.0):
         time.sleep(0.0005)
 
 
-@pytest.mark.parametrize("budget", [256 << 20, 0])
-def test_served_streams_match_oracle(B, budget):
+@pytest.mark.parametrize("budget,split", [(256 << 20, 1), (0, 1), (256 << 20, 2), (256 << 20, 0)])
+def test_served_streams_match_oracle(B, budget, split):
     """Interleaved submission to streams of mixed sizes and directions equals
     the oracle frame by frame; with a fixed device-memory budget, and with
-    budget 0 (rings allocated as streams open, by the free memory)."""
-    srv = B.Server(hbm_budget=budget, ring_frames=2, queue_frames=3)
+    budget 0 (rings allocated as streams open, by the free memory); with the
+    keystream on a quarter or a half of every XCD's CUs, or on shared CUs."""
+    srv = B.Server(hbm_budget=budget, ring_frames=2, queue_frames=3, split_cus=split)
     assert srv.stats()["hbm_budget"] == budget
+    assert srv.stats()["split_cus"] == split
     cases = []
     for i, (name, H, W, C, n, r, T, dec) in enumerate(SERVED):
         pm = plcm_key(n, 5100 + i)
@@ -66,7 +68,7 @@ def test_served_streams_match_oracle(B, budget):
                           next=0, tickets=[]))
     if budget == 0:  # one chunk of at least 4 GiB holds every ring
         assert srv.stats()["hbm_budget"] >= 4 << 30
-    print(f"[case] served streams, interleaved submission, budget {budget}", flush=True)
+    print(f"[case] served streams, interleaved submission, budget {budget} split {split}", flush=True)
     torch.cuda.synchronize()
     # round-robin submission, retrying streams whose queue is full
     pending = True
@@ -140,6 +142,9 @@ def test_server_admission_and_queue_limits(B):
     with pytest.raises(B.CvError) as e:
         srv.open(H, W, C, n, r, plcm_key(n, 2))
     assert e.value.status == B.CV_E_AGAIN
+    for bad in (-1, 4):  # the split takes 0..3 quarters
+        assert B.load().cv_server_tune(srv._h, 2, 2, bad) == B.CV_E_INVAL
+    assert B.load().cv_server_tune(srv._h, 2, 2, 2) == B.CV_E_STATE  # a stream is open
     src = torch.from_numpy(uniform_frames(H, W, C, 3, 4).reshape(3, -1)).to("cuda:0")
     out = torch.empty_like(src)
     print("[case] server queue limits", flush=True)
