@@ -667,13 +667,18 @@ cv_status cv_stream_open(cv_server* S, const cv_geom* geom, cv_map map, const do
           }
           st->ring = S->pool.alloc(st->ring_bytes);
         }
-        if (!st->ring)
+        if (!st->ring) {
           s = fail(CV_E_AGAIN, S->grow ? "the device's free memory (less a reserve of 1/16 of it) "
                                          "cannot hold this stream's keystream ring now"
                                        : "the server's device-memory budget cannot hold this "
                                          "stream's keystream ring now");
-        else
+        } else if (S->streams.size() >= kMaxStreams) {  // others opened while unlocked
+          S->pool.release(st->ring, st->ring_bytes);
+          st->ring = nullptr;
+          s = fail(CV_E_AGAIN, "too many open streams");
+        } else {
           S->streams.push_back(st);
+        }
       }
     }
   }

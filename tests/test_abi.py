@@ -92,6 +92,7 @@ GOOD = [0.3, 0.2, 0.6, 0.4]
     ((8, 8, 1, 1, 5), [0.3, 0.5, 0.6, 0.4], "p must"),
     ((8, 8, 1, 1, 5), [0.3, 0.2, 0.6, 0.0], "p must"),
     ((8, 8, 1, 1, 5), [0.3, float("nan"), 0.6, 0.4], "p must"),
+    ((10923, 16384, 3, 16, 5), GOOD * 16, "frame too large"),  # one row past the largest
 ])
 def test_keysetup_rejects(geom, pm, why):
     st, h = _keysetup(*geom, pm)
