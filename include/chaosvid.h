@@ -128,8 +128,9 @@ typedef struct {
                               (C in {3,4}, W a multiple of 16, 16-byte aligned buffers;
                               otherwise 1), 3 as 2, with CV_PATH_FUSED encryption by whole
                               source-row runs and packed-byte diffusion, and decryption by
-                              whole source-row runs when every subframe fits the LDS as one
-                              tile (4*(W+4) bytes per row plus 4*H) */
+                              whole source-row runs: in one pass per subframe when every
+                              subframe fits the LDS as one tile (4*(W+4) bytes per row plus
+                              4*H), else tile by tile with the multi-stream kernel */
   uint32_t tile_rows_pw;   /* frame rows per LDS tile of the pixel-word kernels */
   uint32_t fused_groups;   /* CV_PATH_FUSED: frame groups in flight (multiple of 8); 0 = as
                               many as can be resident (reading back gives the value used) */

@@ -286,6 +286,21 @@ void set_fused_groups(cv_key* k, uint32_t want) {
   k->fused_cap_skew = cv::rounds_skew_resident_groups(g, k->tile_skew, k->device);
   k->fused_cap_unskew = cv::rounds_unskew_applies(g, k->lds_max)
                             ? cv::rounds_unskew_resident_groups(g, k->device) : 0;
+  k->rows_tile_dec = k->rows_G = k->fused_cap_rows = 0;
+  if (k->fused_cap_unskew == 0 && k->tile_skew > 0) {
+    const uint32_t tile = cv::batch_unskew_tile_rows(g, k->lds_max);
+    const size_t lds = cv::batch_rows_lds_bytes(g, true, tile);
+    const uint32_t kq = g.W % 12 == 0 ? 12 : 4;
+    const uint32_t per_xcd =
+        tile > 0 ? cv::batch_resident_slots(g.C, kq, true, 1024, lds, k->device) : 0;
+    if (per_xcd > 0) {
+      k->rows_tile_dec = tile;
+      k->rows_lds = lds;
+      k->rows_KQ = kq;
+      k->rows_G = std::min(g.n, per_xcd);
+      k->fused_cap_rows = 8 * (per_xcd / k->rows_G);
+    }
+  }
   const uint32_t w = want / 8 * 8;
   k->fused_groups = (w == 0 || w > k->fused_cap) ? k->fused_cap : w;
 }
@@ -335,20 +350,45 @@ cv_status ensure_fused(cv_key* k) {
 // Fused kernel of a direction: the row-run kernels (encryption: any
 // geometry with the pixel-word conditions; decryption: every band one LDS
 // tile) unless the pixel-word kernels are asked for.
-enum FusedKernel { FUSED_PW = 0, FUSED_SKEW = 1, FUSED_UNSKEW = 2 };
+// Decryption of geometries with a band over one LDS tile takes the row-run
+// batch kernel (tile by tile) over the key's frames.
+enum FusedKernel { FUSED_PW = 0, FUSED_SKEW = 1, FUSED_UNSKEW = 2, FUSED_ROWS = 3 };
 
 FusedKernel fused_kernel(const cv_key* k, bool decrypt) {
   if (k->round_variant == 2) return FUSED_PW;
   if (!decrypt) return k->fused_cap_skew > 0 ? FUSED_SKEW : FUSED_PW;
-  return k->fused_cap_unskew > 0 ? FUSED_UNSKEW : FUSED_PW;
+  if (k->fused_cap_unskew > 0) return FUSED_UNSKEW;
+  return k->fused_cap_rows > 0 ? FUSED_ROWS : FUSED_PW;
 }
 
 uint32_t fused_group_cap(const cv_key* k, bool decrypt) {
   switch (fused_kernel(k, decrypt)) {
     case FUSED_SKEW: return std::min(k->fused_groups, k->fused_cap_skew);
     case FUSED_UNSKEW: return std::min(k->fused_groups, k->fused_cap_unskew);
+    case FUSED_ROWS: return std::min(k->fused_groups, k->fused_cap_rows);
     default: return k->fused_groups;
   }
+}
+
+// Tables of the row-run batch kernel for up to T frames (decryption with
+// FUSED_ROWS); nothing to do for other keys.
+cv_status ensure_rows_tables(cv_key* k, uint32_t T) {
+  if (k->fused_cap_rows == 0) return CV_OK;
+  const size_t bytes =
+      cv::stream_rows_table_bytes(T, cv::stream_rows_slots(k->fused_cap_rows, k->rows_G));
+  if (bytes <= k->rows_tables_cap) return CV_OK;
+  drop_graphs(k);                  // captured launches point at the old tables
+  CV_HIP(hipDeviceSynchronize());  // which may still be read
+  if (k->d_rows_tables) (void)hipFree(k->d_rows_tables);
+  k->d_rows_tables = nullptr;
+  k->rows_tables_cap = 0;
+  if (hipMalloc(&k->d_rows_tables, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    k->d_rows_tables = nullptr;
+    return fail(CV_E_NOMEM, "row-run decryption tables allocation failed");
+  }
+  k->rows_tables_cap = bytes;
+  return CV_OK;
 }
 
 // One fused launch over T frames with the workspace given explicitly: shift
@@ -356,7 +396,8 @@ uint32_t fused_group_cap(const cv_key* k, bool decrypt) {
 // group in `counters`, the error word `err`; at most `groups` groups.
 cv_status launch_fused_ws(const cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
                           const uint8_t* ks, uint32_t T, const uint32_t* gm, uint8_t* fscratch,
-                          uint32_t* counters, uint32_t* err, uint32_t groups, hipStream_t st) {
+                          uint32_t* counters, uint32_t* err, uint32_t groups, hipStream_t st,
+                          uint8_t* rows_tables) {
   cv::RoundsFusedArgs a{};
   a.in = in;
   a.out = out;
@@ -371,9 +412,35 @@ cv_status launch_fused_ws(const cv_key* k, bool decrypt, const uint8_t* in, uint
   a.groups = std::min<uint32_t>(std::min(groups, fused_group_cap(k, decrypt)), ((T + 7) / 8) * 8);
   a.spin_limit = k->spin_limit;
   a.decrypt = decrypt;
-  switch (fused_kernel(k, decrypt)) {
+  FusedKernel fk = fused_kernel(k, decrypt);
+  if (fk == FUSED_ROWS && !rows_tables) fk = FUSED_PW;
+  switch (fk) {
     case FUSED_SKEW: CV_HIP(cv::launch_rounds_skew(a, k->tile_skew, st)); break;
     case FUSED_UNSKEW: CV_HIP(cv::launch_rounds_unskew(a, st)); break;
+    case FUSED_ROWS: {
+      cv::StreamRows r{};
+      r.proto.in = in;
+      r.proto.out = out;
+      r.proto.in_last = in + (uint64_t)T * k->F - 4;
+      r.proto.ks = ks;
+      r.proto.gm = gm;
+      r.proto.g = k->g;
+      r.proto.decrypt = 1;
+      r.proto.tile_dec = k->rows_tile_dec;
+      r.ks_stride = (uint64_t)k->g.r * k->F;
+      r.T = T;
+      r.groups = a.groups;
+      r.G = k->rows_G;
+      r.KQ = k->rows_KQ;
+      r.lds = k->rows_lds;
+      r.tables = rows_tables;
+      r.scratch = fscratch;
+      r.counters = counters;
+      r.err = err;
+      r.spin_limit = k->spin_limit;
+      CV_HIP(cv::launch_stream_rows(r, st));
+      break;
+    }
     default: CV_HIP(cv::launch_rounds_fused(a, k->threads, st));
   }
   return CV_OK;
@@ -382,10 +449,11 @@ cv_status launch_fused_ws(const cv_key* k, bool decrypt, const uint8_t* in, uint
 cv_status run_rounds_fused(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
                            const uint8_t* ks, uint32_t T, hipStream_t st) {
   cv_status s = ensure_fused(k);
+  if (s == CV_OK && decrypt) s = ensure_rows_tables(k, T);
   if (s != CV_OK) return s;
   Timed tm(k, st);
   if ((s = launch_fused_ws(k, decrypt, in, out, ks, T, k->d_gm, k->d_fscratch, k->d_counters,
-                           k->d_err, k->fused_groups, st)) != CV_OK)
+                           k->d_err, k->fused_groups, st, k->d_rows_tables)) != CV_OK)
     return s;
   tm.end(1, (uint64_t)T * k->g.r);
   return queue_err_readback(k, st);
@@ -511,6 +579,7 @@ cv_status crypt_batch_graph(cv_key* k, bool decrypt, const uint8_t* in, uint8_t*
     // the fused workspace (allocations are not allowed inside a capture)
     if (use_pw(k, in, out, k->d_ks) && k->path == CV_PATH_FUSED && k->fused_groups > 0) {
       cv_status s = ensure_fused(k);
+      if (s == CV_OK && decrypt) s = ensure_rows_tables(k, T);
       if (s != CV_OK) return s;
     }
     if (k->graphs.size() >= cv_key::kMaxGraphs) {
@@ -902,6 +971,7 @@ void cv_key_free(cv_key* k) {
   if (k->cap) (void)hipStreamDestroy(k->cap);
   if (k->d_fscratch) (void)hipFree(k->d_fscratch);
   if (k->d_counters) (void)hipFree(k->d_counters);
+  if (k->d_rows_tables) (void)hipFree(k->d_rows_tables);
   if (k->d_err) (void)hipFree(k->d_err);
   if (k->h_err) (void)hipHostFree(k->h_err);
   if (k->err_copied) (void)hipEventDestroy(k->err_copied);
@@ -1065,6 +1135,7 @@ cv_status cv_key_autotune(cv_key* k, int decrypt, uint32_t n_frames, void* strea
         if (fused_group_cap(k, dec) < groups) break;  // beyond the resident capacity
         if (variant == 3 && fused_kernel(k, dec) == FUSED_PW) break;  // no row-run kernel here
         if ((s = ensure_workspace(k, n_frames)) != CV_OK || (s = ensure_fused(k)) != CV_OK ||
+            (dec && (s = ensure_rows_tables(k, n_frames)) != CV_OK) ||
             (s = upload_shift_tables(k, seeds.data(), n_frames, st)) != CV_OK)
           break;
         float ms = 0.f;
@@ -1072,7 +1143,7 @@ cv_status cv_key_autotune(cv_key* k, int decrypt, uint32_t n_frames, void* strea
           if (rep == 1 && hipEventRecord(e0, st) != hipSuccess) s = hip_fail(hipErrorUnknown, "hipEventRecord");
           if (s == CV_OK)
             s = launch_fused_ws(k, dec, d_in, d_out, d_ks, n_frames, k->d_gm, k->d_fscratch,
-                                k->d_counters, k->d_err, k->fused_groups, st);
+                                k->d_counters, k->d_err, k->fused_groups, st, k->d_rows_tables);
         }
         if (s != CV_OK) break;
         if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||

@@ -248,6 +248,83 @@ hipError_t launch_batch_rounds(const BatchArgs& a, uint32_t C, uint32_t KQ, bool
   return hipGetLastError();
 }
 
+namespace {
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+__global__ void fill_stream_rows(BatchJob* jobs, uint32_t* group_jobs, uint32_t* group_off,
+                                 uint32_t* slots, BatchJob proto, uint64_t F, uint64_t ks_stride,
+                                 uint32_t T, uint32_t groups, uint32_t G, uint32_t n_slots) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t per = T / groups, rem = T % groups;  // groups below rem take per + 1 frames
+  if (i < T) {
+    BatchJob J = proto;
+    J.in += i * F;
+    J.out += i * F;
+    J.ks += i * ks_stride;
+    J.gm += (uint64_t)i * proto.g.H;
+    jobs[i] = J;
+    const uint32_t q = i % groups, m = i / groups;
+    group_jobs[q * per + min(q, rem) + m] = i;
+  }
+  if (i <= groups) group_off[i] = i * per + min(i, rem);
+  if (i < n_slots) {
+    const uint32_t xcd = i % 8, u = i / 8, group = xcd + 8 * (u / G);
+    slots[i] = group < groups ? batch_slot(group, u % G, G) : kIdleSlot;
+  }
+}
+
+struct StreamRowsLayout {
+  size_t jobs, group_jobs, group_off, slots, bytes;
+};
+
+StreamRowsLayout stream_rows_layout(uint32_t T, uint32_t n_slots) {
+  StreamRowsLayout L;
+  L.jobs = 0;
+  L.group_jobs = align256((size_t)T * sizeof(BatchJob));
+  L.group_off = L.group_jobs + align256(4 * (size_t)T);
+  L.slots = L.group_off + align256(4 * ((size_t)T + 1));
+  L.bytes = L.slots + 4 * (size_t)n_slots;
+  return L;
+}
+
+}  // namespace
+
+size_t stream_rows_table_bytes(uint32_t T, uint32_t n_slots) {
+  return stream_rows_layout(T, n_slots).bytes;
+}
+
+uint32_t stream_rows_slots(uint32_t groups, uint32_t G) { return 8 * ((groups + 7) / 8) * G; }
+
+hipError_t launch_stream_rows(const StreamRows& s, hipStream_t st) {
+  if (s.T == 0 || s.groups == 0 || s.G == 0) return hipErrorInvalidValue;
+  const uint32_t groups = min(s.groups, s.T);  // no group without a frame
+  const uint32_t n_slots = stream_rows_slots(groups, s.G);
+  const StreamRowsLayout L = stream_rows_layout(s.T, n_slots);
+  BatchJob* jobs = reinterpret_cast<BatchJob*>(s.tables + L.jobs);
+  uint32_t* group_jobs = reinterpret_cast<uint32_t*>(s.tables + L.group_jobs);
+  uint32_t* group_off = reinterpret_cast<uint32_t*>(s.tables + L.group_off);
+  uint32_t* slots = reinterpret_cast<uint32_t*>(s.tables + L.slots);
+  const Geom& g = s.proto.g;
+  const uint64_t F = (uint64_t)g.H * g.W * g.C;
+  const uint32_t cover = max(s.T + 1, n_slots);
+  hipLaunchKernelGGL(fill_stream_rows, dim3((cover + 255) / 256), dim3(256), 0, st, jobs, group_jobs,
+                     group_off, slots, s.proto, F, s.ks_stride, s.T, groups, s.G, n_slots);
+  BatchArgs a{};
+  a.jobs = jobs;
+  a.group_jobs = group_jobs;
+  a.group_off = group_off;
+  a.slots = slots;
+  a.scratch = s.scratch;
+  a.scratch_stride = (uint64_t)g.H * g.W * 4;
+  a.counters = s.counters;
+  a.err = s.err;
+  a.n_slots = n_slots;
+  a.groups = groups;
+  a.spin_limit = s.spin_limit;
+  return launch_batch_rounds(a, g.C, s.KQ, true, skew::kThreads, s.lds, st);
+}
+
 uint32_t batch_resident_slots(uint32_t C, uint32_t KQ, bool rows, uint32_t threads, size_t lds,
                               int device, uint32_t reserve_cus, uint32_t min_wgs) {
   int per_cu = 0, cus = 0;

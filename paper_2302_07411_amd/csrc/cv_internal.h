@@ -211,6 +211,26 @@ hipError_t launch_batch_rounds(const BatchArgs& a, uint32_t C, uint32_t KQ, bool
 // would remain.
 uint32_t batch_resident_slots(uint32_t C, uint32_t KQ, bool rows, uint32_t threads, size_t lds,
                               int device, uint32_t reserve_cus = 0, uint32_t min_wgs = 1);
+// The row-run batch kernel over T frames of one stream (a single stream's
+// decryption where a band exceeds one LDS tile).  Its tables -- T jobs, the
+// group lists (group q takes frames q, q + groups, ...) and n_slots slots
+// (groups of G workgroups, XCD-aware as above) -- are written into `tables`
+// (stream_rows_table_bytes) by a kernel, so the launch reads no host memory.
+struct StreamRows {
+  BatchJob proto;          // frame 0's job; frame t's buffers are t frames further on
+  uint64_t ks_stride;      // keystream bytes per frame
+  uint32_t T, groups, G, KQ;
+  size_t lds;              // batch_rows_lds_bytes of the job
+  uint8_t* tables;
+  uint8_t* scratch;        // two pixel-word frames per group
+  uint32_t* counters;      // 128 bytes per group
+  uint32_t* err;
+  uint32_t spin_limit;
+};
+size_t stream_rows_table_bytes(uint32_t T, uint32_t n_slots);
+uint32_t stream_rows_slots(uint32_t groups, uint32_t G);  // n_slots of a launch
+hipError_t launch_stream_rows(const StreamRows& s, hipStream_t st);
+
 // Row-run batch kernel: decryption tile rows for geometry g (0 = does not
 // fit) and the LDS a job needs in either direction.
 uint32_t batch_unskew_tile_rows(const Geom& g, size_t lds_max);

@@ -35,6 +35,15 @@ struct cv_key {
   uint32_t tile_skew = 0;      // rows per LDS tile of the row-run encryption kernel (0 = n/a)
   uint32_t fused_cap_skew = 0; // its resident capacity in groups
   uint32_t fused_cap_unskew = 0;  // resident groups of the row-run decryption kernel (0 = n/a)
+  // decryption where a band exceeds one LDS tile: the row-run batch kernel
+  // over the key's frames, tile by tile (0 = n/a)
+  uint32_t rows_tile_dec = 0;  // its LDS tile rows
+  uint32_t rows_G = 0;         // workgroups per group
+  uint32_t rows_KQ = 0;        // kernel instance (the run width of its encryption code)
+  size_t rows_lds = 0;
+  uint32_t fused_cap_rows = 0; // its resident capacity in groups
+  uint8_t* d_rows_tables = nullptr;  // its device-written job and slot tables
+  size_t rows_tables_cap = 0;
   uint8_t* d_fscratch = nullptr;
   uint32_t* d_counters = nullptr;
   uint32_t* d_err = nullptr;
@@ -181,9 +190,12 @@ bool use_pw(const cv_key* k, const uint8_t* in, const uint8_t* out, const uint8_
 uint32_t fused_group_cap(const cv_key* k, bool decrypt);
 // One fused launch over T frames on an explicit workspace (shift tables,
 // exchange frames of `groups` groups, barrier counters, error word).
+// `rows_tables` (T frames' tables of the row-run batch kernel, or null:
+// then decryption with bands over one LDS tile takes the pixel-word kernel).
 cv_status launch_fused_ws(const cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
                           const uint8_t* ks, uint32_t T, const uint32_t* gm, uint8_t* fscratch,
-                          uint32_t* counters, uint32_t* err, uint32_t groups, hipStream_t st);
+                          uint32_t* counters, uint32_t* err, uint32_t groups, hipStream_t st,
+                          uint8_t* rows_tables = nullptr);
 // The byte round kernels over T frames on an explicit workspace (shift
 // tables, one T-frame scratch buffer); `timed` records profiling events.
 cv_status run_rounds_bytes_ws(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
