@@ -2,9 +2,9 @@
 encrypted or decrypted one call at a time from a ring of buffer slots, each
 call replaying the graph captured for its slot, must equal the oracle frame
 by frame -- with eager work of another key between the replays, for the
-plain and the fused round paths, the byte kernels, calls of several
-internal batches, a 2DLASM key, and after the launch shape changes (which
-drops the graphs)."""
+plain and the fused round paths (also bands over one LDS tile), the byte
+kernels, calls of several internal batches, a 2DLASM key, and after the
+launch shape changes (which drops the graphs)."""
 import numpy as np
 import pytest
 
@@ -30,6 +30,9 @@ CASES = [
     ("rgb768-fused", 768, 768, 3, 16, 5, "fused"),
     ("rgb768-plain", 768, 768, 3, 16, 5, "plain"),
     ("rgb48-fused", 48, 48, 3, 8, 5, "fused"),
+    # bands of 32 rows of 2048 pixels exceed one LDS tile: decryption by the
+    # row-run multi-stream kernel with device-written tables
+    ("wide2048-fused", 64, 2048, 3, 2, 5, "fused"),
     ("odd-bytes", 31, 17, 3, 7, 4, "plain"),
 ]
 
