@@ -40,7 +40,12 @@
  * (thread local) describes the failure.  Frame and keystream buffers are
  * DEVICE pointers owned by the caller; `stream` is a hipStream_t (NULL = the
  * null stream).  Calls that take a stream are asynchronous and
- * stream-ordered.  A key is not thread-safe.
+ * stream-ordered.  A key is not thread-safe.  Successive calls on one key
+ * may take different streams: a call on another stream than the key's last
+ * call waits for that call's work (the key's generator state and workspace
+ * are shared).  A cv_batch_run tick likewise waits for its keys' earlier
+ * calls; a call on a key after a tick that used it, on another stream than
+ * the tick's, must be ordered by the caller (cv_batch_sync, or an event).
  *
  * Asynchronous device errors.  A fused launch whose group barrier times out
  * (or finds a group spread over XCDs) and a 2DLASM sine that cannot be

@@ -380,6 +380,7 @@ cv_status ensure_rows_tables(cv_key* k, uint32_t T) {
   drop_graphs(k);                  // captured launches point at the old tables
   CV_HIP(hipDeviceSynchronize());  // which may still be read
   if (k->d_rows_tables) (void)hipFree(k->d_rows_tables);
+  if (k->order_ev) (void)hipEventDestroy(k->order_ev);
   k->d_rows_tables = nullptr;
   k->rows_tables_cap = 0;
   if (hipMalloc(&k->d_rows_tables, bytes) != hipSuccess) {
@@ -635,7 +636,7 @@ cv_status ensure_ahead(cv_key* k) {
   cv_key::Ahead& a = k->ahead;
   if (a.s) return CV_OK;
   hipError_t e = hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking);
-  for (hipEvent_t* ev : {&a.ks_ready, &a.done[0], &a.done[1], &a.last})
+  for (hipEvent_t* ev : {&a.ks_ready, &a.done[0], &a.done[1]})
     if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
   const size_t nd = 2ull * k->g.n;
   for (int i = 0; i < 2 && e == hipSuccess; i++) {
@@ -688,9 +689,6 @@ cv_status crypt_batch_ahead(cv_key* k, bool decrypt, const uint8_t* in, uint8_t*
   const size_t bytes = (size_t)T * k->g.r * k->F, states = 2ull * k->g.n * sizeof(double);
   if ((s = ahead_buffer(k, buf, bytes)) != CV_OK) return s;
   if ((s = ahead_buffer(k, 1 - buf, bytes)) != CV_OK) return s;
-  // a call on another stream than the last one starts after the last one's
-  // work there (which reads the buffers and shadow copies reused below)
-  if (a.has_last && a.last_stream != st) CV_HIP(hipStreamWaitEvent(st, a.last, 0));
   if ((s = upload_shift_tables(k, s_c, T, st)) != CV_OK) return s;
   if (hit) {
     CV_HIP(hipStreamWaitEvent(st, a.done[a.shadow], 0));
@@ -703,9 +701,6 @@ cv_status crypt_batch_ahead(cv_key* k, bool decrypt, const uint8_t* in, uint8_t*
   CV_HIP(hipEventRecord(a.ks_ready, st));
   if ((s = run_rounds(k, decrypt, in, out, a.d_ks[buf], T, st)) != CV_OK) return s;
   k->frame_index += T;
-  CV_HIP(hipEventRecord(a.last, st));
-  a.last_stream = st;
-  a.has_last = true;
   CV_HIP(hipStreamWaitEvent(a.s, a.ks_ready, 0));
   {
     Timed tm(k, a.s);
@@ -723,6 +718,31 @@ cv_status crypt_batch_ahead(cv_key* k, bool decrypt, const uint8_t* in, uint8_t*
   return CV_OK;
 }
 
+cv_status key_order_wait(const cv_key* k, hipStream_t st) {
+  if (k->order_has && k->order_stream != st) CV_HIP(hipStreamWaitEvent(st, k->order_ev, 0));
+  return CV_OK;
+}
+
+cv_status key_order_mark(cv_key* k, hipStream_t st) {
+  if (!k->order_ev) CV_HIP(hipEventCreateWithFlags(&k->order_ev, hipEventDisableTiming));
+  CV_HIP(hipEventRecord(k->order_ev, st));
+  k->order_stream = st;
+  k->order_has = true;
+  return CV_OK;
+}
+
+// The end of a call that took stream st: mark the key's order there, also
+// behind the work a failed call enqueued (keeping the call's own error).
+cv_status key_order_done(cv_key* k, hipStream_t st, cv_status s) {
+  if (s == CV_OK) return key_order_mark(k, st);
+  const std::string msg = g_last_error;
+  (void)key_order_mark(k, st);
+  return fail(s, msg);
+}
+
+cv_status crypt_frames_ordered(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
+                               const uint32_t* s_c, size_t n, hipStream_t st);
+
 cv_status crypt_frames(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
                        const uint32_t* s_c, size_t n, void* stream) {
   cv_status s = check_frames_args(k, in, out, s_c, n);
@@ -730,6 +750,13 @@ cv_status crypt_frames(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
   if ((s = check_async_errors(k, false)) != CV_OK) return s;
   DeviceGuard dg(k->device);
   hipStream_t st = (hipStream_t)stream;
+  if ((s = key_order_wait(k, st)) != CV_OK) return s;
+  return key_order_done(k, st, crypt_frames_ordered(k, decrypt, in, out, s_c, n, st));
+}
+
+cv_status crypt_frames_ordered(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out,
+                               const uint32_t* s_c, size_t n, hipStream_t st) {
+  cv_status s = CV_OK;
   const size_t B = std::min<size_t>(n, k->batch_frames);
   if ((s = ensure_workspace(k, B)) != CV_OK) return s;
   const bool ahead = k->lookahead && k->map == CV_MAP_PLCM;
@@ -972,6 +999,7 @@ void cv_key_free(cv_key* k) {
   if (k->d_fscratch) (void)hipFree(k->d_fscratch);
   if (k->d_counters) (void)hipFree(k->d_counters);
   if (k->d_rows_tables) (void)hipFree(k->d_rows_tables);
+  if (k->order_ev) (void)hipEventDestroy(k->order_ev);
   if (k->d_err) (void)hipFree(k->d_err);
   if (k->h_err) (void)hipHostFree(k->h_err);
   if (k->err_copied) (void)hipEventDestroy(k->err_copied);
@@ -987,7 +1015,6 @@ void cv_key_free(cv_key* k) {
     if (a.done[i]) (void)hipEventDestroy(a.done[i]);
   }
   if (a.ks_ready) (void)hipEventDestroy(a.ks_ready);
-  if (a.last) (void)hipEventDestroy(a.last);
   if (a.s) (void)hipStreamDestroy(a.s);
   delete k;
 }
@@ -1278,9 +1305,10 @@ cv_status cv_keystream_frames(cv_key* k, uint8_t* ks, size_t n, void* stream) {
   cv_status s = check_async_errors(k, false);
   if (s != CV_OK) return s;
   DeviceGuard dg(k->device);
-  if ((s = launch_keystream(k, ks, (uint32_t)n, (hipStream_t)stream)) != CV_OK) return s;
-  k->frame_index += n;
-  return CV_OK;
+  hipStream_t st = (hipStream_t)stream;
+  if ((s = key_order_wait(k, st)) != CV_OK) return s;
+  if ((s = launch_keystream(k, ks, (uint32_t)n, st)) == CV_OK) k->frame_index += n;
+  return key_order_done(k, st, s);
 }
 
 cv_status cv_apply_rounds(cv_key* k, int decrypt, const uint8_t* in, uint8_t* out,
@@ -1296,14 +1324,14 @@ cv_status cv_apply_rounds(cv_key* k, int decrypt, const uint8_t* in, uint8_t* ou
   hipStream_t st = (hipStream_t)stream;
   const size_t B = std::min<size_t>(n, k->batch_frames);
   if ((s = ensure_workspace(k, B)) != CV_OK) return s;
-  for (size_t f0 = 0; f0 < n; f0 += B) {
+  if ((s = key_order_wait(k, st)) != CV_OK) return s;
+  for (size_t f0 = 0; f0 < n && s == CV_OK; f0 += B) {
     const uint32_t T = (uint32_t)std::min(B, n - f0);
-    if ((s = upload_shift_tables(k, s_c + f0, T, st)) != CV_OK) return s;
-    if ((s = run_rounds(k, decrypt != 0, in + f0 * k->F, out + f0 * k->F,
-                        ks + f0 * (uint64_t)k->g.r * k->F, T, st)) != CV_OK)
-      return s;
+    if ((s = upload_shift_tables(k, s_c + f0, T, st)) == CV_OK)
+      s = run_rounds(k, decrypt != 0, in + f0 * k->F, out + f0 * k->F,
+                     ks + f0 * (uint64_t)k->g.r * k->F, T, st);
   }
-  return CV_OK;
+  return key_order_done(k, st, s);
 }
 
 }  // extern "C"

@@ -936,6 +936,8 @@ cv_status run_tick(cv_batch* b, const cv_batch_item* items, size_t n_items, hipS
   NextPrefetch np;
   ahead = ahead && plan_prefetch(b, items, eligible, hit ? &prev : nullptr, 1 - buf, np);
   if ((s = order_after_last(b, st)) != CV_OK) return s;
+  for (size_t i : eligible)  // after the keys' own calls on other streams
+    if ((s = key_order_wait(items[i].key, st)) != CV_OK) return s;
   for (size_t i : fallback) {
     const cv_batch_item& it = items[i];
     if ((s = crypt_frames(it.key, it.decrypt != 0, it.in, it.out, it.s_c, it.n_frames, st)) != CV_OK)

@@ -99,9 +99,6 @@ struct cv_key {
     hipStream_t s = nullptr;           // private stream (default priority)
     hipEvent_t ks_ready = nullptr;     // call's stream: keystream ready, shadow states copied
     hipEvent_t done[2] = {};           // per shadow copy: the last lookahead using it is complete
-    hipEvent_t last = nullptr;         // end of the last batch's work on its call's stream
-    hipStream_t last_stream = nullptr;
-    bool has_last = false;
     bool used[2] = {};
     double* d_shadow[2] = {};
     cv::PlcmChain* d_chains[2] = {};   // the key's chains with their states in shadow 0 / 1
@@ -113,6 +110,12 @@ struct cv_key {
     uint32_t T = 0;
   } ahead;
   uint64_t ahead_hits = 0, ahead_misses = 0;
+  // Calls share the generator state and the workspace: the stream of the
+  // key's last call that took a stream, and an event behind that call's work
+  // (a call on another stream first waits for it).
+  hipEvent_t order_ev = nullptr;
+  hipStream_t order_stream = nullptr;
+  bool order_has = false;
   // event profiling
   bool profiling = false;
   struct Span {
@@ -182,6 +185,10 @@ bool pw_eligible(const cv_key* k, const uint8_t* in, const uint8_t* out, uint32_
 // Key-path helpers (plain or fused rounds of one key, its workspace).
 cv_status ensure_workspace(cv_key* k, size_t frames);
 cv_status upload_shift_tables(cv_key* k, const uint32_t* s_c, size_t T, hipStream_t st);
+// Order a call of the key on st after its last call on another stream; after
+// the call, note st and record the key's event there.
+cv_status key_order_wait(const cv_key* k, hipStream_t st);
+cv_status key_order_mark(cv_key* k, hipStream_t st);
 cv_status run_rounds(cv_key* k, bool decrypt, const uint8_t* in, uint8_t* out, const uint8_t* ks,
                      uint32_t T, hipStream_t st);
 // Pixel-word kernels apply to this key and these buffers.
