@@ -380,7 +380,6 @@ cv_status ensure_rows_tables(cv_key* k, uint32_t T) {
   drop_graphs(k);                  // captured launches point at the old tables
   CV_HIP(hipDeviceSynchronize());  // which may still be read
   if (k->d_rows_tables) (void)hipFree(k->d_rows_tables);
-  if (k->order_ev) (void)hipEventDestroy(k->order_ev);
   k->d_rows_tables = nullptr;
   k->rows_tables_cap = 0;
   if (hipMalloc(&k->d_rows_tables, bytes) != hipSuccess) {
