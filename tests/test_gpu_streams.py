@@ -3,8 +3,8 @@ key's generator state and workspace are shared, so each call must start
 after the key's last call on the other stream.  Every frame equals the
 oracle's, on both round paths, with and without graph replay, for
 encryption, decryption, and a keystream call followed by the rounds on the
-other stream; and a multi-stream tick waits for its keys' calls on another
-stream."""
+other stream, and decryption calls that grow the key's workspace; and a
+multi-stream tick waits for its keys' calls on another stream."""
 import numpy as np
 import pytest
 
@@ -102,4 +102,35 @@ def test_batch_tick_waits_for_the_keys_calls(B):
     got = dst.cpu().numpy().reshape(want.shape)
     assert np.array_equal(got, want), f"{np.count_nonzero(got != want)} bytes differ"
     bt.close()
+    k.close()
+
+
+def test_growing_calls_of_wide_decryption_on_two_streams(B):
+    """Bands of 2048-pixel rows over one LDS tile: decryption by the row-run
+    multi-stream kernel, whose tables grow with the frames of a call; calls
+    of 1, then 4, then 2 frames on two streams in turn."""
+    h, w, c, n, r = 64, 2048, 3, 2, 5
+    f = h * w * c
+    pm = plcm_key(n, 9100)
+    counts = [1, 4, 2]
+    total = sum(counts)
+    frames = uniform_frames(h, w, c, total, 9101)
+    s_c = confusion_seeds(total, 9102)
+    want = oracle.PlcmKey(h, w, c, n, r, pm).decrypt(frames, s_c)
+    k = B.Key(h, w, c, n, r, pm)
+    k.set_path(B.CV_PATH_FUSED)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    src = _dev(frames)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    print("[case] wide decryption, growing calls on two streams", flush=True)
+    t0 = 0
+    for i, cnt in enumerate(counts):
+        sl = slice(t0 * f, (t0 + cnt) * f)
+        k.decrypt(src[sl], dst[sl], s_c[t0:t0 + cnt], stream=streams[i % 2])
+        t0 += cnt
+    k.sync()
+    torch.cuda.synchronize()
+    got = dst.cpu().numpy().reshape(want.shape)
+    assert np.array_equal(got, want), f"{np.count_nonzero(got != want)} bytes differ"
     k.close()
