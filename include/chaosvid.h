@@ -46,6 +46,7 @@
  * are shared).  A cv_batch_run tick likewise waits for its keys' earlier
  * calls; a call on a key after a tick that used it, on another stream than
  * the tick's, must be ordered by the caller (cv_batch_sync, or an event).
+ * Work captured into a caller's own graph is ordered by the caller.
  *
  * Asynchronous device errors.  A fused launch whose group barrier times out
  * (or finds a group spread over XCDs) and a 2DLASM sine that cannot be

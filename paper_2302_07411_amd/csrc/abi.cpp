@@ -717,12 +717,29 @@ cv_status crypt_batch_ahead(cv_key* k, bool decrypt, const uint8_t* in, uint8_t*
   return CV_OK;
 }
 
+// A stream that a caller is capturing into a graph of its own is left alone:
+// the captured work runs when the caller launches the graph, which the
+// caller orders.
+bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return cs != hipStreamCaptureStatusNone;
+}
+
 cv_status key_order_wait(const cv_key* k, hipStream_t st) {
-  if (k->order_has && k->order_stream != st) CV_HIP(hipStreamWaitEvent(st, k->order_ev, 0));
+  if (k->order_has && k->order_stream != st && !capturing(st))
+    CV_HIP(hipStreamWaitEvent(st, k->order_ev, 0));
   return CV_OK;
 }
 
 cv_status key_order_mark(cv_key* k, hipStream_t st) {
+  if (capturing(st)) {
+    k->order_has = false;
+    return CV_OK;
+  }
   if (!k->order_ev) CV_HIP(hipEventCreateWithFlags(&k->order_ev, hipEventDisableTiming));
   CV_HIP(hipEventRecord(k->order_ev, st));
   k->order_stream = st;
