@@ -147,7 +147,7 @@ typedef struct {
                               are kept, the least recently used dropped.  0: every kernel
                               launched on its own.  Ignored while profiling is on, and with
                               lookahead. */
-  uint32_t lookahead;      /* 1 (PLCM keys; ignored for 2DLASM keys): after each internal
+  uint32_t lookahead;      /* 1 (PLCM and 2DLASM keys): after each internal
                               batch of T frames, generate the next T frames' keystream on a
                               private stream from a copy of the generator states made on the
                               call's stream (the keystream depends only on them, Algorithm 2),

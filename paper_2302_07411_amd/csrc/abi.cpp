@@ -630,6 +630,8 @@ cv_status crypt_batch_graph(cv_key* k, bool decrypt, const uint8_t* in, uint8_t*
 // ------------------------------------------------ keystream lookahead ---
 hipError_t copy_sync(void* dst, const void* src, size_t bytes, hipMemcpyKind kind);
 
+size_t state_doubles(const cv_key* k);
+
 // Stream, events, shadow states and the chain tables that point at them.
 cv_status ensure_ahead(cv_key* k) {
   cv_key::Ahead& a = k->ahead;
@@ -637,14 +639,25 @@ cv_status ensure_ahead(cv_key* k) {
   hipError_t e = hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking);
   for (hipEvent_t* ev : {&a.ks_ready, &a.done[0], &a.done[1]})
     if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
-  const size_t nd = 2ull * k->g.n;
+  const size_t nd = state_doubles(k);
   for (int i = 0; i < 2 && e == hipSuccess; i++) {
     e = hipMalloc(&a.d_shadow[i], nd * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&a.d_chains[i], k->h_chains.size() * sizeof(cv::PlcmChain));
     if (e != hipSuccess) break;
-    std::vector<cv::PlcmChain> ch = k->h_chains;
-    for (cv::PlcmChain& c : ch) c.state = a.d_shadow[i] + (c.state - k->d_state);
-    e = copy_sync(a.d_chains[i], ch.data(), ch.size() * sizeof(cv::PlcmChain), hipMemcpyHostToDevice);
+    if (k->map == CV_MAP_2DLASM) {
+      std::vector<cv::LasmChain> ch = k->h_lchains;
+      for (cv::LasmChain& c : ch) c.state = a.d_shadow[i] + (c.state - k->d_state);
+      e = hipMalloc(&a.d_lchains[i], ch.size() * sizeof(cv::LasmChain));
+      if (e == hipSuccess)
+        e = copy_sync(a.d_lchains[i], ch.data(), ch.size() * sizeof(cv::LasmChain),
+                      hipMemcpyHostToDevice);
+    } else {
+      std::vector<cv::PlcmChain> ch = k->h_chains;
+      for (cv::PlcmChain& c : ch) c.state = a.d_shadow[i] + (c.state - k->d_state);
+      e = hipMalloc(&a.d_chains[i], ch.size() * sizeof(cv::PlcmChain));
+      if (e == hipSuccess)
+        e = copy_sync(a.d_chains[i], ch.data(), ch.size() * sizeof(cv::PlcmChain),
+                      hipMemcpyHostToDevice);
+    }
   }
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -685,13 +698,15 @@ cv_status crypt_batch_ahead(cv_key* k, bool decrypt, const uint8_t* in, uint8_t*
   if (a.valid) (hit ? k->ahead_hits : k->ahead_misses)++;
   a.valid = false;
   const int buf = hit ? a.target : (a.target == 0 ? 1 : 0), nsh = a.shadow == 0 ? 1 : 0;
-  const size_t bytes = (size_t)T * k->g.r * k->F, states = 2ull * k->g.n * sizeof(double);
+  const size_t bytes = (size_t)T * k->g.r * k->F, states = state_doubles(k) * sizeof(double);
   if ((s = ahead_buffer(k, buf, bytes)) != CV_OK) return s;
   if ((s = ahead_buffer(k, 1 - buf, bytes)) != CV_OK) return s;
   if ((s = upload_shift_tables(k, s_c, T, st)) != CV_OK) return s;
   if (hit) {
     CV_HIP(hipStreamWaitEvent(st, a.done[a.shadow], 0));
     CV_HIP(hipMemcpyAsync(k->d_state, a.d_shadow[a.shadow], states, hipMemcpyDeviceToDevice, st));
+    // a 2DLASM lookahead's undecided sine (the key's error word) is read back here
+    if (k->map == CV_MAP_2DLASM && (s = queue_err_readback(k, st)) != CV_OK) return s;
   } else if ((s = launch_keystream(k, a.d_ks[buf], T, st)) != CV_OK) {
     return s;
   }
@@ -703,7 +718,10 @@ cv_status crypt_batch_ahead(cv_key* k, bool decrypt, const uint8_t* in, uint8_t*
   CV_HIP(hipStreamWaitEvent(a.s, a.ks_ready, 0));
   {
     Timed tm(k, a.s);
-    CV_HIP(cv::launch_prbg_plcm(a.d_chains[nsh], k->g.n, a.d_ks[1 - buf], T, prbg_variant(k), a.s));
+    if (k->map == CV_MAP_2DLASM)
+      CV_HIP(cv::launch_prbg_lasm(a.d_lchains[nsh], k->g.n, a.d_ks[1 - buf], T, 0, k->d_err, a.s));
+    else
+      CV_HIP(cv::launch_prbg_plcm(a.d_chains[nsh], k->g.n, a.d_ks[1 - buf], T, prbg_variant(k), a.s));
     tm.end(0, prbg_steps(k, T));
   }
   CV_HIP(hipEventRecord(a.done[nsh], a.s));
@@ -775,7 +793,7 @@ cv_status crypt_frames_ordered(cv_key* k, bool decrypt, const uint8_t* in, uint8
   cv_status s = CV_OK;
   const size_t B = std::min<size_t>(n, k->batch_frames);
   if ((s = ensure_workspace(k, B)) != CV_OK) return s;
-  const bool ahead = k->lookahead && k->map == CV_MAP_PLCM;
+  const bool ahead = k->lookahead;
   const bool graph = k->use_graph && !k->profiling && !ahead;
   for (size_t f0 = 0; f0 < n; f0 += B) {
     const uint32_t T = (uint32_t)std::min(B, n - f0);
@@ -1027,6 +1045,7 @@ void cv_key_free(cv_key* k) {
   for (int i = 0; i < 2; i++) {
     if (a.d_shadow[i]) (void)hipFree(a.d_shadow[i]);
     if (a.d_chains[i]) (void)hipFree(a.d_chains[i]);
+    if (a.d_lchains[i]) (void)hipFree(a.d_lchains[i]);
     if (a.d_ks[i]) (void)hipFree(a.d_ks[i]);
     if (a.done[i]) (void)hipEventDestroy(a.done[i]);
   }

@@ -102,6 +102,7 @@ struct cv_key {
     bool used[2] = {};
     double* d_shadow[2] = {};
     cv::PlcmChain* d_chains[2] = {};   // the key's chains with their states in shadow 0 / 1
+    cv::LasmChain* d_lchains[2] = {};  // the same for a 2DLASM key
     uint8_t* d_ks[2] = {};
     size_t ks_cap[2] = {};
     bool valid = false;                // the fields below describe the last lookahead launched

@@ -5,8 +5,8 @@ at a time must equal the oracle frame by frame, whether a call takes the
 lookahead or not: calls arriving after the lookahead finished, calls queued
 back to back, calls that change the frame count, a keystream call or a state
 set between calls, calls of several internal batches, calls on two streams
-in turn, both round paths, and a 2DLASM key (for which the option is
-ignored)."""
+in turn, both round paths, and 2DLASM keys (their generator runs on the
+private stream the same way)."""
 import numpy as np
 import pytest
 
@@ -144,19 +144,41 @@ def test_lookahead_calls_on_alternating_streams(B):
     k.close()
 
 
-def test_lookahead_ignored_for_2dlasm(B):
-    H, W, C, n, r, T = 48, 48, 3, 4, 3, 3
+@pytest.mark.parametrize("decrypt", [False, True])
+def test_lookahead_for_2dlasm(B, decrypt):
+    """A 2DLASM key: one frame per call, waited for or queued, then a call of
+    two frames (a miss) and a state set from outside (a miss); every frame
+    equals the oracle's and the key's state follows the oracle's."""
+    H, W, C, n, r = 48, 64, 3, 4, 3
+    print(f"[case] 2DLASM lookahead decrypt={decrypt}", flush=True)
     pm = lasm_key(n, 7500)
     k = B.Key(H, W, C, n, r, pm, map=B.CV_MAP_2DLASM)
+    k.set_path(B.CV_PATH_FUSED)
     k.set_launch(lookahead=1)
     ref = oracle.LasmKey(H, W, C, n, r, pm)
-    for t in range(T):
-        frames = uniform_frames(H, W, C, 1, 7600 + t)
-        s_c = confusion_seeds(1, 7700 + t)
-        want = ref.encrypt(frames, s_c)
+    op = ref.decrypt if decrypt else ref.encrypt
+    call = k.decrypt if decrypt else k.encrypt
+    plan = [(1, True, None), (1, True, None), (1, False, None), (2, True, None),
+            (1, True, "set_state"), (1, True, None)]
+    for i, (T, wait, event) in enumerate(plan):
+        if event == "set_state":
+            x, fi = k.get_state()
+            xs = np.ascontiguousarray(np.clip(x * 0.5 + 0.25, 0.0, 1.0))
+            k.set_state(xs, fi)
+            ref.x1, ref.y1, ref.x2, ref.y2 = (np.ascontiguousarray(xs[:, m]) for m in range(4))
+        if wait:
+            torch.cuda.synchronize()
+        frames = uniform_frames(H, W, C, T, 7600 + i)
+        s_c = confusion_seeds(T, 7700 + i)
+        want = op(frames, s_c)
         src = _dev(frames)
         dst = torch.empty_like(src)
-        k.encrypt(src, dst, s_c)
-        assert np.array_equal(_host(dst, want.shape), want)
-    assert k.lookahead_counts() == (0, 0)
+        call(src, dst, s_c)
+        got = _host(dst, want.shape)
+        assert np.array_equal(got, want), f"call {i}: {np.count_nonzero(got != want)} bytes differ"
+    # hits: calls 1 and 2; misses: call 3 (two frames after one), call 4 (after set_state);
+    # call 5 follows the set_state call's lookahead: a hit
+    assert k.lookahead_counts() == (3, 2), k.lookahead_counts()
+    x, _ = k.get_state()
+    assert np.array_equal(x, ref.state())
     k.close()
