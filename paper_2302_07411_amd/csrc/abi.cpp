@@ -636,7 +636,22 @@ size_t state_doubles(const cv_key* k);
 cv_status ensure_ahead(cv_key* k) {
   cv_key::Ahead& a = k->ahead;
   if (a.s) return CV_OK;
-  hipError_t e = hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking);
+  // A stream with a compute-unit mask (here: every CU) gets a hardware queue
+  // of its own; a plain stream may share one with the calls' stream, and then
+  // work queued on it after the lookahead waits for the lookahead.
+  hipError_t e = hipSuccess;
+  {
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, k->device);
+    std::vector<uint32_t> mask((std::max(cus, 1) + 31) / 32, 0xFFFFFFFFu);
+    if (cus % 32) mask.back() = (1u << (cus % 32)) - 1;
+    if (e == hipSuccess) e = hipExtStreamCreateWithCUMask(&a.s, (uint32_t)mask.size(), mask.data());
+    if (e != hipSuccess) {  // masks not supported: a plain stream
+      (void)hipGetLastError();
+      a.s = nullptr;
+      e = hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking);
+    }
+  }
   for (hipEvent_t* ev : {&a.ks_ready, &a.done[0], &a.done[1]})
     if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
   const size_t nd = state_doubles(k);
