@@ -155,12 +155,11 @@ typedef struct {
                               rounds.  The next batch takes it when it starts at the predicted
                               frame with the same T and the state was not set in between;
                               otherwise it is dropped.  The private stream never touches the
-                              key's state.  It has a hardware queue of its own (a stream with
-                              a compute-unit mask of every CU), so work on other streams never
-                              queues behind a lookahead; like every such stream it is ordered
-                              with the legacy null stream (null-stream work waits for a
-                              lookahead in progress).  Costs two keystream buffers of T
-                              frames.  0: off */
+                              key's state.  Beside a call stream other than the null stream
+                              it is a stream with a hardware queue of its own (a compute-unit
+                              mask of every CU), so the call stream's later work never queues
+                              behind a lookahead; beside the null stream it is a non-blocking
+                              stream.  Costs two keystream buffers of T frames.  0: off */
 } cv_launch;
 
 /* Version of the cipher readings above (CV_SPEC_VERSION). */

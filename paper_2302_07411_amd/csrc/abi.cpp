@@ -633,42 +633,57 @@ hipError_t copy_sync(void* dst, const void* src, size_t bytes, hipMemcpyKind kin
 size_t state_doubles(const cv_key* k);
 
 // Stream, events, shadow states and the chain tables that point at them.
-cv_status ensure_ahead(cv_key* k) {
-  cv_key::Ahead& a = k->ahead;
-  if (a.s) return CV_OK;
-  // A stream with a compute-unit mask (here: every CU) gets a hardware queue
-  // of its own; a plain stream may share one with the calls' stream, and then
-  // work queued on it after the lookahead waits for the lookahead.
-  hipError_t e = hipSuccess;
-  {
-    int cus = 0;
-    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, k->device);
-    std::vector<uint32_t> mask((std::max(cus, 1) + 31) / 32, 0xFFFFFFFFu);
-    if (cus % 32) mask.back() = (1u << (cus % 32)) - 1;
-    if (e == hipSuccess) e = hipExtStreamCreateWithCUMask(&a.s, (uint32_t)mask.size(), mask.data());
-    if (e != hipSuccess) {  // masks not supported: a plain stream
+cv_status side_stream(SideStreams& ss, int device, hipStream_t st, hipStream_t* out) {
+  const bool null_stream = st == nullptr || st == hipStreamLegacy;
+  hipStream_t& s = null_stream ? ss.plain : ss.own;
+  if (!s) {
+    hipError_t e = hipErrorNotSupported;
+    if (!null_stream) {
+      int cus = 0;
+      e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+      std::vector<uint32_t> mask((std::max(cus, 1) + 31) / 32, 0xFFFFFFFFu);
+      if (cus % 32) mask.back() = (1u << (cus % 32)) - 1;
+      if (e == hipSuccess) e = hipExtStreamCreateWithCUMask(&s, (uint32_t)mask.size(), mask.data());
+    }
+    if (e != hipSuccess) {  // beside the null stream, or masks not supported
       (void)hipGetLastError();
-      a.s = nullptr;
-      e = hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking);
+      s = nullptr;
+      CV_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     }
   }
+  ss.last = s;
+  *out = s;
+  return CV_OK;
+}
+
+void side_streams_free(SideStreams& ss) {
+  if (ss.plain) (void)hipStreamDestroy(ss.plain);
+  if (ss.own) (void)hipStreamDestroy(ss.own);
+  ss = SideStreams{};
+}
+
+cv_status ensure_ahead(cv_key* k) {
+  cv_key::Ahead& a = k->ahead;
+  if (a.ready) return CV_OK;
+  // (after a failure, a later call completes what is missing)
+  hipError_t e = hipSuccess;
   for (hipEvent_t* ev : {&a.ks_ready, &a.done[0], &a.done[1]})
-    if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+    if (e == hipSuccess && !*ev) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
   const size_t nd = state_doubles(k);
   for (int i = 0; i < 2 && e == hipSuccess; i++) {
-    e = hipMalloc(&a.d_shadow[i], nd * sizeof(double));
+    if (!a.d_shadow[i]) e = hipMalloc(&a.d_shadow[i], nd * sizeof(double));
     if (e != hipSuccess) break;
     if (k->map == CV_MAP_2DLASM) {
       std::vector<cv::LasmChain> ch = k->h_lchains;
       for (cv::LasmChain& c : ch) c.state = a.d_shadow[i] + (c.state - k->d_state);
-      e = hipMalloc(&a.d_lchains[i], ch.size() * sizeof(cv::LasmChain));
+      if (!a.d_lchains[i]) e = hipMalloc(&a.d_lchains[i], ch.size() * sizeof(cv::LasmChain));
       if (e == hipSuccess)
         e = copy_sync(a.d_lchains[i], ch.data(), ch.size() * sizeof(cv::LasmChain),
                       hipMemcpyHostToDevice);
     } else {
       std::vector<cv::PlcmChain> ch = k->h_chains;
       for (cv::PlcmChain& c : ch) c.state = a.d_shadow[i] + (c.state - k->d_state);
-      e = hipMalloc(&a.d_chains[i], ch.size() * sizeof(cv::PlcmChain));
+      if (!a.d_chains[i]) e = hipMalloc(&a.d_chains[i], ch.size() * sizeof(cv::PlcmChain));
       if (e == hipSuccess)
         e = copy_sync(a.d_chains[i], ch.data(), ch.size() * sizeof(cv::PlcmChain),
                       hipMemcpyHostToDevice);
@@ -678,6 +693,7 @@ cv_status ensure_ahead(cv_key* k) {
     (void)hipGetLastError();
     return fail(e == hipErrorOutOfMemory ? CV_E_NOMEM : CV_E_HIP, "lookahead set-up failed");
   }
+  a.ready = true;
   return CV_OK;
 }
 
@@ -730,16 +746,18 @@ cv_status crypt_batch_ahead(cv_key* k, bool decrypt, const uint8_t* in, uint8_t*
   CV_HIP(hipEventRecord(a.ks_ready, st));
   if ((s = run_rounds(k, decrypt, in, out, a.d_ks[buf], T, st)) != CV_OK) return s;
   k->frame_index += T;
-  CV_HIP(hipStreamWaitEvent(a.s, a.ks_ready, 0));
+  hipStream_t ps = nullptr;
+  if ((s = side_stream(a.side, k->device, st, &ps)) != CV_OK) return s;
+  CV_HIP(hipStreamWaitEvent(ps, a.ks_ready, 0));
   {
-    Timed tm(k, a.s);
+    Timed tm(k, ps);
     if (k->map == CV_MAP_2DLASM)
-      CV_HIP(cv::launch_prbg_lasm(a.d_lchains[nsh], k->g.n, a.d_ks[1 - buf], T, 0, k->d_err, a.s));
+      CV_HIP(cv::launch_prbg_lasm(a.d_lchains[nsh], k->g.n, a.d_ks[1 - buf], T, 0, k->d_err, ps));
     else
-      CV_HIP(cv::launch_prbg_plcm(a.d_chains[nsh], k->g.n, a.d_ks[1 - buf], T, prbg_variant(k), a.s));
+      CV_HIP(cv::launch_prbg_plcm(a.d_chains[nsh], k->g.n, a.d_ks[1 - buf], T, prbg_variant(k), ps));
     tm.end(0, prbg_steps(k, T));
   }
-  CV_HIP(hipEventRecord(a.done[nsh], a.s));
+  CV_HIP(hipEventRecord(a.done[nsh], ps));
   a.used[nsh] = true;
   a.target = 1 - buf;
   a.shadow = nsh;
@@ -1065,7 +1083,7 @@ void cv_key_free(cv_key* k) {
     if (a.done[i]) (void)hipEventDestroy(a.done[i]);
   }
   if (a.ks_ready) (void)hipEventDestroy(a.ks_ready);
-  if (a.s) (void)hipStreamDestroy(a.s);
+  side_streams_free(a.side);
   delete k;
 }
 

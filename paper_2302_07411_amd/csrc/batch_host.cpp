@@ -116,7 +116,7 @@ struct Prefetch {
     uint64_t ks_off;     // its keystream in the prefetch's keystream buffer
     uint64_t state_off;  // its generator states in the prefetch's shadow buffer (doubles)
   };
-  hipStream_t s = nullptr;             // private stream (default priority)
+  SideStreams side;                    // private streams (default priority)
   hipEvent_t ks_ready = nullptr;       // tick's stream: keystream generated or adopted, states copied
   hipEvent_t done[2] = {};             // per shadow buffer: the last prefetch using it is complete
   bool used[2] = {};
@@ -781,11 +781,10 @@ cv_status grow_ks(cv_batch* b, int i, uint64_t bytes) {
 
 cv_status ensure_prefetch(cv_batch* b) {
   Prefetch& pf = b->pf;
-  if (pf.s) return CV_OK;
-  hipError_t e = hipStreamCreateWithFlags(&pf.s, hipStreamNonBlocking);
+  hipError_t e = hipSuccess;
   for (hipEvent_t* ev : {&pf.ks_ready, &pf.done[0], &pf.done[1], &pf.copied})
-    if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
-  if (e != hipSuccess) return hip_fail(e, "prefetch stream");
+    if (e == hipSuccess && !*ev) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+  if (e != hipSuccess) return hip_fail(e, "prefetch events");
   return CV_OK;
 }
 
@@ -859,12 +858,19 @@ bool plan_prefetch(cv_batch* b, const cv_batch_item* items, const std::vector<si
   return true;
 }
 
-// Launch the planned prefetch on the prefetch stream: its chain tables go
-// up (after the previous prefetch, which read the same device table), then
-// its keystream launches wait for the tick's stream to have its keystream
-// and the shadow states (pf.ks_ready).
-cv_status launch_prefetch(cv_batch* b, NextPrefetch& np) {
+// Launch the planned prefetch on the private stream beside the tick's
+// stream st: its chain tables go up (after the previous prefetch, which read
+// the same device table: the same stream, or its completion event), then its
+// keystream launches wait for the tick's stream to have its keystream and
+// the shadow states (pf.ks_ready).
+cv_status launch_prefetch(cv_batch* b, NextPrefetch& np, hipStream_t st) {
   Prefetch& pf = b->pf;
+  const hipStream_t prev = pf.side.last;
+  hipStream_t ps = nullptr;
+  cv_status ss = side_stream(pf.side, b->device, st, &ps);
+  if (ss != CV_OK) return ss;
+  if (prev && prev != ps && pf.shadow >= 0 && pf.used[pf.shadow])
+    CV_HIP(hipStreamWaitEvent(ps, pf.done[pf.shadow], 0));
   size_t chain_off[cv::kPrbgVariants], bytes = 0;
   for (int v = 0; v < cv::kPrbgVariants; v++) {
     chain_off[v] = bytes;
@@ -889,26 +895,26 @@ cv_status launch_prefetch(cv_batch* b, NextPrefetch& np) {
   for (int v = 0; v < cv::kPrbgVariants; v++)
     if (!np.chains[v].empty())
       memcpy(pf.h_table + chain_off[v], np.chains[v].data(), np.chains[v].size() * sizeof(cv::PlcmChain));
-  CV_HIP(hipMemcpyAsync(pf.d_table, pf.h_table, bytes, hipMemcpyHostToDevice, pf.s));
-  CV_HIP(hipEventRecord(pf.copied, pf.s));
+  CV_HIP(hipMemcpyAsync(pf.d_table, pf.h_table, bytes, hipMemcpyHostToDevice, ps));
+  CV_HIP(hipEventRecord(pf.copied, ps));
   pf.copy_pending = true;
-  CV_HIP(hipStreamWaitEvent(pf.s, pf.ks_ready, 0));
+  CV_HIP(hipStreamWaitEvent(ps, pf.ks_ready, 0));
   hipEvent_t ta = b->profiling ? pooled(b) : nullptr;
-  if (ta) CV_HIP(hipEventRecord(ta, pf.s));
+  if (ta) CV_HIP(hipEventRecord(ta, ps));
   for (int v = 0; v < cv::kPrbgVariants; v++)
     if (!np.chains[v].empty())
       CV_HIP(cv::launch_prbg_plcm((const cv::PlcmChain*)(pf.d_table + chain_off[v]),
-                                  (uint32_t)np.chains[v].size(), b->d_ks[np.target], 0, v, pf.s));
+                                  (uint32_t)np.chains[v].size(), b->d_ks[np.target], 0, v, ps));
   if (ta) {
     hipEvent_t tb = pooled(b);
     if (tb) {
-      CV_HIP(hipEventRecord(tb, pf.s));
+      CV_HIP(hipEventRecord(tb, ps));
       b->spans.push_back({ta, tb, 0, np.steps});
     } else {
       b->event_pool.push_back(ta);
     }
   }
-  CV_HIP(hipEventRecord(pf.done[np.shadow], pf.s));
+  CV_HIP(hipEventRecord(pf.done[np.shadow], ps));
   pf.used[np.shadow] = true;
   pf.entries = std::move(np.entries);
   pf.target = np.target;
@@ -979,7 +985,7 @@ cv_status run_tick(cv_batch* b, const cv_batch_item* items, size_t n_items, hipS
   const bool hooked = hit || ahead;
   if ((s = batch_enqueue(b, cj, fj, b->d_ks[buf], st, hooked ? &hooks : nullptr)) != CV_OK) return s;
   for (size_t i : eligible) items[i].key->frame_index += items[i].n_frames;
-  return ahead ? launch_prefetch(b, np) : CV_OK;
+  return ahead ? launch_prefetch(b, np, st) : CV_OK;
 }
 
 }  // namespace
@@ -1047,7 +1053,7 @@ void release(cv_batch* b) {
     if (p) (void)hipFree(p);
   for (hipEvent_t e : {pf.ks_ready, pf.done[0], pf.done[1], pf.copied})
     if (e) (void)hipEventDestroy(e);
-  if (pf.s) (void)hipStreamDestroy(pf.s);
+  side_streams_free(pf.side);
   if (b->d_scratch) (void)hipFree(b->d_scratch);
   if (b->d_counters) (void)hipFree(b->d_counters);
   if (b->d_err) (void)hipFree(b->d_err);

@@ -10,6 +10,21 @@
 
 using cv::Geom;
 
+// Private streams for work that runs beside a caller's stream st (a key's
+// lookahead, a batch's prefetch), chosen per call.  Beside the legacy null
+// stream: a non-blocking stream, so that null-stream work does not wait for
+// the private work.  Beside any other stream: a stream with a compute-unit
+// mask of every CU, which gets a hardware queue of its own (a plain stream
+// may share st's queue, and st's later work would then wait behind the
+// private work); such a stream is ordered with the null stream, which st is
+// not.  Consecutive private launches are ordered by the callers' events, not
+// by the stream.
+struct SideStreams {
+  hipStream_t plain = nullptr;  // non-blocking
+  hipStream_t own = nullptr;    // masked (or plain where masks are not supported)
+  hipStream_t last = nullptr;   // the stream of the last private work
+};
+
 // One video stream's key: device-resident generator state plus the
 // workspace its calls reuse.
 struct cv_key {
@@ -96,7 +111,8 @@ struct cv_key {
   // predicted frame with the same T and the state was not set in between
   bool lookahead = false;
   struct Ahead {
-    hipStream_t s = nullptr;           // private stream (default priority)
+    bool ready = false;                // events, shadow copies and chain tables set up
+    SideStreams side;                  // private streams (default priority)
     hipEvent_t ks_ready = nullptr;     // call's stream: keystream ready, shadow states copied
     hipEvent_t done[2] = {};           // per shadow copy: the last lookahead using it is complete
     bool used[2] = {};
@@ -186,6 +202,9 @@ bool pw_eligible(const cv_key* k, const uint8_t* in, const uint8_t* out, uint32_
 // Key-path helpers (plain or fused rounds of one key, its workspace).
 cv_status ensure_workspace(cv_key* k, size_t frames);
 cv_status upload_shift_tables(cv_key* k, const uint32_t* s_c, size_t T, hipStream_t st);
+// The private stream for work beside st (see SideStreams); release them.
+cv_status side_stream(SideStreams& ss, int device, hipStream_t st, hipStream_t* out);
+void side_streams_free(SideStreams& ss);
 // Order a call of the key on st after its last call on another stream; after
 // the call, note st and record the key's event there.
 cv_status key_order_wait(const cv_key* k, hipStream_t st);
