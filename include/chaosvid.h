@@ -158,8 +158,10 @@ typedef struct {
                               key's state.  Beside a call stream other than the null stream
                               it is a stream with a hardware queue of its own (a compute-unit
                               mask of every CU), so the call stream's later work never queues
-                              behind a lookahead; beside the null stream it is a non-blocking
-                              stream.  Costs two keystream buffers of T frames.  0: off */
+                              behind a lookahead (such a stream is ordered with the legacy
+                              null stream: null-stream work issued meanwhile waits for the
+                              lookahead); beside the null stream it is a non-blocking stream.
+                              Costs two keystream buffers of T frames.  0: off */
 } cv_launch;
 
 /* Version of the cipher readings above (CV_SPEC_VERSION). */
