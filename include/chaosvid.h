@@ -441,7 +441,10 @@ typedef struct {
                            count predicted, copying the advanced states into the keys on its
                            stream; otherwise it generates its own keystream and the
                            prefetched work is dropped.  The private stream never touches a
-                           key.  Ticks then go kernel by kernel, without graphs.  0: off */
+                           key; it is chosen as for cv_launch.lookahead (its own hardware
+                           queue beside a stream other than the null stream, non-blocking
+                           beside the null stream).  Ticks then go kernel by kernel,
+                           without graphs.  0: off */
 } cv_batch_shape;
 
 /* Counters of a batch object (host-side, no synchronisation). */
