@@ -507,7 +507,7 @@ def bench_served(B, torch, np, args):
             for d in (False, True)]
     late = [i for i in late if i is not None]
     late_out = {i: torch.empty(480 * 480 * 3, dtype=torch.uint8, device=dev) for i in late}
-    cap_factors = [f for f in (1.25, 1.5, 1.75, 2.0, 2.5, 3.0, 4.0) if args.serve_capacity_seconds > 0]
+    cap_factors = [f for f in (1.25, 1.5, 1.75, 2.0, 2.25, 2.5, 3.0, 4.0) if args.serve_capacity_seconds > 0]
     per_stream_max = RATE * secs * 3 + sum(RATE * f * args.serve_capacity_seconds * 3 for f in cap_factors)
     seeds = [confusion_seeds(int(per_stream_max) + 64, 9700 + i) for i in range(N)]
     torch.cuda.synchronize()
@@ -947,7 +947,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-capacity-seconds", type=float, default=3.0,
                     help="seconds per run of the served capacity sweep (0 = skip)")
-    ap.add_argument("--serve-ring", type=int, default=8,
+    ap.add_argument("--serve-ring", type=int, default=16,
                     help="keystream frames generated ahead per served stream")
     ap.add_argument("--serve-split", type=int, default=1, choices=[1, 2, 3],
                     help="quarters of every XCD's compute units for served keystream generation")
