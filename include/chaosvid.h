@@ -547,7 +547,10 @@ cv_status cv_server_create(int device, size_t hbm_budget, cv_server **out);
 
 /* Ring depth (keystream frames generated ahead, >= 1) and queue depth
  * (frames a stream may have submitted and not finished, >= 1) for streams
- * opened after the call.  split_cus = q in 1..3 runs keystream generation
+ * opened after the call.  A deeper ring lets a stream's generator run
+ * further ahead while arrivals are few, which absorbs bursts of arrivals
+ * near the generator's serial rate (ring_frames * r*H*W*C bytes of device
+ * memory per stream).  split_cus = q in 1..3 runs keystream generation
  * on q quarters of the compute units of every XCD and the rounds on the
  * rest (1, a quarter, is the default); 0 lets both use every CU.
  * CV_E_INVAL if a depth is 0 or above 64 or split_cus is outside 0..3;
