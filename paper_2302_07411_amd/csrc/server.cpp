@@ -212,6 +212,14 @@ struct cv_server {
   std::vector<cv_stream*> streams;
   std::vector<std::pair<cv_stream*, uint32_t>> ks_launch;  // in flight
   bool ks_busy = false;
+  // 2DLASM streams' keystream: one launch over all their chains, from a
+  // chain table staged in pinned memory, with the launch's own word for a
+  // sine that could not be rounded
+  cv::LasmChain* d_lasm = nullptr;
+  cv::LasmChain* h_lasm = nullptr;
+  size_t lasm_cap = 0;  // chains
+  uint32_t* d_lasm_err = nullptr;
+  uint32_t* h_lasm_err = nullptr;
   Clock::time_point ks_launch_t;
   std::deque<Tick> ticks;
   cv_server_stats stats{};
@@ -268,6 +276,56 @@ void plan_keystream(cv_server* S, std::vector<ChainJob>& cj, std::vector<LasmJob
     st->ks_issued += k;
     st->in_ks_launch = true;
   }
+}
+
+// One keystream launch over the chains of every 2DLASM stream in `lj` on
+// the keystream stream (mutex not held; the previous keystream launch, which
+// read the same tables, is complete).  Chains are sorted by length so that
+// the chains of a workgroup end together.
+cv_status launch_lasm_keystream(cv_server* S, const std::vector<LasmJob>& lj) {
+  std::vector<cv::LasmChain> ch;
+  for (const LasmJob& l : lj)
+    for (const cv::LasmChain& c : l.k->h_lchains) {
+      cv::LasmChain x = c;
+      x.out_off = l.ks_off + c.out_off;  // absolute: the launch gets a null base
+      x.frames = l.frames;
+      ch.push_back(x);
+    }
+  std::stable_sort(ch.begin(), ch.end(), [](const cv::LasmChain& a, const cv::LasmChain& b) {
+    return a.nbytes * a.frames > b.nbytes * b.frames;
+  });
+  if (!S->d_lasm_err) {
+    if (hipMalloc(&S->d_lasm_err, sizeof(uint32_t)) != hipSuccess ||
+        hipHostMalloc(&S->h_lasm_err, sizeof(uint32_t)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(CV_E_NOMEM, "2DLASM error word allocation failed");
+    }
+    *S->h_lasm_err = 0;
+    CV_HIP(hipMemcpyAsync(S->d_lasm_err, S->h_lasm_err, sizeof(uint32_t), hipMemcpyHostToDevice,
+                          S->s_ks));
+  }
+  if (ch.size() > S->lasm_cap) {
+    if (S->d_lasm) (void)hipFree(S->d_lasm);
+    if (S->h_lasm) (void)hipHostFree(S->h_lasm);
+    S->d_lasm = nullptr;
+    S->h_lasm = nullptr;
+    S->lasm_cap = 0;
+    const size_t cap = ch.size() + ch.size() / 2;
+    if (hipMalloc(&S->d_lasm, cap * sizeof(cv::LasmChain)) != hipSuccess ||
+        hipHostMalloc(&S->h_lasm, cap * sizeof(cv::LasmChain)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(CV_E_NOMEM, "2DLASM chain table allocation failed");
+    }
+    S->lasm_cap = cap;
+  }
+  memcpy(S->h_lasm, ch.data(), ch.size() * sizeof(cv::LasmChain));
+  CV_HIP(hipMemcpyAsync(S->d_lasm, S->h_lasm, ch.size() * sizeof(cv::LasmChain),
+                        hipMemcpyHostToDevice, S->s_ks));
+  CV_HIP(cv::launch_prbg_lasm(S->d_lasm, (uint32_t)ch.size(), nullptr, 0, 0, S->d_lasm_err,
+                              S->s_ks));
+  CV_HIP(hipMemcpyAsync(S->h_lasm_err, S->d_lasm_err, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                        S->s_ks));
+  return CV_OK;
 }
 
 // Queued frames with keystream ready, from every stream (mutex held).
@@ -387,9 +445,9 @@ void worker_main(cv_server* S) {
       for (auto& [st, k] : S->ks_launch) {
         st->ks_ready += k;
         st->in_ks_launch = false;
-        if (st->key->map != CV_MAP_PLCM && *st->key->h_err)
-          set_error(S, CV_E_HIP, "a 2DLASM sine could not be rounded with certainty");
       }
+      if (S->h_lasm_err && *S->h_lasm_err)
+        set_error(S, CV_E_HIP, "a 2DLASM sine could not be rounded with certainty");
       S->ks_launch.clear();
       S->ks_busy = false;
       S->stats.keystream_ms +=
@@ -463,14 +521,7 @@ void worker_main(cv_server* S) {
         S->ks_launch_t = Clock::now();
         lk.unlock();
         cv_status s = cj.empty() ? CV_OK : batch_enqueue(S->kb, cj, {}, nullptr, S->s_ks);
-        for (const LasmJob& l : lj) {
-          if (s != CV_OK) break;
-          if (cv::launch_prbg_lasm(l.k->d_lchains, l.k->g.n, (uint8_t*)(uintptr_t)l.ks_off, l.frames, 0,
-                                   l.k->d_err, S->s_ks) != hipSuccess ||
-              hipMemcpyAsync(l.k->h_err, l.k->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost,
-                             S->s_ks) != hipSuccess)
-            s = fail(CV_E_HIP, "2DLASM keystream launch failed");
-        }
+        if (s == CV_OK && !lj.empty()) s = launch_lasm_keystream(S, lj);
         std::string msg = s != CV_OK ? cv_last_error() : "";
         hipError_t e = hipEventRecord(S->ks_ev, S->s_ks);
         lk.lock();
@@ -528,7 +579,10 @@ void destroy(cv_server* S) {
   cv_batch_free(S->kb);
   if (S->s_rounds) (void)hipStreamDestroy(S->s_rounds);
   if (S->s_ks) (void)hipStreamDestroy(S->s_ks);
-
+  if (S->d_lasm) (void)hipFree(S->d_lasm);
+  if (S->h_lasm) (void)hipHostFree(S->h_lasm);
+  if (S->d_lasm_err) (void)hipFree(S->d_lasm_err);
+  if (S->h_lasm_err) (void)hipHostFree(S->h_lasm_err);
   delete S;
 }
 

@@ -169,3 +169,33 @@ def test_lasm_key_errors(B):
     pm = good.copy()
     pm[0, 2] = 1.0  # mu = 1 is admissible
     B.Key(H, W, C, n, r, pm, map=B.CV_MAP_2DLASM)
+
+
+def test_several_lasm_streams_in_the_server(B):
+    """2DLASM streams of different sizes beside a PLCM stream in the server:
+    one keystream launch holds the chains of every 2DLASM stream (of unequal
+    lengths); each stream's frames equal the oracle's."""
+    r = 5
+    specs = [(48, 64, 3, 4, True), (32, 48, 3, 2, True), (64, 64, 4, 8, True), (48, 48, 3, 4, False)]
+    T = 3
+    srv = B.Server(hbm_budget=256 << 20, ring_frames=2, queue_frames=T)
+    cases = []
+    for i, (H, W, C, n, lasm) in enumerate(specs):
+        pm = lasm_key(n, 8100 + i) if lasm else plcm_key(n, 8100 + i)
+        frames = uniform_frames(H, W, C, T, 8200 + i)
+        s_c = confusion_seeds(T, 8300 + i)
+        ref = oracle.LasmKey(H, W, C, n, r, pm) if lasm else oracle.PlcmKey(H, W, C, n, r, pm)
+        st = srv.open(H, W, C, n, r, pm, map=B.CV_MAP_2DLASM if lasm else B.CV_MAP_PLCM)
+        src = [_dev(frames[t]) for t in range(T)]
+        out = [torch.empty_like(x) for x in src]
+        cases.append((st, src, out, s_c, ref.encrypt(frames, s_c)))
+    print("[case] several 2DLASM streams in the server", flush=True)
+    for t in range(T):
+        for st, src, out, s_c, _ in cases:
+            st.submit(src[t], out[t], int(s_c[t]))
+    srv.drain()
+    for i, (st, src, out, s_c, want) in enumerate(cases):
+        for t in range(T):
+            got = _host(out[t], want[t].shape)
+            assert np.array_equal(got, want[t]), f"stream {i} frame {t}"
+    srv.close()
