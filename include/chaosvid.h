@@ -486,7 +486,11 @@ cv_status cv_batch_set_shape(cv_batch *batch, const cv_batch_shape *shape);
  * another device, an s_c of 0, overlapping buffers), CV_E_NOMEM, CV_E_HIP
  * (including a group barrier timeout of an earlier tick, which leaves that
  * tick's output invalid and every later call on this batch failing).
- * Calls on one batch are ordered with each other even across streams. */
+ * Calls on one batch are ordered with each other even across streams.
+ * Items the batched kernels do not take -- 2DLASM keys, geometries outside
+ * C in {3,4} with W a multiple of 16, unaligned buffers -- run on their
+ * key's own path, one after another on `stream`
+ * (cv_batch_info.last_fallback_items). */
 cv_status cv_batch_run(cv_batch *batch, const cv_batch_item *items, size_t n_items,
                        void *stream);
 
